@@ -1,0 +1,441 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix (no GPU).
+
+Each test checks the oracle against something other than itself: an independent
+Philox implementation, exact high-precision thresholds, the first-fit
+characterisation of the colouring, brute-force energies (eq. 4-6 and the dense
+Ising form, eq. 3), a per-phase audit of the annealer from definitions,
+closed-form balanced min-cuts, and special cases of the schedule.
+"""
+import json
+import math
+import os
+import random
+import shutil
+import subprocess
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+
+import gdi_synth as gs
+from oracle import exhaustive, ref_tiny
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def edge_list(g):
+    src = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    keep = src < g.col
+    return src[keep], g.col[keep].astype(np.int64), g.w[keep].astype(np.int64)
+
+
+def cut_from_scratch(g, s):
+    a, b, w = edge_list(g)
+    s = np.asarray(s, dtype=np.int64)
+    return int((w * (s[a] != s[b])).sum())
+
+
+def closed_form_graph(case):
+    n, kind = case["n"], case["kind"]
+    if kind == "cycle":
+        a = np.arange(n); b = (a + 1) % n
+    elif kind == "path":
+        a = np.arange(n - 1); b = a + 1
+    elif kind == "complete":
+        a, b = np.triu_indices(n, 1)
+    elif kind == "star":
+        a = np.zeros(n - 1, dtype=np.int64); b = np.arange(1, n)
+    elif kind == "torus":
+        return gs.torus_graph(case["L"], 0, "unit")
+    elif kind == "two_cliques":
+        h = n // 2
+        a1, b1 = np.triu_indices(h, 1)
+        a = np.concatenate([a1, a1 + h, [0]]); b = np.concatenate([b1, b1 + h, [h]])
+    elif kind == "complete_bipartite":
+        h = n // 2
+        a = np.repeat(np.arange(h), h); b = np.tile(np.arange(h, n), h)
+    else:
+        raise ValueError(kind)
+    return gs.from_edges(n, a, b, np.ones(len(a), dtype=np.int64))
+
+
+# ---------------------------------------------------------------- Philox (P10)
+
+def _aten_probe(tmp_path_factory):
+    inc = None
+    try:
+        import torch
+
+        inc = os.path.join(os.path.dirname(torch.__file__), "include")
+    except Exception:
+        pass
+    if not inc or not os.path.exists(os.path.join(inc, "ATen", "core", "PhiloxRNGEngine.h")):
+        pytest.skip("PyTorch headers not available")
+    if shutil.which("g++") is None:
+        pytest.skip("g++ not available")
+    exe = str(tmp_path_factory.mktemp("aten") / "probe")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-I", inc, "-o", exe,
+                    os.path.join(HERE, "aten_philox_probe.cpp")], check=True)
+    return exe
+
+
+def test_philox_matches_independent_implementation(oracle_lib, tmp_path_factory):
+    """Oracle Philox4x32-10 == PyTorch's header-only Philox engine and the pure-Python one."""
+    exe = _aten_probe(tmp_path_factory)
+    rng = np.random.default_rng(5)
+    rows = [(0, 0, 0, 0, 0), (2**64 - 1, 2**32 - 1, 2**32 - 1, 2**32 - 1, 2**32 - 1),
+            (1, 0, 0, 0, 1), (12345678901, 7, 3, 0, 0)]
+    for _ in range(300):
+        rows.append((int(rng.integers(0, 2**63)) * 2 + int(rng.integers(0, 2)),
+                     *[int(v) for v in rng.integers(0, 2**32, size=4, dtype=np.uint64)]))
+    # counters the annealer uses: (node, sweep, replica, stream)
+    for node in (0, 1, 999_999):
+        for t in (0, 1, 1999):
+            rows.append((1, node, t, 0, 0))
+            rows.append((1, node, 0, 255, 1))
+    inp = "\n".join(" ".join(str(v) for v in r) for r in rows) + "\n"
+    out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout.split()
+    ref = np.array(out, dtype=np.uint64).reshape(-1, 4).astype(np.uint32)
+    for r, exp in zip(rows, ref):
+        got = oracle_lib.philox(r[0], [r[1:]])[0]
+        assert np.array_equal(got, exp), r
+        assert tuple(int(v) for v in exp) == ref_tiny.philox4x32_10(r[0], r[1:]), r
+
+
+def test_philox_uniform_words(oracle_lib):
+    """Words x0 and x1 of consecutive node counters are uniform and uncorrelated (chi-square)."""
+    m = 200_000
+    ctr = np.zeros((m, 4), dtype=np.uint32)
+    ctr[:, 0] = np.arange(m)
+    ctr[:, 1] = 17
+    x = oracle_lib.philox(99, ctr)
+    for w in (0, 1):
+        counts = np.bincount(x[:, w] >> 24, minlength=256)
+        chi2 = ((counts - m / 256) ** 2 / (m / 256)).sum()
+        assert chi2 < 350, chi2  # 255 dof: p ~ 1e-4 at 350
+    joint = np.bincount((x[:, 0] >> 28) * 16 + (x[:, 1] >> 28), minlength=256)
+    chi2 = ((joint - m / 256) ** 2 / (m / 256)).sum()
+    assert chi2 < 350, chi2
+    bits = ((x[:, 0][:, None] >> np.arange(32, dtype=np.uint32)) & 1).mean(axis=0)
+    assert np.all(np.abs(bits - 0.5) < 0.006)
+
+
+# ---------------------------------------------------------------- thresholds (P11)
+
+def exact_threshold(d, T):
+    getcontext().prec = 60
+    v = (Decimal(-d) / Decimal(T)).exp() * Decimal(2) ** 32
+    return min(int(v), 2**32 - 1), v
+
+
+def test_thresholds_match_exact_arithmetic(oracle_lib):
+    """floor(2^32 exp(-d/T)) in FP64/libm equals the exact value (60-digit decimal)."""
+    temps = gs.geometric_temps(3.0, 0.05, 40).tolist() + [1.0, 0.5, 7.25, 100.0]
+    width = 80
+    tab = oracle_lib.thresholds(np.array(temps), width)
+    near = 0
+    for t, T in enumerate(temps):
+        for d in range(1, width + 1):
+            exp_val, raw = exact_threshold(d, T)
+            frac = raw - int(raw)
+            if min(frac, 1 - frac) < Decimal("1e-6") and raw > 1:
+                near += 1  # within FP64 reach of an integer: either rounding is acceptable
+                assert abs(int(tab[t, d]) - exp_val) <= 1
+                continue
+            assert int(tab[t, d]) == exp_val, (T, d)
+    assert near < 5
+
+
+def test_threshold_shape(oracle_lib):
+    """Monotone in d, last non-zero entry at floor(32 ln2 T), saturates at 2^32-1 for huge T."""
+    for T in (0.05, 0.3, 2.0, 3.0, 10.0):
+        tab = oracle_lib.thresholds(np.array([T]), 800)[0, 1:]
+        assert np.all(np.diff(tab.astype(np.int64)) <= 0)
+        last = np.nonzero(tab)[0].max() + 1 if tab.any() else 0
+        assert last == math.floor(32 * math.log(2) * T), (T, last)
+    assert oracle_lib.threshold(5, 1e300) == 2**32 - 1
+    assert oracle_lib.threshold(1, 1e-3) == 0
+
+
+# ---------------------------------------------------------------- colouring (P5)
+
+@pytest.mark.parametrize("gen", ["er", "rgg", "torus", "torus_odd"])
+def test_colouring_is_first_fit(oracle_lib, gen):
+    """Proper colouring, and each node's colour is the least one missing among lower neighbours."""
+    g = {"er": lambda: gs.er_graph(400, 0.05, 3), "rgg": lambda: gs.rgg_graph(3000, 9.0, 4),
+         "torus": lambda: gs.torus_graph(20, 1), "torus_odd": lambda: gs.torus_graph(7, 1)}[gen]()
+    col, C = oracle_lib.colour(g)
+    assert C == col.max() + 1
+    for i in range(g.n):
+        nb = g.col[g.row_ptr[i]:g.row_ptr[i + 1]]
+        assert not np.any(col[nb] == col[i])
+        lower = set(col[nb[nb < i]].tolist())
+        assert all(c in lower for c in range(col[i]))
+        assert col[i] not in lower
+    col2, _ = oracle_lib.colour(g)
+    assert np.array_equal(col, col2)
+    if gen == "torus":
+        assert C == 2  # even torus in row-major order is bipartite and first-fit finds it
+    if gen == "torus_odd":
+        assert C >= 3  # an odd torus contains odd cycles, so it is not bipartite
+
+
+# ---------------------------------------------------------------- energy (P1, P2)
+
+def random_small_graph(rng, n, p, weights):
+    while True:
+        g = gs.er_graph(n, p, int(rng.integers(0, 2**31)), weights)
+        if g.nnz > 0:
+            return g
+
+
+def test_flip_delta_equals_energy_difference(oracle_lib):
+    """dE_i = B s_i h_i + 4A(1 - s_i M) equals E(s with i flipped) - E(s), eq. 4-6, exhaustively."""
+    rng = np.random.default_rng(11)
+    for trial in range(6):
+        n = int(rng.integers(5, 11))
+        g = random_small_graph(rng, n, 0.5, "pm1" if trial % 2 else "unit")
+        A, B = int(rng.integers(0, 4)), int(rng.integers(0, 4))
+        S, M, cut, E = exhaustive.all_energies(g, A, B)
+        idx = {tuple(r): k for k, r in enumerate(S.tolist())}
+        for k in rng.integers(0, len(S), size=40):
+            s = S[k].astype(np.int8)
+            for i in range(n):
+                t = s.copy(); t[i] = -t[i]
+                assert oracle_lib.flip_delta(g, s, A, B, i) == E[idx[tuple(t.tolist())]] - E[k]
+                assert oracle_lib.energy(g, s, A, B) == E[k]
+
+
+def test_energy_equals_dense_ising_form(oracle_lib):
+    """A M^2 + B cut_w == A n + B W/2 + sum_{i<j} (2A - B w_ij/2) s_i s_j for all 2^n states (eq. 3)."""
+    rng = np.random.default_rng(12)
+    for _ in range(4):
+        n = int(rng.integers(4, 11))
+        g = random_small_graph(rng, n, 0.6, "pm1")
+        A, B = 2, 3
+        Wm = np.zeros((n, n))
+        a, b, w = edge_list(g)
+        Wm[a, b] = w; Wm[b, a] = w
+        J = 2 * A - B * Wm / 2.0
+        np.fill_diagonal(J, 0.0)
+        S, M, cut, E = exhaustive.all_energies(g, A, B)
+        Sf = S.astype(np.float64)
+        dense = A * n + B * w.sum() / 2.0 + 0.5 * np.einsum("ki,ij,kj->k", Sf, J, Sf)
+        assert np.array_equal(dense, E.astype(np.float64))
+        for k in rng.integers(0, len(S), size=30):
+            assert oracle_lib.energy(g, S[k].astype(np.int8), A, B) == E[k]
+
+
+# ---------------------------------------------------------------- closed forms / eq. 7 (P3)
+
+def test_closed_form_min_cuts(oracle_lib):
+    with open(os.path.join(HERE, "golden", "closed_forms.json")) as f:
+        cases = json.load(f)["cases"]
+    for case in cases:
+        g = closed_form_graph(case)
+        best, _ = exhaustive.balanced_min_cut(g)
+        assert best == case["min_cut"], case["name"]
+
+
+def test_eq7_coefficients_make_ground_state_balanced(oracle_lib):
+    """With A/B >= min(2*Delta, n)/8 (eq. 7) the minimum of E is the balanced min-cut."""
+    rng = np.random.default_rng(13)
+    for _ in range(5):
+        n = int(rng.integers(8, 15)) // 2 * 2
+        g = random_small_graph(rng, n, 0.4, "unit")
+        B = 1
+        A = math.ceil(min(2 * int(g.degrees().max()), n) / 8)
+        _, M, cut, E = exhaustive.all_energies(g, A, B)
+        best, _ = exhaustive.balanced_min_cut(g)
+        assert E.min() == B * best
+        assert np.all(np.abs(M[E == E.min()]) <= 2)
+
+
+def test_annealer_reaches_balanced_min_cut(oracle_lib):
+    """Best of 10 runs (the paper's protocol, Sec. VI) reaches the exhaustive balanced min-cut.
+
+    Graphs have max degree <= 4, so A = B = 1 satisfies eq. 7 and the minimum of E is the
+    balanced min-cut. A single run is often trapped (a swap costs 4A first), so only the
+    best of the ten is pinned; the mean must beat random balanced partitions by far.
+    """
+    T = gs.geometric_temps(3.0, 0.05, 400)
+    rng = np.random.default_rng(0)
+    for gseed in (2076, 2155, 2173, 2266):
+        g = gs.rgg_graph(18, 3.2, gseed, "unit")
+        assert g.degrees().max() <= 4
+        best, _ = exhaustive.balanced_min_cut(g)
+        _, _, _, E = exhaustive.all_energies(g, 1, 1)
+        assert E.min() == best
+        runs = [oracle_lib.anneal(g, T, seed, A=1, B=1) for seed in range(10)]
+        assert all(r["M"] == 0 for r in runs)
+        assert min(r["cut"] for r in runs) == best
+        rand = []
+        for _ in range(200):
+            s = np.ones(g.n, dtype=np.int8)
+            s[rng.permutation(g.n)[: g.n // 2]] = -1
+            rand.append(cut_from_scratch(g, s))
+        assert np.mean([r["cut"] for r in runs]) < 0.6 * np.mean(rand)
+
+
+def test_torus_close_to_bisection_width(oracle_lib):
+    """Unit L x L torus (L even): bisection width 2L. Quality sanity, not parity.
+
+    Balance is conserved once reached, so domain walls move only by swaps and coarsen
+    slowly: the annealer ends balanced within a few times 2L, far below the ~L^2 edges
+    a random balanced partition cuts.
+    """
+    L = 16
+    g = gs.torus_graph(L, 0, "unit")
+    runs = [oracle_lib.anneal(g, gs.geometric_temps(3.0, 0.05, 1500), seed) for seed in range(3)]
+    assert all(r["M"] == 0 for r in runs)
+    assert all(r["cut"] >= 2 * L for r in runs)
+    assert min(r["cut"] for r in runs) <= 3 * 2 * L
+
+
+# ---------------------------------------------------------------- the schedule itself (P6, P7)
+
+def decide_from_definitions(g, prev, i, c_members, t, T, seed, replica, A, B, gated_mode):
+    """One node's decision recomputed from eq. 5/6 energies, the gate and exact thresholds."""
+    M0 = int(prev.sum())
+    s = (M0 > 0) - (M0 < 0)
+    D = abs(M0) // 2
+    O = int(np.sum(prev[c_members] == s)) if s != 0 else 0
+    x = ref_tiny.philox4x32_10(seed, (i, t, replica, 0))
+    if gated_mode:
+        gated = prev[i] == s and x[1] * O < (D << 32)
+        m_seen = M0 if gated else 0
+    else:
+        m_seen = M0
+    flipped = prev.copy(); flipped[i] = -flipped[i]
+    d_cut = cut_from_scratch(g, flipped) - cut_from_scratch(g, prev)
+    d_bal = (m_seen - 2 * int(prev[i])) ** 2 - m_seen ** 2
+    dE = B * d_cut + A * d_bal
+    if dE <= 0:
+        return True
+    thr, _ = exact_threshold(dE, T)
+    return x[0] < thr
+
+
+@pytest.mark.parametrize("gated_mode", [True, False])
+def test_phase_audit_from_definitions(oracle_lib, gated_mode):
+    """Every phase of the oracle's trajectory, re-derived node by node from definitions."""
+    cases = [(gs.er_graph(40, 0.15, 31, "pm1"), 2, 1), (gs.rgg_graph(60, 6.0, 32, "unit"), 1, 1),
+             (gs.er_graph(37, 0.2, 33, "unit"), 1, 2)]
+    for g, A, B in cases:
+        T = gs.geometric_temps(2.5, 0.3, 8)
+        seed, replica = 77, 3
+        r = oracle_lib.anneal(g, T, seed, A=A, B=B, replica=replica,
+                              mode=0 if gated_mode else 1, phase_trace=True, phase_spins=True)
+        col, C = oracle_lib.colour(g)
+        prev = np.array([1 if ref_tiny.philox4x32_10(seed, (i, 0, replica, 1))[0] & 1 else -1
+                         for i in range(g.n)], dtype=np.int64)
+        for t in range(T.size):
+            for c in range(C):
+                nxt = r["phase_spins"][t, c].astype(np.int64)
+                members = np.nonzero(col == c)[0]
+                assert np.array_equal(nxt[col != c], prev[col != c])
+                for i in members:
+                    flip = decide_from_definitions(g, prev, i, members, t, T[t], seed, replica, A, B,
+                                                   gated_mode)
+                    assert nxt[i] == (-prev[i] if flip else prev[i]), (t, c, i)
+                assert r["phase_m"][t, c] == nxt.sum()
+                assert r["phase_cut"][t, c] == cut_from_scratch(g, nxt)
+                prev = nxt
+        assert np.array_equal(prev, r["spins"])
+
+
+@pytest.mark.parametrize("gated", [True, False])
+def test_pure_python_reference_agrees(oracle_lib, gated):
+    """An independent pure-Python implementation gives the same trajectory, in any visiting order."""
+    for k, (g, S) in enumerate([(gs.er_graph(70, 0.08, 41, "pm1"), 25),
+                                (gs.rgg_graph(120, 7.0, 42, "unit"), 20),
+                                (gs.torus_graph(6, 43, "pm1"), 30)]):
+        T = gs.geometric_temps(2.0, 0.05, S)
+        a, b, w = edge_list(g)
+        edges = list(zip(a.tolist(), b.tolist(), w.tolist()))
+        r = oracle_lib.anneal(g, T, 1000 + k, mode=0 if gated else 1, replica=k)
+        s, M, cut = ref_tiny.anneal(g.n, edges, list(T), 1000 + k, replica=k, gated=gated,
+                                    visit_seed=k + 5)
+        assert np.array_equal(r["spins"], np.array(s, dtype=np.int8))
+        assert (r["M"], r["cut"]) == (M, cut)
+
+
+# ---------------------------------------------------------------- determinism and resume (P8, P9)
+
+def test_thread_count_invariance(oracle_lib):
+    g = gs.rgg_graph(20000, 8.0, 51)
+    T = gs.geometric_temps(3.0, 0.05, 30)
+    r1 = oracle_lib.anneal(g, T, 5, n_threads=1, trace=True)
+    r8 = oracle_lib.anneal(g, T, 5, n_threads=8, trace=True)
+    assert np.array_equal(r1["spins"], r8["spins"])
+    assert np.array_equal(r1["trace_cut"], r8["trace_cut"])
+
+
+def test_resume_equals_uninterrupted(oracle_lib):
+    g = gs.er_graph(500, 0.02, 52, "pm1")
+    T = gs.geometric_temps(2.0, 0.05, 60)
+    full = oracle_lib.anneal(g, T, 9, trace=True)
+    head = oracle_lib.anneal(g, T[:25], 9)
+    tail = oracle_lib.anneal(g, T, 9, start_sweep=25, init=head["spins"], trace=True)
+    assert np.array_equal(full["spins"], tail["spins"])
+    assert (full["M"], full["cut"]) == (tail["M"], tail["cut"])
+    assert np.array_equal(full["trace_m"][25:], tail["trace_m"][25:])
+
+
+def test_tracked_state_matches_recompute(oracle_lib):
+    """Incrementally tracked M and cut == from-scratch values after every phase."""
+    g = gs.rgg_graph(2000, 8.0, 53, "pm1")
+    T = gs.geometric_temps(3.0, 0.05, 12)
+    r = oracle_lib.anneal(g, T, 4, phase_trace=True, phase_spins=True)
+    for t in range(T.size):
+        for c in range(r["C"]):
+            s = r["phase_spins"][t, c]
+            assert r["phase_m"][t, c] == int(s.astype(np.int64).sum())
+            assert r["phase_cut"][t, c] == cut_from_scratch(g, s)
+
+
+# ---------------------------------------------------------------- special cases (P12)
+
+def test_infinite_temperature_alternates(oracle_lib):
+    """T -> inf: every threshold is 2^32-1, so each spin flips every sweep (unless x0 = 2^32-1)."""
+    g = gs.er_graph(90, 0.1, 61, "pm1")
+    S = 7
+    T = np.full(S, 1e300)
+    for t in range(S):
+        for i in range(g.n):
+            assert ref_tiny.philox4x32_10(3, (i, t, 0, 0))[0] != 2**32 - 1
+    r0 = oracle_lib.anneal(g, T[:1], 3, start_sweep=1)  # zero sweeps: the initial state
+    r = oracle_lib.anneal(g, T, 3, trace=True)
+    assert np.array_equal(r["spins"], (-1) ** S * r0["spins"])
+    assert np.all(r["trace_m"] == r0["M"] * (-1) ** np.arange(1, S + 1))
+
+
+def test_no_balance_term_collapses_to_one_side(oracle_lib):
+    """A = 0, unit weights, cold: the cut term alone drives a dense graph to one part (cut 0)."""
+    g = gs.er_graph(100, 0.5, 62, "unit")
+    r = oracle_lib.anneal(g, gs.geometric_temps(0.5, 0.05, 100), 8, A=0, B=1)
+    assert r["cut"] == 0 and abs(r["M"]) == g.n
+
+
+def test_no_cut_term_balances(oracle_lib):
+    """B = 0: the gated balance term alone brings M to 0 (n even)."""
+    g = gs.er_graph(1000, 0.01, 63, "unit")
+    r = oracle_lib.anneal(g, gs.geometric_temps(1.0, 0.05, 60), 8, A=1, B=0, trace=True)
+    assert r["M"] == 0
+
+
+def test_snapshot_balance_is_unstable_and_gated_is_not(oracle_lib):
+    """The literal per-phase snapshot drives the 2-class torus into a limit cycle; GATED balances it."""
+    g, _ = gs.workload("torus100")
+    T = gs.geometric_temps(3.0, 0.05, 300)
+    gated = oracle_lib.anneal(g, T, 1, mode=0, trace=True)
+    snap = oracle_lib.anneal(g, T, 1, mode=1, trace=True)
+    assert np.all(np.abs(gated["trace_m"][-50:]) == 0)
+    assert np.abs(snap["trace_m"][-50:]).max() > 1000
+
+
+def test_odd_n_stays_balanced(oracle_lib):
+    """Odd n: non-gated spins see a balanced M = 0, so |M| settles at 1."""
+    g = gs.rgg_graph(5001, 8.0, 64)
+    r = oracle_lib.anneal(g, gs.geometric_temps(3.0, 0.05, 300), 2, trace=True)
+    assert np.all(np.abs(r["trace_m"][-30:]) == 1)
