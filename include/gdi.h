@@ -1,0 +1,210 @@
+/*
+ * gdi.h -- C ABI of the MI355X (gfx950) Globally Decoupled Ising annealer for
+ * balanced 2-way min-cut partitioning.
+ *
+ * The method (paper: "GPU-based Ising Computing for Solving Balanced Min-Cut
+ * Graph Partitioning Problem", Sec. IV eq. 4-6 and Sec. V Alg. 3):
+ *
+ *   spins s_i in {-1,+1} encode the two parts (s_i = +1 -> V1, -1 -> V2,
+ *   Sec. IV-A); the energy is E = A*M^2 + B*cut_w with M = sum_i s_i (eq. 5,
+ *   the balance penalty) and cut_w = sum over edges of w_ij*[s_i != s_j]
+ *   (eq. 6, weighted). Instead of the dense all-to-all coupling of the balance
+ *   term, every spin reads a separately tracked global magnetisation M
+ *   (Alg. 3's global G), so a spin's flip cost is
+ *       dE_i = B*s_i*h_i + 4A*(1 - s_i*M_seen),   h_i = sum_j w_ij s_j,
+ *   and only its sparse neighbours are read.
+ *
+ * Deterministic execution (where the paper's asynchronous GPU update is
+ * unspecified, Sec. V-B/V-C):
+ *   - nodes are coloured by first-fit greedy colouring in ascending node id;
+ *     each sweep visits the colour classes in ascending colour, one phase per
+ *     class; all spins of a class decide against the same pre-phase state;
+ *   - M_seen: GDI_BAL_GATED (default): an over-side spin (s_i == sign(M0))
+ *     sees M0 iff x1 * O < floor(|M0|/2) * 2^32, where M0 is the magnetisation
+ *     at the start of the phase and O the number of over-side spins in the
+ *     class; every other spin sees 0. GDI_BAL_SNAPSHOT: every spin sees M0;
+ *   - Metropolis acceptance: flip iff dE <= 0 or x0 < thr_t(dE) with
+ *     thr_t(d) = min(2^32-1, floor(2^32*exp(-d/T_t))) built on the host in FP64;
+ *   - x0, x1 are words 0 and 1 of Philox4x32-10 (Salmon et al., SC'11) with
+ *     key (seed & 0xffffffff, seed >> 32) and counter (node, sweep, replica, 0);
+ *     the initial state uses counter (node, 0, replica, 1): s = +1 iff x0 odd.
+ * All arithmetic after the threshold table is integer, so results are
+ * bit-identical across launch shapes and runs.
+ *
+ * Conventions:
+ *   - Return codes: GDI_OK (0) or a negative GDI_E* code; gdi_last_error()
+ *     returns a thread-local message for the last non-zero return.
+ *   - Node ids are the caller's ids ("original order") in every input and
+ *     output; the library relabels internally.
+ *   - The caller owns every input array; gdi_create copies what it needs.
+ *     The handle owns its device memory until gdi_destroy.
+ *   - Host variants block until the result is on the host. The *_dev
+ *     variants take device pointers and are ordered on the stream set with
+ *     gdi_set_stream (default: the null stream); they return after enqueueing
+ *     (device errors are then reported by the next call on the handle).
+ *   - One handle must not be used from two threads at once.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef GDI_H
+#define GDI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ codes */
+#define GDI_OK 0
+#define GDI_EINVAL (-1)   /* malformed CSR, bad schedule, NULL argument */
+#define GDI_ERANGE (-2)   /* a weight sum or an energy change does not fit int32 */
+#define GDI_ENOMEM (-3)   /* host or device allocation failed */
+#define GDI_EDEVICE (-4)  /* HIP error, no gfx950 device, or launch does not fit */
+#define GDI_ESTATE (-5)   /* NULL handle or call out of order */
+#define GDI_ETIMEOUT (-6) /* a bounded device-side wait expired (no hang) */
+
+#define GDI_BAL_GATED 0u
+#define GDI_BAL_SNAPSHOT 1u
+
+/* Scope of the persistent sweep launch. */
+#define GDI_SCOPE_AUTO 0u
+#define GDI_SCOPE_WORKGROUP 1u /* whole instance inside one workgroup */
+#define GDI_SCOPE_GRID 2u      /* instance spread over the whole device */
+
+typedef struct gdi_graph gdi_graph;
+
+/* Annealing schedule (Alg. 3 outer loop, with Metropolis temperatures). */
+typedef struct {
+    uint32_t n_sweeps;        /* S >= 1: length of temps */
+    uint32_t start_sweep;     /* first sweep to run (resume); 0 = fresh start */
+    const double *temps;      /* host, S temperatures T_t > 0 (FP64); read during the call */
+    int32_t A;                /* balance coefficient (eq. 5) */
+    int32_t B;                /* cut coefficient (eq. 6) */
+    uint32_t replica;         /* Philox counter word 2 */
+    uint32_t balance_mode;    /* GDI_BAL_GATED or GDI_BAL_SNAPSHOT */
+    const int8_t *init_spins; /* host, n spins (original order) to start from, or NULL for the Philox state */
+    int64_t *trace_m;         /* host, S entries or NULL: M after each sweep t >= start_sweep */
+    int64_t *trace_cut;       /* host, S entries or NULL: weighted cut after each sweep t >= start_sweep */
+} gdi_schedule;
+
+/* Launch tuning; zero fields mean "choose automatically". */
+typedef struct {
+    uint32_t scope;           /* GDI_SCOPE_* */
+    uint32_t block;           /* threads per workgroup: 64..1024, multiple of 64 */
+    uint32_t grid;            /* workgroups for GDI_SCOPE_GRID (<= co-resident capacity) */
+    uint32_t lanes_per_node;  /* 1, 2, 4, 8, 16, 32 or 64 lanes share one CSR row */
+} gdi_tuning;
+
+/* Outcome of the last anneal on a handle. */
+typedef struct {
+    int64_t magnetization;    /* M = sum of spins = |V1| - |V2| */
+    int64_t cut_weighted;     /* tracked weighted cut */
+    double sweep_ms;          /* device time of the persistent sweep launch */
+    uint32_t n_colours;       /* number of colour classes (phases per sweep) */
+    uint32_t scope;           /* GDI_SCOPE_WORKGROUP or GDI_SCOPE_GRID */
+    uint32_t grid;            /* workgroups launched */
+    uint32_t block;           /* threads per workgroup */
+    uint32_t lanes_per_node;
+    uint32_t table_width;     /* largest dE with a non-zero threshold (K) */
+} gdi_result;
+
+/* Graph facts after gdi_create. */
+typedef struct {
+    int32_t n;
+    int32_t n_colours;
+    int64_t nnz;              /* directed CSR entries = 2|E| */
+    int64_t max_abs_wdeg;     /* max_i sum_j |w_ij| */
+    int32_t max_degree;
+    int32_t pad;
+} gdi_graph_info;
+
+/*
+ * gdi_create -- validate a symmetric CSR graph (Sec. IV-A: G(V,E), here with
+ * int32 edge weights), colour it, relabel it colour-major and upload it.
+ *   row_ptr  host, n+1 int32, row_ptr[0] = 0, non-decreasing
+ *   col_idx  host, row_ptr[n] int32 column ids in [0,n), strictly increasing within a row,
+ *            no self-loops; every edge (i,j,w) must have its mirror (j,i,w)
+ *   weights  host, row_ptr[n] int32 edge weights
+ *   n        number of nodes, >= 2
+ *   out      receives the handle
+ * Errors: GDI_EINVAL (malformed or asymmetric CSR, NULL pointer, n < 2),
+ *         GDI_ERANGE (sum_j |w_ij| > 2^30 for some i), GDI_ENOMEM, GDI_EDEVICE.
+ * Validation runs before any device call, so malformed input fails without a GPU.
+ */
+int gdi_create(const int32_t *row_ptr, const int32_t *col_idx, const int32_t *weights, int32_t n,
+               gdi_graph **out);
+
+/* gdi_destroy -- release the handle and its device memory (NULL is a no-op). */
+void gdi_destroy(gdi_graph *g);
+
+/* gdi_set_stream -- order all later device work of the handle on this hipStream_t (NULL = null stream). */
+int gdi_set_stream(gdi_graph *g, void *hip_stream);
+
+/* gdi_set_tuning -- override launch parameters (NULL restores automatic choice). */
+int gdi_set_tuning(gdi_graph *g, const gdi_tuning *tune);
+
+/*
+ * gdi_anneal -- run sweeps start_sweep..S-1 of the GDI schedule (Alg. 3 with
+ * the deterministic readings above) in one persistent device launch and copy
+ * the final spins (original node order) to spins_out (host, n int8).
+ * The final state is returned, not the best one seen.
+ * Errors: GDI_EINVAL (schedule), GDI_ERANGE (|B|*max_wdeg + 4|A|(n+1) >= 2^31),
+ *         GDI_ESTATE, GDI_EDEVICE, GDI_ETIMEOUT, GDI_ENOMEM.
+ */
+int gdi_anneal(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *spins_out);
+
+/* gdi_anneal_dev -- as gdi_anneal, with d_spins_out a device pointer (n int8, original order);
+ * stream-ordered, returns after enqueueing. trace_* pointers must be NULL. */
+int gdi_anneal_dev(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *d_spins_out);
+
+/* gdi_last_result -- outcome of the last anneal (synchronises the handle's stream). */
+int gdi_last_result(gdi_graph *g, gdi_result *out);
+
+/*
+ * gdi_cut -- from-scratch weighted cut, crossing-edge count (the paper's "cut",
+ * Sec. VI) and magnetisation M of a spin vector (host, n int8, original order,
+ * any non-positive value counts as -1). The paper's imbalance "bal" is |M|/2.
+ * Any output pointer may be NULL.
+ */
+int gdi_cut(gdi_graph *g, const int8_t *spins, int64_t *cut_weighted, int64_t *cut_edges,
+            int64_t *magnetization);
+
+/* gdi_cut_dev -- as gdi_cut with d_spins a device pointer; blocks until the three values are on the host. */
+int gdi_cut_dev(gdi_graph *g, const int8_t *d_spins, int64_t *cut_weighted, int64_t *cut_edges,
+                int64_t *magnetization);
+
+/* gdi_get_info -- graph facts. */
+int gdi_get_info(const gdi_graph *g, gdi_graph_info *out);
+
+/* gdi_get_colouring -- colour of every node (original order) and class sizes (n_colours entries). */
+int gdi_get_colouring(const gdi_graph *g, int32_t *colour_out, int32_t *class_size_out);
+
+/*
+ * gdi_colour_csr -- host-only: first-fit greedy colouring in ascending node id of a
+ * validated CSR (colour_out: n int32). Returns the number of colours (> 0) or a GDI_E* code.
+ */
+int gdi_colour_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t *colour_out);
+
+/*
+ * gdi_threshold_table -- host-only: out[t*(width+1) + d] = min(2^32-1, floor(2^32*exp(-d/T_t)))
+ * for t < n_sweeps, 1 <= d <= width; entry d = 0 is 2^32-1. temps must be > 0.
+ */
+int gdi_threshold_table(const double *temps, uint32_t n_sweeps, int32_t width, uint32_t *out);
+
+/*
+ * gdi_philox4x32_10 -- host-only: the Philox4x32-10 block of one counter under
+ * key (seed low, seed high). For checking the generator the kernels use.
+ */
+int gdi_philox4x32_10(uint64_t seed, const uint32_t ctr[4], uint32_t out[4]);
+
+/* gdi_last_error -- thread-local message of the last failing call ("" if none). */
+const char *gdi_last_error(void);
+
+/* gdi_version -- ABI version (major*10000 + minor*100 + patch). */
+int gdi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GDI_H */

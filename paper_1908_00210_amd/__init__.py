@@ -1,0 +1,297 @@
+"""Python binding of libgdi.so, the MI355X GDI annealer (C ABI in include/gdi.h).
+
+Argument marshalling only: every step of the annealing path runs in the HIP
+kernels of libgdi.so. There is no CPU fallback: if the library is missing or no
+gfx950 device is present, the calls raise.
+
+Host-array entry points take numpy arrays; the ``*_dev`` entry points take
+device pointers (e.g. ``torch.Tensor.data_ptr()`` of a tensor on ``cuda:0``) and
+run on the stream given to :func:`set_stream`.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = [
+    "GdiError", "lib", "LIB_PATH", "BAL_GATED", "BAL_SNAPSHOT", "SCOPE_AUTO", "SCOPE_WORKGROUP",
+    "SCOPE_GRID", "Schedule", "Tuning", "Result", "GraphInfo", "create", "destroy", "anneal",
+    "anneal_dev", "cut", "cut_dev", "last_result", "set_stream", "set_tuning", "get_info",
+    "get_colouring", "colour_csr", "threshold_table", "philox4x32_10", "version", "Annealer",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgdi.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, ESTATE, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+_NAMES = {EINVAL: "GDI_EINVAL", ERANGE: "GDI_ERANGE", ENOMEM: "GDI_ENOMEM", EDEVICE: "GDI_EDEVICE",
+          ESTATE: "GDI_ESTATE", ETIMEOUT: "GDI_ETIMEOUT"}
+BAL_GATED, BAL_SNAPSHOT = 0, 1
+SCOPE_AUTO, SCOPE_WORKGROUP, SCOPE_GRID = 0, 1, 2
+
+
+class GdiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [
+        ("n_sweeps", ctypes.c_uint32),
+        ("start_sweep", ctypes.c_uint32),
+        ("temps", ctypes.c_void_p),
+        ("A", ctypes.c_int32),
+        ("B", ctypes.c_int32),
+        ("replica", ctypes.c_uint32),
+        ("balance_mode", ctypes.c_uint32),
+        ("init_spins", ctypes.c_void_p),
+        ("trace_m", ctypes.c_void_p),
+        ("trace_cut", ctypes.c_void_p),
+    ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("scope", ctypes.c_uint32), ("block", ctypes.c_uint32), ("grid", ctypes.c_uint32),
+                ("lanes_per_node", ctypes.c_uint32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("magnetization", ctypes.c_int64),
+        ("cut_weighted", ctypes.c_int64),
+        ("sweep_ms", ctypes.c_double),
+        ("n_colours", ctypes.c_uint32),
+        ("scope", ctypes.c_uint32),
+        ("grid", ctypes.c_uint32),
+        ("block", ctypes.c_uint32),
+        ("lanes_per_node", ctypes.c_uint32),
+        ("table_width", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("n_colours", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("max_abs_wdeg", ctypes.c_int64), ("max_degree", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+# every symbol include/gdi.h declares, with (restype, argtypes)
+_P = ctypes.c_void_p
+SIGNATURES = {
+    "gdi_create": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "gdi_destroy": (None, [_P]),
+    "gdi_set_stream": (ctypes.c_int, [_P, _P]),
+    "gdi_set_tuning": (ctypes.c_int, [_P, ctypes.POINTER(Tuning)]),
+    "gdi_anneal": (ctypes.c_int, [_P, ctypes.POINTER(Schedule), ctypes.c_uint64, _P]),
+    "gdi_anneal_dev": (ctypes.c_int, [_P, ctypes.POINTER(Schedule), ctypes.c_uint64, _P]),
+    "gdi_last_result": (ctypes.c_int, [_P, ctypes.POINTER(Result)]),
+    "gdi_cut": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "gdi_cut_dev": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "gdi_get_info": (ctypes.c_int, [_P, ctypes.POINTER(GraphInfo)]),
+    "gdi_get_colouring": (ctypes.c_int, [_P, _P, _P]),
+    "gdi_colour_csr": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
+    "gdi_threshold_table": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_int32, _P]),
+    "gdi_philox4x32_10": (ctypes.c_int, [ctypes.c_uint64, _P, _P]),
+    "gdi_last_error": (ctypes.c_char_p, []),
+    "gdi_version": (ctypes.c_int, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Loads libgdi.so (raises if it has not been built: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1908_00210_amd/build.py "
+                              "or __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc < 0:
+        raise GdiError(rc, lib().gdi_last_error().decode(errors="replace"))
+    return rc
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def version() -> int:
+    return lib().gdi_version()
+
+
+def create(row_ptr, col, w, n: int):
+    """gdi_create on a symmetric int32 CSR; returns the opaque handle (an int)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col, dtype=np.int32)
+    ww = np.ascontiguousarray(w, dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(lib().gdi_create(_ptr(rp), _ptr(ci), _ptr(ww), int(n), ctypes.byref(h)))
+    return h.value
+
+
+def destroy(h):
+    lib().gdi_destroy(h)
+
+
+def set_stream(h, stream_ptr: int | None):
+    _check(lib().gdi_set_stream(h, stream_ptr))
+
+
+def set_tuning(h, scope: int = 0, block: int = 0, grid: int = 0, lanes_per_node: int = 0, reset=False):
+    if reset:
+        _check(lib().gdi_set_tuning(h, None))
+        return
+    t = Tuning(scope, block, grid, lanes_per_node)
+    _check(lib().gdi_set_tuning(h, ctypes.byref(t)))
+
+
+def _schedule(temps, A, B, replica, mode, start_sweep, init, trace_m, trace_cut):
+    T = np.ascontiguousarray(temps, dtype=np.float64)
+    s = Schedule(n_sweeps=T.size, start_sweep=start_sweep, temps=T.ctypes.data, A=A, B=B,
+                 replica=replica, balance_mode=mode,
+                 init_spins=None if init is None else init.ctypes.data,
+                 trace_m=None if trace_m is None else trace_m.ctypes.data,
+                 trace_cut=None if trace_cut is None else trace_cut.ctypes.data)
+    return s, T
+
+
+def anneal(h, n: int, temps, seed: int, A: int = 1, B: int = 1, replica: int = 0, mode: int = BAL_GATED,
+           start_sweep: int = 0, init=None, trace: bool = False) -> dict:
+    """gdi_anneal: returns dict(spins (original order), M, cut, result, [trace_m, trace_cut])."""
+    T = np.ascontiguousarray(temps, dtype=np.float64)
+    init_a = None if init is None else np.ascontiguousarray(init, dtype=np.int8)
+    tm = np.zeros(T.size, dtype=np.int64) if trace else None
+    tc = np.zeros(T.size, dtype=np.int64) if trace else None
+    s, T = _schedule(T, A, B, replica, mode, start_sweep, init_a, tm, tc)
+    out = np.zeros(n, dtype=np.int8)
+    _check(lib().gdi_anneal(h, ctypes.byref(s), ctypes.c_uint64(seed), _ptr(out)))
+    r = last_result(h)
+    d = dict(spins=out, M=r.magnetization, cut=r.cut_weighted, result=r.as_dict())
+    if trace:
+        d["trace_m"], d["trace_cut"] = tm, tc
+    return d
+
+
+def anneal_dev(h, temps, seed: int, d_spins_out: int, A: int = 1, B: int = 1, replica: int = 0,
+               mode: int = BAL_GATED, start_sweep: int = 0, init=None):
+    """gdi_anneal_dev: enqueues the anneal on the handle's stream; d_spins_out is a device pointer."""
+    init_a = None if init is None else np.ascontiguousarray(init, dtype=np.int8)
+    s, T = _schedule(temps, A, B, replica, mode, start_sweep, init_a, None, None)
+    _check(lib().gdi_anneal_dev(h, ctypes.byref(s), ctypes.c_uint64(seed), ctypes.c_void_p(d_spins_out)))
+
+
+def last_result(h) -> Result:
+    r = Result()
+    _check(lib().gdi_last_result(h, ctypes.byref(r)))
+    return r
+
+
+def cut(h, spins) -> tuple:
+    """(weighted cut, crossing edges, M) of host spins (original order)."""
+    s = np.ascontiguousarray(spins, dtype=np.int8)
+    cw, ce, m = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().gdi_cut(h, _ptr(s), ctypes.byref(cw), ctypes.byref(ce), ctypes.byref(m)))
+    return cw.value, ce.value, m.value
+
+
+def cut_dev(h, d_spins: int) -> tuple:
+    cw, ce, m = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().gdi_cut_dev(h, ctypes.c_void_p(d_spins), ctypes.byref(cw), ctypes.byref(ce), ctypes.byref(m)))
+    return cw.value, ce.value, m.value
+
+
+def get_info(h) -> GraphInfo:
+    i = GraphInfo()
+    _check(lib().gdi_get_info(h, ctypes.byref(i)))
+    return i
+
+
+def get_colouring(h, n: int, n_colours: int) -> tuple:
+    col = np.zeros(n, dtype=np.int32)
+    sizes = np.zeros(n_colours, dtype=np.int32)
+    _check(lib().gdi_get_colouring(h, _ptr(col), _ptr(sizes)))
+    return col, sizes
+
+
+def colour_csr(row_ptr, col, n: int) -> tuple:
+    """Host-only first-fit colouring: (colour array, number of colours)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(col, dtype=np.int32)
+    out = np.zeros(n, dtype=np.int32)
+    C = _check(lib().gdi_colour_csr(_ptr(rp), _ptr(ci), int(n), _ptr(out)))
+    return out, C
+
+
+def threshold_table(temps, width: int) -> np.ndarray:
+    T = np.ascontiguousarray(temps, dtype=np.float64)
+    out = np.zeros((T.size, width + 1), dtype=np.uint32)
+    _check(lib().gdi_threshold_table(_ptr(T), T.size, int(width), _ptr(out)))
+    return out
+
+
+def philox4x32_10(seed: int, ctr) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _check(lib().gdi_philox4x32_10(ctypes.c_uint64(seed), _ptr(c), _ptr(out)))
+    return out
+
+
+class Annealer:
+    """Owns one gdi_graph handle for a graph with fields n, row_ptr, col, w."""
+
+    def __init__(self, graph):
+        self.n = int(graph.n)
+        self.h = create(graph.row_ptr, graph.col, graph.w, self.n)
+        self.info = get_info(self.h)
+
+    def close(self):
+        if self.h:
+            destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def anneal(self, temps, seed, **kw) -> dict:
+        return anneal(self.h, self.n, temps, seed, **kw)
+
+    def anneal_dev(self, temps, seed, d_spins_out, **kw):
+        anneal_dev(self.h, temps, seed, d_spins_out, **kw)
+
+    def cut(self, spins):
+        return cut(self.h, spins)
+
+    def result(self) -> Result:
+        return last_result(self.h)
+
+    def tune(self, **kw):
+        set_tuning(self.h, **kw)
+
+    def set_stream(self, stream_ptr):
+        set_stream(self.h, stream_ptr)
+
+    def colouring(self):
+        return get_colouring(self.h, self.n, self.info.n_colours)

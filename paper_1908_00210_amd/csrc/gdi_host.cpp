@@ -1,0 +1,720 @@
+// gdi_host.cpp -- host side of the GDI annealer library (C ABI in include/gdi.h).
+//
+// Responsibilities: CSR validation (before any device call), first-fit greedy
+// colouring in ascending node id, colour-major relabelling with 64-aligned class
+// starts, FP64 -> uint32 Metropolis threshold tables, device buffers, launch
+// selection (workgroup or grid scope) and result transfer. No exception crosses
+// the C ABI.
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gdi.h"
+#include "gdi_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? GDI_ENOMEM : GDI_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                                   \
+    do {                                                      \
+        hipError_t e_ = (expr);                               \
+        if (e_ != hipSuccess) return hip_fail(e_, (what));    \
+    } while (0)
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // grow-only allocation of at least count elements
+    hipError_t reserve(size_t count)
+    {
+        if (count <= n && p) return hipSuccess;
+        release();
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
+        if (e != hipSuccess) return e;
+        p = static_cast<T *>(q);
+        n = count;
+        return hipSuccess;
+    }
+};
+
+}  // namespace
+
+struct gdi_graph {
+    int32_t n = 0, n_pad = 0, C = 0;
+    int64_t nnz = 0;
+    int64_t max_abs_wdeg = 0;
+    int32_t max_degree = 0;
+    std::vector<int32_t> colour;      // original order
+    std::vector<int32_t> cbeg, csz;   // per class, new ids
+    std::vector<int32_t> orig;        // new -> original (-1 padding)
+
+    DevBuf<int32_t> d_rp, d_orig, d_cbeg, d_csz, d_P;
+    DevBuf<int2> d_adj;
+    DevBuf<int8_t> d_spin, d_io;
+    DevBuf<int64_t> d_state, d_red, d_trace;
+    DevBuf<uint32_t> d_thr;
+    DevBuf<uint64_t> d_bar;
+
+    std::vector<double> thr_key;      // temperatures of the cached table
+    int32_t thr_K = -1;
+    int64_t thr_demax = -1;
+
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    gdi_tuning tune{};
+    bool have_tune = false;
+
+    // last run
+    bool pending = false;
+    int64_t last_cut0 = 0;
+    gdi_result last{};
+    bool last_valid = false;
+
+    ~gdi_graph()
+    {
+        d_rp.release(); d_orig.release(); d_cbeg.release(); d_csz.release(); d_P.release();
+        d_adj.release(); d_spin.release(); d_io.release(); d_state.release(); d_red.release();
+        d_trace.release(); d_thr.release(); d_bar.release();
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+    }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ validation
+int validate_csr(const int32_t *rp, const int32_t *col, const int32_t *w, int32_t n, int64_t *max_wdeg,
+                 int32_t *max_deg)
+{
+    if (!rp || !col || !w) return fail(GDI_EINVAL, "NULL CSR array");
+    if (n < 2) return fail(GDI_EINVAL, "n must be >= 2");
+    if (rp[0] != 0) return fail(GDI_EINVAL, "row_ptr[0] must be 0");
+    for (int32_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i])
+            return fail(GDI_EINVAL, "row_ptr is decreasing at row " + std::to_string(i));
+    int64_t mw = 0;
+    int32_t md = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int64_t s = 0;
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t j = col[k];
+            if (j < 0 || j >= n)
+                return fail(GDI_EINVAL, "column out of range in row " + std::to_string(i));
+            if (j == i) return fail(GDI_EINVAL, "self-loop at node " + std::to_string(i));
+            if (k > rp[i] && col[k - 1] >= j)
+                return fail(GDI_EINVAL, "columns not strictly increasing (or duplicate) in row " +
+                                            std::to_string(i));
+            s += std::llabs((long long)w[k]);
+        }
+        if (s > (int64_t(1) << 30))
+            return fail(GDI_ERANGE, "sum of |weights| exceeds 2^30 at node " + std::to_string(i));
+        mw = std::max(mw, s);
+        md = std::max(md, rp[i + 1] - rp[i]);
+    }
+    // symmetry: every (i, j, w) has its mirror (j, i, w); rows are sorted, so binary search
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t j = col[k];
+            const int32_t *b = col + rp[j], *e = col + rp[j + 1];
+            const int32_t *f = std::lower_bound(b, e, i);
+            if (f == e || *f != i)
+                return fail(GDI_EINVAL, "edge (" + std::to_string(i) + "," + std::to_string(j) +
+                                            ") has no mirror");
+            if (w[f - col] != w[k])
+                return fail(GDI_EINVAL, "edge (" + std::to_string(i) + "," + std::to_string(j) +
+                                            ") has a different mirror weight");
+        }
+    }
+    *max_wdeg = mw;
+    *max_deg = md;
+    return GDI_OK;
+}
+
+// First-fit greedy colouring in ascending node id. used[c] == i marks colour c as
+// taken by an already coloured neighbour of node i.
+int32_t colour_first_fit(const int32_t *rp, const int32_t *col, int32_t n, int32_t *colour)
+{
+    std::vector<int32_t> used((size_t)n + 1, -1);
+    int32_t ncol = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
+            const int32_t j = col[k];
+            if (j < i) used[(size_t)colour[j]] = i;
+        }
+        int32_t c = 0;
+        while (used[(size_t)c] == i) ++c;
+        colour[i] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    return ncol;
+}
+
+uint32_t threshold_of(int64_t d, double T)
+{
+    const double v = std::floor(std::ldexp(std::exp(-(double)d / T), 32));
+    if (v >= 4294967295.0) return 0xFFFFFFFFu;
+    if (v <= 0.0) return 0u;
+    return (uint32_t)v;
+}
+
+struct Choice {
+    uint32_t scope, block, grid, lanes;
+    bool spins_lds;
+};
+
+int lanes_for_degree(double avg_deg)
+{
+    int L = 1;
+    while (L < 32 && 2.0 * L < avg_deg) L *= 2;
+    return L;
+}
+
+const int64_t kSpinLimit = int64_t(1) << 22;
+const int32_t kWgMaxNodes = 65536;
+
+int pick_launch(gdi_graph *g, Choice *ch)
+{
+    const gdi_tuning t = g->have_tune ? g->tune : gdi_tuning{};
+    const double avg = g->n ? (double)g->nnz / g->n : 0.0;
+    ch->lanes = t.lanes_per_node ? t.lanes_per_node : (uint32_t)lanes_for_degree(avg);
+    if (ch->lanes == 0 || ch->lanes > 64 || (ch->lanes & (ch->lanes - 1)))
+        return fail(GDI_EINVAL, "lanes_per_node must be a power of two in [1, 64]");
+    ch->block = t.block ? t.block : 1024u;
+    if (ch->block < 64 || ch->block > GDI_MAX_BLOCK || ch->block % 64 || ch->block < ch->lanes)
+        return fail(GDI_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+    ch->scope = t.scope ? t.scope : (g->n_pad <= kWgMaxNodes ? GDI_SCOPE_WORKGROUP : GDI_SCOPE_GRID);
+    if (ch->scope != GDI_SCOPE_WORKGROUP && ch->scope != GDI_SCOPE_GRID)
+        return fail(GDI_EINVAL, "unknown scope");
+    ch->grid = 1;
+    ch->spins_lds = false;
+    if (ch->scope == GDI_SCOPE_WORKGROUP) {
+        int dev = 0, lds_max = 0;
+        HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+        HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+                "hipDeviceGetAttribute");
+        ch->spins_lds = gdi_wg_lds_bytes(g->n_pad, g->C, 1) + 64 <= lds_max;
+        if (gdi_wg_lds_bytes(g->n_pad, g->C, 0) + 64 > lds_max)
+            return fail(GDI_ERANGE, "too many colour classes for one workgroup's LDS");
+    } else {
+        int cap = 0;
+        int e = gdi_grid_capacity((int)ch->block, (int)ch->lanes, &cap);
+        if (e) return fail(GDI_EDEVICE, std::string("occupancy query: ") + gdi_hip_error_string(e));
+        int dev = 0, cus = 0;
+        HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+        uint32_t want = t.grid ? t.grid : (uint32_t)std::min(cap, cus);
+        if (want < 1 || (int)want > cap)
+            return fail(GDI_EDEVICE, "grid of " + std::to_string(want) +
+                                         " workgroups cannot be co-resident (capacity " +
+                                         std::to_string(cap) + ")");
+        ch->grid = want;
+    }
+    return GDI_OK;
+}
+
+int check_device()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    HIP_TRY(hipGetDeviceProperties(&prop, dev), "hipGetDeviceProperties");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(GDI_EDEVICE, std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
+    return GDI_OK;
+}
+
+int upload(gdi_graph *g, const int32_t *rp, const int32_t *col, const int32_t *w)
+{
+    const int32_t n = g->n;
+    // colour-major relabel: class c in ascending original id, class starts aligned
+    std::vector<int32_t> cnt((size_t)g->C, 0);
+    for (int32_t i = 0; i < n; ++i) cnt[(size_t)g->colour[i]]++;
+    g->cbeg.assign((size_t)g->C, 0);
+    g->csz = cnt;
+    int64_t pos = 0;
+    for (int32_t c = 0; c < g->C; ++c) {
+        g->cbeg[(size_t)c] = (int32_t)pos;
+        pos += cnt[(size_t)c];
+        pos = (pos + GDI_CLASS_ALIGN - 1) / GDI_CLASS_ALIGN * GDI_CLASS_ALIGN;
+    }
+    if (pos > INT32_MAX - 1) return fail(GDI_ERANGE, "padded node count exceeds int32");
+    g->n_pad = (int32_t)pos;
+    std::vector<int32_t> inv((size_t)n);
+    g->orig.assign((size_t)g->n_pad, -1);
+    std::vector<int32_t> fillc((size_t)g->C, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t c = g->colour[i];
+        const int32_t v = g->cbeg[(size_t)c] + fillc[(size_t)c]++;
+        inv[(size_t)i] = v;
+        g->orig[(size_t)v] = i;
+    }
+    std::vector<int32_t> nrp((size_t)g->n_pad + 1, 0);
+    for (int32_t v = 0; v < g->n_pad; ++v) {
+        const int32_t o = g->orig[(size_t)v];
+        nrp[(size_t)v + 1] = nrp[(size_t)v] + (o >= 0 ? rp[o + 1] - rp[o] : 0);
+    }
+    std::vector<int2> adj((size_t)g->nnz);
+    std::vector<std::pair<int32_t, int32_t>> row;
+    for (int32_t v = 0; v < g->n_pad; ++v) {
+        const int32_t o = g->orig[(size_t)v];
+        if (o < 0) continue;
+        row.clear();
+        for (int32_t k = rp[o]; k < rp[o + 1]; ++k) row.emplace_back(inv[(size_t)col[k]], w[k]);
+        std::sort(row.begin(), row.end());
+        int64_t base = nrp[(size_t)v];
+        for (size_t q = 0; q < row.size(); ++q) adj[(size_t)base + q] = make_int2(row[q].first, row[q].second);
+    }
+    HIP_TRY(g->d_rp.reserve(nrp.size()), "hipMalloc row_ptr");
+    HIP_TRY(g->d_adj.reserve(adj.size()), "hipMalloc adjacency");
+    HIP_TRY(g->d_orig.reserve(g->orig.size()), "hipMalloc orig");
+    HIP_TRY(g->d_cbeg.reserve((size_t)g->C), "hipMalloc classes");
+    HIP_TRY(g->d_csz.reserve((size_t)g->C), "hipMalloc classes");
+    HIP_TRY(g->d_P.reserve((size_t)g->C + 2), "hipMalloc P");
+    HIP_TRY(g->d_spin.reserve((size_t)g->n_pad), "hipMalloc spins");
+    HIP_TRY(g->d_io.reserve((size_t)n), "hipMalloc io");
+    HIP_TRY(g->d_state.reserve(8), "hipMalloc state");
+    HIP_TRY(g->d_red.reserve(4), "hipMalloc state");
+    HIP_TRY(hipMemcpy(g->d_rp.p, nrp.data(), nrp.size() * 4, hipMemcpyHostToDevice), "upload row_ptr");
+    if (!adj.empty())
+        HIP_TRY(hipMemcpy(g->d_adj.p, adj.data(), adj.size() * sizeof(int2), hipMemcpyHostToDevice),
+                "upload adjacency");
+    HIP_TRY(hipMemcpy(g->d_orig.p, g->orig.data(), g->orig.size() * 4, hipMemcpyHostToDevice), "upload orig");
+    HIP_TRY(hipMemcpy(g->d_cbeg.p, g->cbeg.data(), g->cbeg.size() * 4, hipMemcpyHostToDevice), "upload classes");
+    HIP_TRY(hipMemcpy(g->d_csz.p, g->csz.data(), g->csz.size() * 4, hipMemcpyHostToDevice), "upload classes");
+    HIP_TRY(hipEventCreate(&g->ev0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&g->ev1), "hipEventCreate");
+    return GDI_OK;
+}
+
+// Threshold table for the schedule, cached on the handle by temperature content.
+int ensure_table(gdi_graph *g, const gdi_schedule *s, int64_t de_max)
+{
+    const uint32_t S = s->n_sweeps;
+    if (g->thr_K >= 0 && g->thr_demax == de_max && g->thr_key.size() == S &&
+        std::memcmp(g->thr_key.data(), s->temps, S * sizeof(double)) == 0)
+        return GDI_OK;
+    // width K: largest d <= de_max with a non-zero threshold at some sweep
+    int64_t K = 0;
+    for (uint32_t t = 0; t < S; ++t) {
+        const double T = s->temps[t];
+        // thr(d) >= 1 iff 2^32 exp(-d/T) >= 1, i.e. d <= 32 ln2 T; probe around that bound exactly
+        int64_t d = (int64_t)std::min<double>((double)de_max, std::floor(32.0 * 0.6931471805599453 * T) + 2.0);
+        if (threshold_of(d, T) != 0) {
+            while (d < de_max && threshold_of(d + 1, T) != 0) ++d;
+        } else {
+            while (d > K && threshold_of(d, T) == 0) --d;
+        }
+        K = std::max(K, d);
+    }
+    if (K > (int64_t)64 * 1024 * 1024 / std::max<uint32_t>(S, 1))
+        return fail(GDI_ERANGE, "threshold table too large (temperatures too high for the graph size)");
+    std::vector<uint32_t> tab((size_t)S * (size_t)(K + 1));
+    for (uint32_t t = 0; t < S; ++t) {
+        uint32_t *row = tab.data() + (size_t)t * (size_t)(K + 1);
+        row[0] = 0xFFFFFFFFu;
+        for (int64_t d = 1; d <= K; ++d) row[d] = threshold_of(d, s->temps[t]);
+    }
+    HIP_TRY(g->d_thr.reserve(tab.size()), "hipMalloc thresholds");
+    HIP_TRY(hipMemcpyAsync(g->d_thr.p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, g->stream),
+            "upload thresholds");
+    HIP_TRY(hipStreamSynchronize(g->stream), "upload thresholds");
+    g->thr_key.assign(s->temps, s->temps + S);
+    g->thr_K = (int32_t)K;
+    g->thr_demax = de_max;
+    return GDI_OK;
+}
+
+int finish_pending(gdi_graph *g)
+{
+    if (!g->pending) return GDI_OK;
+    g->pending = false;
+    HIP_TRY(hipStreamSynchronize(g->stream), "anneal");
+    int64_t st[8], red[4];
+    HIP_TRY(hipMemcpy(st, g->d_state.p, sizeof(st), hipMemcpyDeviceToHost), "read state");
+    HIP_TRY(hipMemcpy(red, g->d_red.p, sizeof(red), hipMemcpyDeviceToHost), "read state");
+    if (st[3] != 0) {
+        g->last_valid = false;
+        return fail(GDI_ETIMEOUT, "a device-side barrier wait expired; results are invalid");
+    }
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, g->ev0, g->ev1), "hipEventElapsedTime");
+    g->last.magnetization = st[0];
+    g->last.cut_weighted = red[1] / 2 + st[1];
+    g->last.sweep_ms = ms;
+    g->last_cut0 = red[1] / 2;
+    g->last_valid = true;
+    return GDI_OK;
+}
+
+int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host_out, int8_t *dev_out)
+{
+    if (!g) return fail(GDI_ESTATE, "NULL handle");
+    if (!s) return fail(GDI_EINVAL, "NULL schedule");
+    int rc = finish_pending(g);
+    if (rc) return rc;
+    const uint32_t S = s->n_sweeps;
+    if (S < 1) return fail(GDI_EINVAL, "n_sweeps must be >= 1");
+    if (!s->temps) return fail(GDI_EINVAL, "NULL temps");
+    if (s->start_sweep > S) return fail(GDI_EINVAL, "start_sweep > n_sweeps");
+    for (uint32_t t = 0; t < S; ++t)
+        if (!(s->temps[t] > 0.0)) return fail(GDI_EINVAL, "temperatures must be > 0");
+    if (s->balance_mode > GDI_BAL_SNAPSHOT) return fail(GDI_EINVAL, "unknown balance_mode");
+    if (dev_out && (s->trace_m || s->trace_cut)) return fail(GDI_EINVAL, "traces need the host variant");
+    const int64_t de_max = std::llabs((long long)s->B) * g->max_abs_wdeg + 4 * std::llabs((long long)s->A) * ((int64_t)g->n + 1);
+    if (de_max >= (int64_t(1) << 31))
+        return fail(GDI_ERANGE, "|B|*max_wdeg + 4|A|(n+1) must be < 2^31");
+    const bool trace = s->trace_m || s->trace_cut;
+
+    Choice ch;
+    if ((rc = pick_launch(g, &ch))) return rc;
+    if ((rc = ensure_table(g, s, de_max))) return rc;
+    const uint64_t phases = (uint64_t)(S - s->start_sweep) * (uint64_t)g->C;
+    uint64_t bar_words = 0;
+    if (ch.scope == GDI_SCOPE_GRID) {
+        if (phases > (uint64_t(1) << 22)) return fail(GDI_ERANGE, "too many phases for one launch");
+        bar_words = phases * (GDI_BAR_GROUPS + 1) * GDI_BAR_PAD;
+        HIP_TRY(g->d_bar.reserve(bar_words), "hipMalloc barrier");
+    }
+    if (trace) HIP_TRY(g->d_trace.reserve(2 * (size_t)S), "hipMalloc trace");
+
+    hipStream_t st = g->stream;
+    // initial state
+    if (s->init_spins) {
+        HIP_TRY(hipMemcpyAsync(g->d_io.p, s->init_spins, (size_t)g->n, hipMemcpyHostToDevice, st), "upload spins");
+        if ((rc = gdi_launch_gather_in(g->d_orig.p, g->d_io.p, g->n_pad, g->d_spin.p, st)))
+            return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
+    } else {
+        if ((rc = gdi_launch_init_spins(g->d_orig.p, nullptr, g->d_spin.p, g->n_pad, (uint32_t)seed,
+                                        (uint32_t)(seed >> 32), s->replica, st)))
+            return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
+    }
+    rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_state.p), 8, st);
+    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_red.p), 4, st);
+    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_P.p), (g->C + 2) / 2, st);
+    if (!rc && trace) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_trace.p), 2 * (int64_t)S, st);
+    if (!rc && bar_words) rc = gdi_launch_fill_u64(g->d_bar.p, (int64_t)bar_words, st);
+    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->d_cbeg.p, g->d_csz.p,
+                                    g->C, g->d_red.p, g->d_P.p, st);
+    // the sweep kernels read the initial M from state[0]
+    if (!rc) {
+        hipError_t e = hipMemcpyAsync(g->d_state.p, g->d_red.p, 8, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "state copy");
+    }
+    if (rc) return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
+
+    GdiSweepArgs a{};
+    a.rp = g->d_rp.p;
+    a.adj = g->d_adj.p;
+    a.orig = g->d_orig.p;
+    a.spin = g->d_spin.p;
+    a.cbeg = g->d_cbeg.p;
+    a.csz = g->d_csz.p;
+    a.thr = g->d_thr.p;
+    a.state = g->d_state.p;
+    a.P = g->d_P.p;
+    a.trace_m = trace ? g->d_trace.p : nullptr;
+    a.trace_dcut = trace ? g->d_trace.p + S : nullptr;
+    a.bar_grp = bar_words ? g->d_bar.p : nullptr;
+    a.bar_glob = bar_words ? g->d_bar.p + phases * GDI_BAR_GROUPS * GDI_BAR_PAD : nullptr;
+    a.n = g->n;
+    a.n_pad = g->n_pad;
+    a.C = g->C;
+    a.K = g->thr_K;
+    a.t0 = s->start_sweep;
+    a.S = S;
+    a.A4 = 4 * s->A;
+    a.B = s->B;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.replica = s->replica;
+    a.snapshot = s->balance_mode == GDI_BAL_SNAPSHOT ? 1u : 0u;
+    a.spin_limit = kSpinLimit;
+
+    HIP_TRY(hipEventRecord(g->ev0, st), "hipEventRecord");
+    if (ch.scope == GDI_SCOPE_WORKGROUP)
+        rc = gdi_launch_sweep_wg(a, (int)ch.block, (int)ch.lanes, ch.spins_lds ? 1 : 0, st);
+    else
+        rc = gdi_launch_sweep_grid(a, (int)ch.grid, (int)ch.block, (int)ch.lanes, st);
+    if (rc) return fail(GDI_EDEVICE, std::string("sweep launch: ") + gdi_hip_error_string(rc));
+    HIP_TRY(hipEventRecord(g->ev1, st), "hipEventRecord");
+
+    g->last = gdi_result{};
+    g->last.n_colours = (uint32_t)g->C;
+    g->last.scope = ch.scope;
+    g->last.grid = ch.grid;
+    g->last.block = ch.block;
+    g->last.lanes_per_node = ch.lanes;
+    g->last.table_width = (uint32_t)g->thr_K;
+    g->last_valid = false;
+
+    int8_t *out_dev = dev_out ? dev_out : g->d_io.p;
+    if ((rc = gdi_launch_scatter_out(g->d_orig.p, g->d_spin.p, g->n_pad, out_dev, st)))
+        return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
+    g->pending = true;
+    if (dev_out) return GDI_OK;
+
+    if ((rc = finish_pending(g))) return rc;
+    HIP_TRY(hipMemcpy(host_out, g->d_io.p, (size_t)g->n, hipMemcpyDeviceToHost), "download spins");
+    if (trace) {
+        std::vector<int64_t> tr(2 * (size_t)S);
+        HIP_TRY(hipMemcpy(tr.data(), g->d_trace.p, tr.size() * 8, hipMemcpyDeviceToHost), "download trace");
+        int64_t cut = g->last_cut0;
+        for (uint32_t t = s->start_sweep; t < S; ++t) {
+            cut += tr[S + t];
+            if (s->trace_m) s->trace_m[t] = tr[t];
+            if (s->trace_cut) s->trace_cut[t] = cut;
+        }
+    }
+    return GDI_OK;
+}
+
+int cut_impl(gdi_graph *g, const int8_t *spins, bool dev, int64_t *cw, int64_t *ce, int64_t *m)
+{
+    if (!g) return fail(GDI_ESTATE, "NULL handle");
+    if (!spins) return fail(GDI_EINVAL, "NULL spins");
+    int rc = finish_pending(g);
+    if (rc) return rc;
+    hipStream_t st = g->stream;
+    const int8_t *src = spins;
+    if (!dev) {
+        HIP_TRY(hipMemcpyAsync(g->d_io.p, spins, (size_t)g->n, hipMemcpyHostToDevice, st), "upload spins");
+        src = g->d_io.p;
+    }
+    // a scratch copy so a pending anneal state is not disturbed
+    DevBuf<int8_t> tmp;
+    HIP_TRY(tmp.reserve((size_t)g->n_pad), "hipMalloc");
+    DevBuf<int32_t> P;
+    HIP_TRY(P.reserve((size_t)g->C + 2), "hipMalloc");
+    DevBuf<int64_t> red;
+    HIP_TRY(red.reserve(4), "hipMalloc");
+    rc = gdi_launch_gather_in(g->d_orig.p, src, g->n_pad, tmp.p, st);
+    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(red.p), 4, st);
+    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(P.p), (g->C + 2) / 2, st);
+    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, tmp.p, g->n_pad, g->d_cbeg.p, g->d_csz.p, g->C,
+                                    red.p, P.p, st);
+    if (rc) {
+        tmp.release(); P.release(); red.release();
+        return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
+    }
+    int64_t h[4];
+    hipError_t e = hipMemcpyAsync(h, red.p, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    tmp.release(); P.release(); red.release();
+    if (e != hipSuccess) return hip_fail(e, "gdi_cut");
+    if (m) *m = h[0];
+    if (cw) *cw = h[1] / 2;
+    if (ce) *ce = h[2] / 2;
+    return GDI_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int gdi_version(void) { return 100; }
+
+const char *gdi_last_error(void) { return g_err.c_str(); }
+
+int gdi_colour_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, int32_t *colour_out)
+{
+    if (!row_ptr || !col_idx || !colour_out) return fail(GDI_EINVAL, "NULL argument");
+    if (n < 1) return fail(GDI_EINVAL, "n must be >= 1");
+    try {
+        return colour_first_fit(row_ptr, col_idx, n, colour_out);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_threshold_table(const double *temps, uint32_t n_sweeps, int32_t width, uint32_t *out)
+{
+    if (!temps || !out || width < 0) return fail(GDI_EINVAL, "bad argument");
+    for (uint32_t t = 0; t < n_sweeps; ++t) {
+        if (!(temps[t] > 0.0)) return fail(GDI_EINVAL, "temperatures must be > 0");
+        uint32_t *row = out + (size_t)t * (size_t)(width + 1);
+        row[0] = 0xFFFFFFFFu;
+        for (int32_t d = 1; d <= width; ++d) row[d] = threshold_of(d, temps[t]);
+    }
+    return GDI_OK;
+}
+
+int gdi_philox4x32_10(uint64_t seed, const uint32_t ctr[4], uint32_t out[4])
+{
+    if (!ctr || !out) return fail(GDI_EINVAL, "NULL argument");
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)0xD2511F53u * x0;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * x2;
+        const uint32_t y0 = (uint32_t)(b >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = (uint32_t)(a >> 32) ^ x3 ^ k1;
+        x0 = y0;
+        x1 = (uint32_t)b;
+        x2 = y2;
+        x3 = (uint32_t)a;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+    return GDI_OK;
+}
+
+int gdi_create(const int32_t *row_ptr, const int32_t *col_idx, const int32_t *weights, int32_t n,
+               gdi_graph **out)
+{
+    if (!out) return fail(GDI_EINVAL, "NULL out");
+    *out = nullptr;
+    gdi_graph *g = nullptr;
+    try {
+        int64_t mw = 0;
+        int32_t md = 0;
+        int rc = validate_csr(row_ptr, col_idx, weights, n, &mw, &md);
+        if (rc) return rc;
+        g = new gdi_graph();
+        g->n = n;
+        g->nnz = row_ptr[n];
+        g->max_abs_wdeg = mw;
+        g->max_degree = md;
+        g->colour.assign((size_t)n, 0);
+        g->C = colour_first_fit(row_ptr, col_idx, n, g->colour.data());
+        if ((rc = check_device())) { delete g; return rc; }
+        if ((rc = upload(g, row_ptr, col_idx, weights))) { delete g; return rc; }
+    } catch (const std::bad_alloc &) {
+        delete g;
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+    *out = g;
+    return GDI_OK;
+}
+
+void gdi_destroy(gdi_graph *g)
+{
+    if (!g) return;
+    if (g->pending) (void)hipStreamSynchronize(g->stream);
+    delete g;
+}
+
+int gdi_set_stream(gdi_graph *g, void *hip_stream)
+{
+    if (!g) return fail(GDI_ESTATE, "NULL handle");
+    int rc = finish_pending(g);
+    if (rc) return rc;
+    g->stream = (hipStream_t)hip_stream;
+    return GDI_OK;
+}
+
+int gdi_set_tuning(gdi_graph *g, const gdi_tuning *tune)
+{
+    if (!g) return fail(GDI_ESTATE, "NULL handle");
+    if (tune) {
+        g->tune = *tune;
+        g->have_tune = true;
+    } else {
+        g->have_tune = false;
+    }
+    return GDI_OK;
+}
+
+int gdi_anneal(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *spins_out)
+{
+    if (!spins_out) return fail(GDI_EINVAL, "NULL spins_out");
+    try {
+        return anneal_impl(g, s, seed, spins_out, nullptr);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_anneal_dev(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *d_spins_out)
+{
+    if (!d_spins_out) return fail(GDI_EINVAL, "NULL d_spins_out");
+    try {
+        return anneal_impl(g, s, seed, nullptr, d_spins_out);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_last_result(gdi_graph *g, gdi_result *out)
+{
+    if (!g) return fail(GDI_ESTATE, "NULL handle");
+    if (!out) return fail(GDI_EINVAL, "NULL out");
+    int rc = finish_pending(g);
+    if (rc) return rc;
+    if (!g->last_valid) return fail(GDI_ESTATE, "no completed anneal on this handle");
+    *out = g->last;
+    return GDI_OK;
+}
+
+int gdi_cut(gdi_graph *g, const int8_t *spins, int64_t *cut_weighted, int64_t *cut_edges,
+            int64_t *magnetization)
+{
+    try {
+        return cut_impl(g, spins, false, cut_weighted, cut_edges, magnetization);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_cut_dev(gdi_graph *g, const int8_t *d_spins, int64_t *cut_weighted, int64_t *cut_edges,
+                int64_t *magnetization)
+{
+    try {
+        return cut_impl(g, d_spins, true, cut_weighted, cut_edges, magnetization);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_get_info(const gdi_graph *g, gdi_graph_info *out)
+{
+    if (!g) return fail(GDI_ESTATE, "NULL handle");
+    if (!out) return fail(GDI_EINVAL, "NULL out");
+    out->n = g->n;
+    out->n_colours = g->C;
+    out->nnz = g->nnz;
+    out->max_abs_wdeg = g->max_abs_wdeg;
+    out->max_degree = g->max_degree;
+    out->pad = 0;
+    return GDI_OK;
+}
+
+int gdi_get_colouring(const gdi_graph *g, int32_t *colour_out, int32_t *class_size_out)
+{
+    if (!g) return fail(GDI_ESTATE, "NULL handle");
+    if (colour_out) std::memcpy(colour_out, g->colour.data(), (size_t)g->n * 4);
+    if (class_size_out) std::memcpy(class_size_out, g->csz.data(), (size_t)g->C * 4);
+    return GDI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,64 @@
+// gdi_internal.h -- structures shared by the host library and the gfx950 kernels.
+//
+// Device layout of one graph (colour-major relabelling, built by gdi_create):
+//   new ids: class c occupies [cbeg[c], cbeg[c] + csz[c]); cbeg[c] is a multiple of
+//            GDI_CLASS_ALIGN, ids in the gaps are padding nodes with empty rows
+//   rp      int32 [n_pad + 1]   row pointers over new ids
+//   adj     int2  [nnz]         {new column id, weight}, interleaved so one 8-byte
+//                               load fetches a whole CSR entry
+//   orig    int32 [n_pad]       original id of each new id (-1 for padding); the
+//                               Philox counter uses the original id
+//   spin    int8  [n_pad]       +1 / -1 (0 for padding)
+#pragma once
+
+#include <stdint.h>
+
+#define GDI_CLASS_ALIGN 64
+#define GDI_MAX_BLOCK 1024
+#define GDI_BAR_GROUPS 8       // workgroups are grouped by blockIdx % 8 for the two-level barrier
+#define GDI_BAR_PAD 16         // uint64 words between group counters (128 bytes)
+
+struct GdiSweepArgs {
+    const int32_t *rp;
+    const int2 *adj;
+    const int32_t *orig;
+    int8_t *spin;
+    const int32_t *cbeg;       // C class starts (device)
+    const int32_t *csz;        // C class sizes (device)
+    const uint32_t *thr;       // S rows of (K+1) thresholds, indexed by absolute sweep
+    int64_t *state;            // [0] M, [1] cut delta accumulator, [2] flips, [3] error flag
+    int32_t *P;                // C counts of +1 spins per class
+    int64_t *trace_m;          // S entries or null
+    int64_t *trace_dcut;       // S entries or null (per-sweep cut change, accumulated by atomics)
+    uint64_t *bar_grp;         // phases * GDI_BAR_GROUPS * GDI_BAR_PAD
+    uint64_t *bar_glob;        // phases * GDI_BAR_PAD
+    int32_t n;                 // real nodes
+    int32_t n_pad;
+    int32_t C;
+    int32_t K;                 // table width: thresholds exist for 1 <= dE <= K
+    uint32_t t0;               // first sweep
+    uint32_t S;                // one past the last sweep
+    int32_t A4;                // 4*A
+    int32_t B;
+    uint32_t key0, key1;       // Philox key
+    uint32_t replica;
+    uint32_t snapshot;         // 1 = SNAPSHOT balance mode
+    int64_t spin_limit;        // bounded waits: polls before giving up
+};
+
+// host-side launchers (gdi_kernels.hip)
+int gdi_launch_init_spins(const int32_t *orig, const int8_t *init_orig, int8_t *spin, int32_t n_pad,
+                          uint32_t key0, uint32_t key1, uint32_t replica, void *stream);
+int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad,
+                      const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P,
+                      void *stream);
+int gdi_launch_fill_u64(uint64_t *p, int64_t count, void *stream);
+int gdi_launch_scatter_out(const int32_t *orig, const int8_t *spin, int32_t n_pad, int8_t *out_orig,
+                           void *stream);
+int gdi_launch_gather_in(const int32_t *orig, const int8_t *in_orig, int32_t n_pad, int8_t *spin,
+                         void *stream);
+int gdi_launch_sweep_wg(const GdiSweepArgs &a, int block, int lanes, int spins_in_lds, void *stream);
+int gdi_launch_sweep_grid(const GdiSweepArgs &a, int grid, int block, int lanes, void *stream);
+int gdi_grid_capacity(int block, int lanes, int *max_grid);
+int gdi_wg_lds_bytes(int32_t n_pad, int32_t C, int spins_in_lds);
+const char *gdi_hip_error_string(int code);

@@ -1,0 +1,536 @@
+// gdi_kernels.hip -- gfx950 kernels of the GDI annealer (wave64, CDNA4).
+//
+// The hot path is one persistent launch per anneal: every sweep visits the
+// colour classes in ascending colour; in each phase the nodes of one class
+// read their CSR rows, gather neighbour spins, form the local field
+// h_i = sum_j w_ij s_j, and make the Metropolis decision of Sec. V Alg. 3
+// (balance term from the tracked magnetisation, eq. 5 / eq. 6 flip cost).
+// The per-phase change of the magnetisation is reduced with wave reductions,
+// an LDS accumulator and (grid scope) a two-level atomic barrier.
+//
+// Two scopes share the same per-node update:
+//   k_sweep_wg   -- one workgroup owns the whole instance; phases are separated
+//                   by s_barrier; spins live in LDS when they fit.
+//   k_sweep_grid -- all co-resident workgroups (cooperative launch) split every
+//                   class into 64-node-aligned chunks; phases are separated by a
+//                   device-wide barrier that also sums the per-workgroup dM.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "gdi_internal.h"
+
+namespace {
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Counter-based generator of Salmon, Moraes, Dror and Shaw (SC'11): ten rounds of
+// two 32x32->64 multiplies (multipliers 0xD2511F53, 0xCD9E8D57) whose high halves
+// are xored into the other counter words together with the key, and a Weyl key
+// schedule (0x9E3779B9, 0xBB67AE85).
+struct Words4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words4 philox10(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                           uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t a_lo = 0xD2511F53u * x0;
+        const uint32_t a_hi = __umulhi(0xD2511F53u, x0);
+        const uint32_t b_lo = 0xCD9E8D57u * x2;
+        const uint32_t b_hi = __umulhi(0xCD9E8D57u, x2);
+        x0 = b_hi ^ x1 ^ k0;
+        x1 = b_lo;
+        x2 = a_hi ^ x3 ^ k1;
+        x3 = a_lo;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {x0, x1, x2, x3};
+}
+
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Magnetisation snapshot of one phase: what every node of the class reads.
+struct PhaseView {
+    int32_t M0;   // magnetisation at the start of the phase
+    int32_t s;    // sign(M0)
+    int32_t D;    // floor(|M0| / 2): flips that would restore balance
+    uint32_t O;   // over-side spins (s_i == s) in the class
+};
+
+__device__ __forceinline__ PhaseView make_view(int32_t M0, int32_t P_c, int32_t size_c, int32_t C,
+                                               int32_t n)
+{
+    PhaseView v;
+    v.M0 = M0;
+    v.s = (M0 > 0) - (M0 < 0);
+    v.D = (M0 < 0 ? -M0 : M0) >> 1;
+    // with a single class P_c is implied by M: (M + n) / 2 spins are +1
+    const int32_t pc = (C == 1) ? (M0 + n) / 2 : P_c;
+    v.O = (uint32_t)(v.s > 0 ? pc : (v.s < 0 ? size_c - pc : 0));
+    return v;
+}
+
+// One node of the current class: L lanes share its CSR row. All L lanes return
+// the same decision; lane 0 of the subgroup performs the write.
+// SpinPtr is an LDS or a global int8 pointer.
+template <int L>
+__device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t *sp, int32_t v,
+                                            int lane, uint32_t t, const PhaseView &pv,
+                                            const uint32_t *thr_row, int32_t *h_out,
+                                            int32_t *sigma_out)
+{
+    const int32_t r0 = a.rp[v];
+    const int32_t r1 = a.rp[v + 1];
+    int32_t h = 0;
+    for (int32_t k = r0 + lane; k < r1; k += L) {
+        const int2 e = a.adj[k];
+        h += e.y * (int32_t)sp[e.x];
+    }
+    if (L > 1) {
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) h += __shfl_xor(h, off, L);
+    }
+    const int32_t sigma = sp[v];
+    const bool need_gate = !a.snapshot && pv.D > 0 && sigma == pv.s;
+    uint32_t x0 = 0, x1 = 0;
+    bool have = false;
+    if (need_gate) {
+        const Words4 r = philox10((uint32_t)a.orig[v], t, a.replica, 0u, a.key0, a.key1);
+        x0 = r.w0;
+        x1 = r.w1;
+        have = true;
+    }
+    int32_t m_seen;
+    if (a.snapshot) {
+        m_seen = pv.M0;
+    } else {
+        const bool gated = need_gate && ((uint64_t)x1 * pv.O < ((uint64_t)(uint32_t)pv.D << 32));
+        m_seen = gated ? pv.M0 : 0;
+    }
+    const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
+    bool flip;
+    if (dE <= 0) {
+        flip = true;
+    } else if (dE > a.K) {
+        flip = false;
+    } else {
+        if (!have) x0 = philox10((uint32_t)a.orig[v], t, a.replica, 0u, a.key0, a.key1).w0;
+        flip = x0 < thr_row[dE];
+    }
+    *h_out = h;
+    *sigma_out = sigma;
+    return flip;
+}
+
+// ------------------------------------------------------------------ workgroup scope
+template <int L, bool SPIN_LDS>
+__global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_wg(GdiSweepArgs a)
+{
+    extern __shared__ int32_t dyn[];
+    __shared__ int32_t acc[3];
+    int32_t *Psh = dyn;
+    const int c_round = (a.C + 3) & ~3;
+    int8_t *sp = SPIN_LDS ? reinterpret_cast<int8_t *>(dyn + c_round) : a.spin;
+
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    for (int i = tid; i < a.C; i += nth) Psh[i] = a.P[i];
+    if (SPIN_LDS)
+        for (int i = tid; i < a.n_pad; i += nth) sp[i] = a.spin[i];
+    if (tid < 3) acc[tid] = 0;
+    int32_t M = (int32_t)a.state[0];
+    __syncthreads();
+
+    const int sub = tid / L, lane = tid % L, nsub = nth / L;
+    int64_t dcut = 0, dcut_total = 0;
+    uint32_t p = 0;
+    for (uint32_t t = a.t0; t < a.S; ++t) {
+        const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)(a.K + 1);
+        for (int32_t c = 0; c < a.C; ++c, ++p) {
+            const int32_t beg = a.cbeg[c];
+            const int32_t size = a.csz[c];
+            const PhaseView pv = make_view(M, Psh[c], size, a.C, a.n);
+            int32_t dM = 0;
+            for (int32_t j = sub; j < size; j += nsub) {
+                const int32_t v = beg + j;
+                int32_t h, sigma;
+                const bool flip = node_decide<L>(a, sp, v, lane, t, pv, thr_row, &h, &sigma);
+                if (flip && lane == 0) {
+                    sp[v] = (int8_t)(-sigma);
+                    dM -= 2 * sigma;
+                    dcut += (int64_t)sigma * h;
+                }
+            }
+            dM = wave_sum_i32(dM);
+            if ((tid & 63) == 0 && dM != 0) atomicAdd(&acc[p % 3], dM);
+            __syncthreads();
+            const int32_t tot = acc[p % 3];
+            M += tot;
+            if (tid == 0) {
+                if (a.C > 1) Psh[c] += tot / 2;
+                acc[(p + 2) % 3] = 0;
+            }
+        }
+        if (a.trace_m) {
+            if (tid == 0) a.trace_m[t] = M;
+            const int64_t w = wave_sum_i64(dcut);
+            if ((tid & 63) == 0 && w != 0) atomicAdd((unsigned long long *)&a.trace_dcut[t], (unsigned long long)w);
+            dcut_total += dcut;
+            dcut = 0;
+        }
+    }
+    dcut_total += dcut;
+    __syncthreads();
+    if (SPIN_LDS)
+        for (int i = tid; i < a.n_pad; i += nth) a.spin[i] = sp[i];
+    for (int i = tid; i < a.C; i += nth) a.P[i] = Psh[i];
+    if (tid == 0) a.state[0] = M;
+    const int64_t w = wave_sum_i64(dcut_total);
+    if ((tid & 63) == 0 && w != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)w);
+}
+
+// ------------------------------------------------------------------ grid scope
+// Two-level barrier that also sums the per-workgroup dM of phase p.
+// Level 1: workgroups of group x = blockIdx % 8 add (2^40 + dM) to their group
+// word; the last arriver (count == group size) adds (2^40 + group sum) to the
+// phase's global word. Everyone polls the global word until it holds all
+// groups. Counts live above bit 40, sums below (|sum| < 2^39).
+__device__ __forceinline__ bool grid_phase_sync(const GdiSweepArgs &a, uint32_t p, int32_t d,
+                                                uint32_t x, uint32_t gsz, uint32_t ngroups,
+                                                int32_t *tot)
+{
+    const uint64_t one = 1ull << 40, half = 1ull << 39;
+    uint64_t *gw = a.bar_grp + ((size_t)p * GDI_BAR_GROUPS + x) * GDI_BAR_PAD;
+    uint64_t *glw = a.bar_glob + (size_t)p * GDI_BAR_PAD;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const uint64_t add = one + (uint64_t)(int64_t)d;
+    const uint64_t now = __hip_atomic_fetch_add(gw, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + add;
+    const uint64_t cnt = (now + half) >> 40;
+    if (cnt == gsz) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+        const uint64_t gsum = now - (cnt << 40);
+        __hip_atomic_fetch_add(glw, one + gsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    for (int64_t tries = 0;; ++tries) {
+        const uint64_t v = __hip_atomic_load(glw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t c2 = (v + half) >> 40;
+        if (c2 >= ngroups) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            *tot = (int32_t)(int64_t)(v - (c2 << 40));
+            return true;
+        }
+        if (tries >= a.spin_limit) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+template <int L>
+__global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_grid(GdiSweepArgs a)
+{
+    extern __shared__ int32_t Psh[];
+    __shared__ int32_t wg_acc;
+    __shared__ int32_t total;
+    __shared__ int32_t abort_flag;
+
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    // XCD-aware chunk order: consecutive workgroup ids land on different XCDs,
+    // so give each XCD (b % 8) a contiguous range of chunks.
+    const uint32_t q = (G % 8u == 0u) ? (b % 8u) * (G / 8u) + b / 8u : b;
+    const uint32_t ngroups = G < GDI_BAR_GROUPS ? G : GDI_BAR_GROUPS;
+    const uint32_t x = b % ngroups;
+    const uint32_t gsz = G / ngroups + (x < G % ngroups ? 1u : 0u);
+
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    for (int i = tid; i < a.C; i += nth) Psh[i] = a.P[i];
+    if (tid == 0) {
+        wg_acc = 0;
+        abort_flag = 0;
+    }
+    int32_t M = (int32_t)a.state[0];
+    __syncthreads();
+
+    const int sub = tid / L, lane = tid % L, nsub = nth / L;
+    int64_t dcut = 0, dcut_total = 0;
+    uint32_t p = 0;
+    for (uint32_t t = a.t0; t < a.S; ++t) {
+        const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)(a.K + 1);
+        for (int32_t c = 0; c < a.C; ++c, ++p) {
+            const int32_t beg = a.cbeg[c];
+            const int32_t size = a.csz[c];
+            const PhaseView pv = make_view(M, Psh[c], size, a.C, a.n);
+            int32_t chunk = (size + (int32_t)G - 1) / (int32_t)G;
+            chunk = (chunk + GDI_CLASS_ALIGN - 1) & ~(GDI_CLASS_ALIGN - 1);
+            const int32_t lo = (int32_t)q * chunk;
+            const int32_t hi = min(size, lo + chunk);
+            int32_t dM = 0;
+            for (int32_t j = lo + sub; j < hi; j += nsub) {
+                const int32_t v = beg + j;
+                int32_t h, sigma;
+                const bool flip = node_decide<L>(a, a.spin, v, lane, t, pv, thr_row, &h, &sigma);
+                if (flip && lane == 0) {
+                    a.spin[v] = (int8_t)(-sigma);
+                    dM -= 2 * sigma;
+                    dcut += (int64_t)sigma * h;
+                }
+            }
+            dM = wave_sum_i32(dM);
+            if ((tid & 63) == 0 && dM != 0) atomicAdd(&wg_acc, dM);
+            __syncthreads();
+            if (tid == 0) {
+                const int32_t d = wg_acc;
+                wg_acc = 0;
+                int32_t tot = 0;
+                if (!grid_phase_sync(a, p, d, x, gsz, ngroups, &tot)) {
+                    abort_flag = 1;
+                    __hip_atomic_store(&a.state[3], (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                total = tot;
+            }
+            __syncthreads();
+            if (abort_flag) return;
+            const int32_t tot = total;
+            M += tot;
+            if (tid == 0 && a.C > 1) Psh[c] += tot / 2;
+        }
+        if (a.trace_m) {
+            if (b == 0 && tid == 0) a.trace_m[t] = M;
+            const int64_t w = wave_sum_i64(dcut);
+            if ((tid & 63) == 0 && w != 0) atomicAdd((unsigned long long *)&a.trace_dcut[t], (unsigned long long)w);
+            dcut_total += dcut;
+            dcut = 0;
+        }
+    }
+    dcut_total += dcut;
+    __syncthreads();
+    if (b == 0) {
+        for (int i = tid; i < a.C; i += nth) a.P[i] = Psh[i];
+        if (tid == 0) a.state[0] = M;
+    }
+    const int64_t w = wave_sum_i64(dcut_total);
+    if ((tid & 63) == 0 && w != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)w);
+}
+
+// ------------------------------------------------------------------ helpers
+__global__ void k_init_spins(const int32_t *orig, const int8_t *init_orig, int8_t *spin, int32_t n_pad,
+                             uint32_t key0, uint32_t key1, uint32_t replica)
+{
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_pad) return;
+    const int32_t o = orig[v];
+    int8_t s = 0;
+    if (o >= 0) {
+        if (init_orig) {
+            s = init_orig[o] > 0 ? 1 : -1;
+        } else {
+            const Words4 r = philox10((uint32_t)o, 0u, replica, 1u, key0, key1);
+            s = (r.w0 & 1u) ? 1 : -1;
+        }
+    }
+    spin[v] = s;
+}
+
+__global__ void k_gather_in(const int32_t *orig, const int8_t *in_orig, int32_t n_pad, int8_t *spin)
+{
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_pad) return;
+    const int32_t o = orig[v];
+    spin[v] = o >= 0 ? (in_orig[o] > 0 ? 1 : -1) : 0;
+}
+
+__global__ void k_scatter_out(const int32_t *orig, const int8_t *spin, int32_t n_pad, int8_t *out_orig)
+{
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_pad) return;
+    const int32_t o = orig[v];
+    if (o >= 0) out_orig[o] = spin[v];
+}
+
+__global__ void k_fill_u64(uint64_t *p, int64_t count)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t st = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < count; k += st) p[k] = 0;
+}
+
+// From-scratch M, doubled weighted cut, doubled crossing count and per-class +1 counts.
+__global__ void k_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad,
+                         const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P)
+{
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t m = 0, cw = 0, ce = 0;
+    if (v < n_pad) {
+        const int32_t s = spin[v];
+        if (s != 0) {
+            m = s;
+            for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
+                const int2 e = adj[k];
+                if (spin[e.x] != s) {
+                    cw += e.y;
+                    ce += 1;
+                }
+            }
+            if (s > 0) {
+                int32_t lo = 0, hi = C - 1;  // class of v: last c with cbeg[c] <= v
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (cbeg[mid] <= v) lo = mid; else hi = mid - 1;
+                }
+                if (v < cbeg[lo] + csz[lo]) atomicAdd(&P[lo], 1);
+            }
+        }
+    }
+    m = wave_sum_i64(m);
+    cw = wave_sum_i64(cw);
+    ce = wave_sum_i64(ce);
+    if ((threadIdx.x & 63) == 0) {
+        if (m) atomicAdd((unsigned long long *)&out3[0], (unsigned long long)m);
+        if (cw) atomicAdd((unsigned long long *)&out3[1], (unsigned long long)cw);
+        if (ce) atomicAdd((unsigned long long *)&out3[2], (unsigned long long)ce);
+    }
+}
+
+inline int status(hipError_t e) { return (int)e; }
+
+template <int L>
+const void *wg_kernel(bool lds)
+{
+    return lds ? (const void *)k_sweep_wg<L, true> : (const void *)k_sweep_wg<L, false>;
+}
+
+const void *pick_wg(int lanes, bool lds)
+{
+    switch (lanes) {
+    case 1: return wg_kernel<1>(lds);
+    case 2: return wg_kernel<2>(lds);
+    case 4: return wg_kernel<4>(lds);
+    case 8: return wg_kernel<8>(lds);
+    case 16: return wg_kernel<16>(lds);
+    case 32: return wg_kernel<32>(lds);
+    case 64: return wg_kernel<64>(lds);
+    default: return nullptr;
+    }
+}
+
+const void *pick_grid(int lanes)
+{
+    switch (lanes) {
+    case 1: return (const void *)k_sweep_grid<1>;
+    case 2: return (const void *)k_sweep_grid<2>;
+    case 4: return (const void *)k_sweep_grid<4>;
+    case 8: return (const void *)k_sweep_grid<8>;
+    case 16: return (const void *)k_sweep_grid<16>;
+    case 32: return (const void *)k_sweep_grid<32>;
+    case 64: return (const void *)k_sweep_grid<64>;
+    default: return nullptr;
+    }
+}
+
+inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+int gdi_launch_init_spins(const int32_t *orig, const int8_t *init_orig, int8_t *spin, int32_t n_pad,
+                          uint32_t key0, uint32_t key1, uint32_t replica, void *stream)
+{
+    hipLaunchKernelGGL(k_init_spins, dim3(blocks_for(n_pad, 256)), dim3(256), 0, (hipStream_t)stream,
+                       orig, init_orig, spin, n_pad, key0, key1, replica);
+    return status(hipGetLastError());
+}
+
+int gdi_launch_gather_in(const int32_t *orig, const int8_t *in_orig, int32_t n_pad, int8_t *spin,
+                         void *stream)
+{
+    hipLaunchKernelGGL(k_gather_in, dim3(blocks_for(n_pad, 256)), dim3(256), 0, (hipStream_t)stream,
+                       orig, in_orig, n_pad, spin);
+    return status(hipGetLastError());
+}
+
+int gdi_launch_scatter_out(const int32_t *orig, const int8_t *spin, int32_t n_pad, int8_t *out_orig,
+                           void *stream)
+{
+    hipLaunchKernelGGL(k_scatter_out, dim3(blocks_for(n_pad, 256)), dim3(256), 0, (hipStream_t)stream,
+                       orig, spin, n_pad, out_orig);
+    return status(hipGetLastError());
+}
+
+int gdi_launch_fill_u64(uint64_t *p, int64_t count, void *stream)
+{
+    if (count <= 0) return 0;
+    const unsigned g = (unsigned)std::min<int64_t>(blocks_for(count, 256), 4096);
+    hipLaunchKernelGGL(k_fill_u64, dim3(g), dim3(256), 0, (hipStream_t)stream, p, count);
+    return status(hipGetLastError());
+}
+
+int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad,
+                      const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P,
+                      void *stream)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(n_pad, 256)), dim3(256), 0, (hipStream_t)stream, rp, adj,
+                       spin, n_pad, cbeg, csz, C, out3, P);
+    return status(hipGetLastError());
+}
+
+int gdi_wg_lds_bytes(int32_t n_pad, int32_t C, int spins_in_lds)
+{
+    const int c_round = (C + 3) & ~3;
+    return c_round * 4 + (spins_in_lds ? n_pad : 0);
+}
+
+int gdi_launch_sweep_wg(const GdiSweepArgs &a, int block, int lanes, int spins_in_lds, void *stream)
+{
+    const void *f = pick_wg(lanes, spins_in_lds != 0);
+    if (!f) return (int)hipErrorInvalidValue;
+    const int lds = gdi_wg_lds_bytes(a.n_pad, a.C, spins_in_lds);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return status(e);
+    GdiSweepArgs copy = a;
+    void *args[] = {&copy};
+    e = hipLaunchKernel(f, dim3(1), dim3(block), args, (size_t)lds, (hipStream_t)stream);
+    return status(e);
+}
+
+int gdi_grid_capacity(int block, int lanes, int *max_grid)
+{
+    const void *f = pick_grid(lanes);
+    if (!f) return (int)hipErrorInvalidValue;
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, block, 256);
+    if (e != hipSuccess) return status(e);
+    *max_grid = cus * per_cu;
+    return 0;
+}
+
+int gdi_launch_sweep_grid(const GdiSweepArgs &a, int grid, int block, int lanes, void *stream)
+{
+    const void *f = pick_grid(lanes);
+    if (!f) return (int)hipErrorInvalidValue;
+    const int lds = ((a.C + 3) & ~3) * 4;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return status(e);
+    GdiSweepArgs copy = a;
+    void *args[] = {&copy};
+    e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(block), args, (unsigned)lds, (hipStream_t)stream);
+    return status(e);
+}
+
+const char *gdi_hip_error_string(int code) { return hipGetErrorString((hipError_t)code); }
