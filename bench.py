@@ -1,0 +1,148 @@
+#!/usr/bin/env python3
+"""Benchmark of the GDI annealing path on one MI355X.
+
+One step = one full anneal of the workload (all sweeps of the schedule, every
+colour phase, in one persistent launch, plus the initial-state and output
+kernels) on synthetic input already resident in HBM. Prints one JSON line.
+
+Default workload: random geometric graph, n = 1,000,000 points in the unit
+square, mean degree 8, unit int32 weights, 2000 sweeps with geometric T from
+3.0 to 0.05, A = B = 1.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "spin-updates/s + HBM GB/s; cut @ fixed wall time: plain vs batched/learned"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_sweep(n: int, nnz: int) -> int:
+    """row_ptr (4(n+1)) + CSR column and weight (8 nnz) + spin read and write (2n)."""
+    return 4 * (n + 1) + 8 * nnz + 2 * n
+
+
+def cpu_baseline(g, temps, seed, sweeps):
+    import oracle
+
+    t0 = time.perf_counter()
+    oracle.anneal(g, temps[:sweeps], seed)
+    dt = time.perf_counter() - t0
+    return {"value": g.n * sweeps / dt, "unit": "spin-updates/s", "cores": oracle.max_threads(),
+            "kind": "oracle",
+            "sample": f"first {sweeps} of the {temps.size} sweeps of the same workload "
+                      f"(n={g.n}), C oracle with OpenMP, {dt:.2f} s wall incl. colouring"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rgg1m")
+    ap.add_argument("--sweeps", type=int, default=0, help="override the schedule length")
+    ap.add_argument("--cpu-sweeps", type=int, default=2000)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: --gpus {args.gpus} is not supported "
+              "(every instance fits one MI355X; see DESIGN.md for how the path would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import gdi_synth as gs
+    import paper_1908_00210_amd as gdi
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    spec = gs.WORKLOADS[args.workload]
+    g = spec["graph"]()
+    S = args.sweeps or spec["sweeps"]
+    temps = gs.geometric_temps(spec["t0"], spec["t1"], S)
+    seed = 1
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    out = torch.empty(g.n, dtype=torch.int8, device=dev)
+
+    t0 = time.perf_counter()
+    ann = gdi.Annealer(g)
+    create_s = time.perf_counter() - t0
+    ann.set_stream(stream.cuda_stream)
+    for _ in range(args.warmup):
+        ann.anneal_dev(temps, seed, out.data_ptr())
+        ann.result()
+    torch.cuda.synchronize()
+    sweep_ms = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ann.anneal_dev(temps, seed, out.data_ptr())
+        # device time of this step's sweep launch (HIP events on the same stream)
+        sweep_ms.append(ann.result().sweep_ms)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    res = ann.result()
+    cw, ce, m = ann.cut_dev(out.data_ptr())
+    info = ann.info
+
+    n, nnz = g.n, g.nnz
+    updates = n * S
+    value = updates * args.steps / elapsed
+    kern_s = float(np.mean(sweep_ms)) / 1e3
+    bytes_launch = algorithmic_bytes_per_sweep(n, nnz) * S
+    achieved = bytes_launch / kern_s / 1e9
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+        if tj.get("workload") == args.workload and tj.get("sweeps") == S:
+            traffic = tj.get("hbm_bytes_per_launch")
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "spin-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload, "graph": g.name, "n": n, "nnz": nnz, "sweeps": S,
+            "t0": spec["t0"], "t1": spec["t1"], "A": 1, "B": 1, "colours": int(info.n_colours),
+            "scope": int(res.scope), "grid": int(res.grid), "block": int(res.block),
+            "lanes_per_node": int(res.lanes_per_node), "parallelism": "single-gpu",
+        },
+        "sweeps_per_s": S * args.steps / elapsed,
+        "hbm_gbs": achieved,
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "kernel": "k_sweep_grid" if res.scope == gdi.SCOPE_GRID else "k_sweep_wg",
+            "kernel_ms": kern_s * 1e3, "bytes_per_launch": bytes_launch,
+        },
+        "result": {"M": int(m), "cut_weighted": int(cw), "cut_edges": int(ce),
+                   "tracked_cut": int(res.cut_weighted), "create_s": create_s},
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(g, temps, seed, min(args.cpu_sweeps, S))
+    ann.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -54,7 +54,7 @@ class Schedule(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("scope", ctypes.c_uint32), ("block", ctypes.c_uint32), ("grid", ctypes.c_uint32),
-                ("lanes_per_node", ctypes.c_uint32)]
+                ("lanes_per_node", ctypes.c_uint32), ("pad", ctypes.c_uint32), ("spin_limit", ctypes.c_uint64)]
 
 
 class Result(ctypes.Structure):
@@ -151,11 +151,12 @@ def set_stream(h, stream_ptr: int | None):
     _check(lib().gdi_set_stream(h, stream_ptr))
 
 
-def set_tuning(h, scope: int = 0, block: int = 0, grid: int = 0, lanes_per_node: int = 0, reset=False):
+def set_tuning(h, scope: int = 0, block: int = 0, grid: int = 0, lanes_per_node: int = 0,
+               spin_limit: int = 0, reset=False):
     if reset:
         _check(lib().gdi_set_tuning(h, None))
         return
-    t = Tuning(scope, block, grid, lanes_per_node)
+    t = Tuning(scope, block, grid, lanes_per_node, 0, spin_limit)
     _check(lib().gdi_set_tuning(h, ctypes.byref(t)))
 
 
@@ -283,6 +284,9 @@ class Annealer:
 
     def cut(self, spins):
         return cut(self.h, spins)
+
+    def cut_dev(self, d_spins: int):
+        return cut_dev(self.h, d_spins)
 
     def result(self) -> Result:
         return last_result(self.h)

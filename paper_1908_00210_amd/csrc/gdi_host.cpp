@@ -457,7 +457,7 @@ int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host
     a.key1 = (uint32_t)(seed >> 32);
     a.replica = s->replica;
     a.snapshot = s->balance_mode == GDI_BAL_SNAPSHOT ? 1u : 0u;
-    a.spin_limit = kSpinLimit;
+    a.spin_limit = (g->have_tune && g->tune.spin_limit) ? (int64_t)g->tune.spin_limit : kSpinLimit;
 
     HIP_TRY(hipEventRecord(g->ev0, st), "hipEventRecord");
     if (ch.scope == GDI_SCOPE_WORKGROUP)

@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit for bit.
+
+All arithmetic of the path is integer, so spins, magnetisation, tracked cut and
+the per-sweep traces must be identical to the oracle's for every workload,
+launch shape and balance mode.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import gdi_synth as gs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gdi():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1908_00210_amd as gdi
+
+    gdi.lib()
+    return gdi
+
+
+def run_both(gdi, oracle_lib, g, T, seed=1, mode=0, tune=None, trace=True, replica=0, A=1, B=1,
+             start_sweep=0, init=None, label=""):
+    print(f"[case] {label} n={g.n} nnz={g.nnz} S={T.size} mode={mode} tune={tune} seed={seed}",
+          flush=True)
+    ref = oracle_lib.anneal(g, T, seed, A=A, B=B, mode=mode, trace=trace, replica=replica,
+                            start_sweep=start_sweep, init=init)
+    with gdi.Annealer(g) as a:
+        if tune:
+            a.tune(**tune)
+        r = a.anneal(T, seed, mode=mode, trace=trace, replica=replica, A=A, B=B,
+                     start_sweep=start_sweep, init=init)
+        cw, ce, m = a.cut(r["spins"])
+    return ref, r, (cw, ce, m)
+
+
+def assert_same(ref, r, trace=True, t0=0):
+    assert np.array_equal(r["spins"], ref["spins"])
+    assert r["M"] == ref["M"]
+    assert r["cut"] == ref["cut"]
+    if trace:
+        assert np.array_equal(r["trace_m"][t0:], ref["trace_m"][t0:])
+        assert np.array_equal(r["trace_cut"][t0:], ref["trace_cut"][t0:])
+
+
+SMALL = {
+    "er301_pm1": lambda: gs.er_graph(301, 0.05, 7, "pm1"),
+    "rgg2500": lambda: gs.rgg_graph(2500, 8.0, 8, "unit"),
+    "torus13": lambda: gs.torus_graph(13, 9, "pm1"),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("scope", [1, 2])
+def test_small_graphs(gdi, oracle_lib, name, mode, scope):
+    g = SMALL[name]()
+    T = gs.geometric_temps(2.5, 0.05, 40)
+    ref, r, (cw, ce, m) = run_both(gdi, oracle_lib, g, T, seed=11, mode=mode, tune=dict(scope=scope),
+                                   label=name)
+    assert_same(ref, r)
+    assert (cw, m) == (ref["cut"], ref["M"])
+    assert ce == oracle_lib.cut(g, ref["spins"])[1]
+
+
+@pytest.mark.parametrize("tune", [
+    dict(scope=1, lanes_per_node=1, block=64),
+    dict(scope=1, lanes_per_node=4, block=256),
+    dict(scope=1, lanes_per_node=64, block=1024),
+    dict(scope=2, lanes_per_node=1, block=64, grid=1),
+    dict(scope=2, lanes_per_node=2, block=128, grid=7),
+    dict(scope=2, lanes_per_node=16, block=512, grid=64),
+    dict(scope=2, lanes_per_node=8, block=1024, grid=256),
+    dict(scope=2, lanes_per_node=32, block=256, grid=300),
+])
+def test_launch_shape_invariance(gdi, oracle_lib, tune):
+    """Same trajectory for every scope, block, grid and lanes-per-node choice (ragged tails)."""
+    g = gs.rgg_graph(7777, 10.0, 12, "pm1")
+    T = gs.geometric_temps(3.0, 0.05, 30)
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, seed=5, tune=tune, label="shape")
+    assert_same(ref, r)
+
+
+def test_er800_full_schedule(gdi, oracle_lib):
+    g, T = gs.workload("er800")
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, label="er800")
+    assert_same(ref, r)
+
+
+def test_torus100_full_schedule(gdi, oracle_lib):
+    g, T = gs.workload("torus100")
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, label="torus100")
+    assert_same(ref, r)
+    assert r["M"] == 0
+
+
+def test_rgg1m_full_schedule_bench_launch(gdi, oracle_lib):
+    """The benchmark workload and launch configuration, all 2000 sweeps, traces included."""
+    g, T = gs.workload("rgg1m")
+    t = time.time()
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, label="rgg1m")
+    print(f"rgg1m: both sides in {time.time() - t:.1f}s, GPU sweep {r['result']['sweep_ms']:.1f} ms",
+          flush=True)
+    assert r["result"]["scope"] == gdi.SCOPE_GRID
+    assert_same(ref, r)
+
+
+def test_odd_n_negative_weights_and_coefficients(gdi, oracle_lib):
+    g = gs.er_graph(999, 0.01, 13, "pm1")
+    T = gs.geometric_temps(4.0, 0.1, 50)
+    for A, B in ((3, 2), (0, 1), (1, 0), (2, -1)):
+        ref, r, _ = run_both(gdi, oracle_lib, g, T, A=A, B=B, label=f"A{A}B{B}")
+        assert_same(ref, r)
+
+
+def test_degenerate_graphs(gdi, oracle_lib):
+    T = gs.geometric_temps(2.0, 0.05, 20)
+    # two nodes, one edge
+    g = gs.from_edges(2, [0], [1], [1])
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, label="k2")
+    assert_same(ref, r)
+    # no edges at all: one colour class
+    g = gs.Graph(n=65, row_ptr=np.zeros(66, np.int32), col=np.zeros(0, np.int32),
+                 w=np.zeros(0, np.int32), name="empty")
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, label="no-edges")
+    assert_same(ref, r)
+    # a star: one row of 4000 entries, 4000 rows of one entry; isolated nodes too
+    a = np.zeros(4000, np.int64); b = np.arange(1, 4001)
+    g = gs.from_edges(4100, a, b, np.ones(4000, np.int64))
+    for scope in (1, 2):
+        ref, r, _ = run_both(gdi, oracle_lib, g, T, tune=dict(scope=scope), label="star")
+        assert_same(ref, r)
+
+
+def test_single_sweep_and_empty_resume(gdi, oracle_lib):
+    g = gs.rgg_graph(3000, 8.0, 14)
+    T = gs.geometric_temps(2.0, 0.05, 1)
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, label="S=1")
+    assert_same(ref, r)
+    # start_sweep == S: nothing runs, the initial state comes back
+    init = np.where(np.arange(g.n) % 3 == 0, 1, -1).astype(np.int8)
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, start_sweep=1, init=init, trace=False, label="S=0")
+    assert np.array_equal(r["spins"], init) and np.array_equal(ref["spins"], init)
+
+
+def test_infinite_temperature_alternation(gdi, oracle_lib):
+    g = gs.er_graph(400, 0.03, 15, "pm1")
+    T = np.full(9, 1e300)
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, label="T=inf")
+    assert_same(ref, r)
+
+
+def test_resume_on_gpu(gdi, oracle_lib):
+    g = gs.rgg_graph(150_000, 8.0, 16)
+    T = gs.geometric_temps(3.0, 0.05, 120)
+    with gdi.Annealer(g) as a:
+        full = a.anneal(T, 21, trace=True)
+        head = a.anneal(T[:50], 21)
+        tail = a.anneal(T, 21, start_sweep=50, init=head["spins"], trace=True)
+    assert np.array_equal(full["spins"], tail["spins"])
+    assert np.array_equal(full["trace_cut"][50:], tail["trace_cut"][50:])
+    ref = oracle_lib.anneal(g, T, 21)
+    assert np.array_equal(full["spins"], ref["spins"])
+
+
+def test_replicas_and_repeat_determinism(gdi, oracle_lib):
+    g = gs.er_graph(2000, 0.01, 17)
+    T = gs.geometric_temps(2.0, 0.05, 60)
+    with gdi.Annealer(g) as a:
+        outs = [a.anneal(T, 3, replica=rep) for rep in (0, 1, 255, 1)]
+    assert np.array_equal(outs[1]["spins"], outs[3]["spins"])
+    assert not np.array_equal(outs[0]["spins"], outs[1]["spins"])
+    for rep, o in zip((0, 1, 255), outs[:3]):
+        ref = oracle_lib.anneal(g, T, 3, replica=rep)
+        assert np.array_equal(o["spins"], ref["spins"])
+
+
+def test_device_pointer_path(gdi, oracle_lib):
+    """gdi_anneal_dev / gdi_cut_dev on torch device memory and torch's stream."""
+    import torch
+
+    g = gs.rgg_graph(90_000, 8.0, 18, "pm1")
+    T = gs.geometric_temps(3.0, 0.05, 80)
+    ref = oracle_lib.anneal(g, T, 8)
+    out = torch.full((g.n,), 7, dtype=torch.int8, device="cuda:0")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s), gdi.Annealer(g) as a:
+        a.set_stream(s.cuda_stream)
+        a.anneal_dev(T, 8, out.data_ptr())
+        res = a.result()
+        cw, ce, m = a.cut_dev(out.data_ptr())
+    s.synchronize()
+    assert np.array_equal(out.cpu().numpy(), ref["spins"])
+    assert (res.magnetization, res.cut_weighted) == (ref["M"], ref["cut"])
+    assert (cw, m) == (ref["cut"], ref["M"])
+
+
+def test_forced_barrier_timeout_reports_error_and_recovers(gdi, oracle_lib):
+    """A host-set tiny spin limit makes the bounded barrier waits give up: GDI_ETIMEOUT, no hang."""
+    g = gs.rgg_graph(20_000, 8.0, 19)
+    T = gs.geometric_temps(3.0, 0.05, 20)
+    with gdi.Annealer(g) as a:
+        a.tune(scope=2, grid=256, spin_limit=1)
+        with pytest.raises(gdi.GdiError) as e:
+            a.anneal(T, 1)
+        assert e.value.code == gdi.ETIMEOUT
+        a.tune(reset=True)
+        a.tune(scope=2)
+        r = a.anneal(T, 1)
+    assert np.array_equal(r["spins"], oracle_lib.anneal(g, T, 1)["spins"])
+
+
+def test_bad_schedule_is_rejected(gdi):
+    g = gs.er_graph(100, 0.05, 20)
+    with gdi.Annealer(g) as a:
+        for T in (np.array([1.0, 0.0]), np.array([np.nan]), np.array([-1.0])):
+            with pytest.raises(gdi.GdiError) as e:
+                a.anneal(T, 1)
+            assert e.value.code == gdi.EINVAL
+        with pytest.raises(gdi.GdiError) as e:
+            a.anneal(np.ones(3), 1, mode=7)
+        assert e.value.code == gdi.EINVAL
+        with pytest.raises(gdi.GdiError) as e:
+            a.anneal(np.ones(3), 1, A=2**28)
+        assert e.value.code == gdi.ERANGE
+        r = a.anneal(np.ones(3), 1)  # still usable
+        assert r["spins"].shape == (g.n,)
