@@ -114,10 +114,15 @@ def main():
     achieved = bytes_launch / kern_s / 1e9
     traffic = None
     if os.path.exists(args.traffic_json):
+        # counters only stand for the kernel source they were taken on
+        import hashlib
+
         with open(args.traffic_json) as f:
             tj = json.load(f)
-        if tj.get("workload") == args.workload and tj.get("sweeps") == S:
-            traffic = tj.get("hbm_bytes_per_launch")
+        with open(os.path.join(ROOT, "paper_1908_00210_amd", "csrc", "gdi_kernels.hip"), "rb") as f:
+            src = hashlib.sha256(f.read()).hexdigest()[:16]
+        if tj.get("workload") == args.workload and tj.get("kernel_source_sha256_16") == src:
+            traffic = tj["hbm_bytes_per_sweep"] * S
     line = {
         "metric": METRIC,
         "value": value,
