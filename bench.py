@@ -147,7 +147,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_sweep_grid" if res.scope == gdi.SCOPE_GRID else "k_sweep_wg",
+            "kernel": {gdi.SCOPE_GRID: "k_sweep_halo", gdi.SCOPE_GRID_FENCED: "k_sweep_grid"}.get(res.scope, "k_sweep_wg"),
             "kernel_ms": kern_s * 1e3, "bytes_per_launch": bytes_launch,
         },
         "result": {"M": int(m), "cut_weighted": int(cw), "cut_edges": int(ce),

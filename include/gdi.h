@@ -69,7 +69,10 @@ extern "C" {
 /* Scope of the persistent sweep launch. */
 #define GDI_SCOPE_AUTO 0u
 #define GDI_SCOPE_WORKGROUP 1u /* whole instance inside one workgroup */
-#define GDI_SCOPE_GRID 2u      /* instance spread over the whole device */
+#define GDI_SCOPE_GRID 2u      /* instance spread over the whole device; spins exchanged through
+                                  per-workgroup LDS windows, no cache-wide fences */
+#define GDI_SCOPE_GRID_FENCED 3u /* whole device, spins gathered from global memory with
+                                    release/acquire fences per phase (any graph) */
 
 typedef struct gdi_graph gdi_graph;
 

@@ -17,7 +17,7 @@ import numpy as np
 
 __all__ = [
     "GdiError", "lib", "LIB_PATH", "BAL_GATED", "BAL_SNAPSHOT", "SCOPE_AUTO", "SCOPE_WORKGROUP",
-    "SCOPE_GRID", "Schedule", "Tuning", "Result", "GraphInfo", "create", "destroy", "anneal",
+    "SCOPE_GRID", "SCOPE_GRID_FENCED", "Schedule", "Tuning", "Result", "GraphInfo", "create", "destroy", "anneal",
     "anneal_dev", "cut", "cut_dev", "last_result", "set_stream", "set_tuning", "get_info",
     "get_colouring", "colour_csr", "threshold_table", "philox4x32_10", "version", "Annealer",
 ]
@@ -28,7 +28,7 @@ OK, EINVAL, ERANGE, ENOMEM, EDEVICE, ESTATE, ETIMEOUT = 0, -1, -2, -3, -4, -5, -
 _NAMES = {EINVAL: "GDI_EINVAL", ERANGE: "GDI_ERANGE", ENOMEM: "GDI_ENOMEM", EDEVICE: "GDI_EDEVICE",
           ESTATE: "GDI_ESTATE", ETIMEOUT: "GDI_ETIMEOUT"}
 BAL_GATED, BAL_SNAPSHOT = 0, 1
-SCOPE_AUTO, SCOPE_WORKGROUP, SCOPE_GRID = 0, 1, 2
+SCOPE_AUTO, SCOPE_WORKGROUP, SCOPE_GRID, SCOPE_GRID_FENCED = 0, 1, 2, 3
 
 
 class GdiError(RuntimeError):

@@ -76,6 +76,16 @@ struct gdi_graph {
     std::vector<int32_t> colour;      // original order
     std::vector<int32_t> cbeg, csz;   // per class, new ids
     std::vector<int32_t> orig;        // new -> original (-1 padding)
+    std::vector<int32_t> h_rp;        // new-id CSR kept on the host for launch layouts
+    std::vector<int2> h_adj;
+    std::vector<int32_t> cls;         // class of each new id (-1 padding)
+
+    // halo layout for one grid size (k_sweep_halo)
+    int32_t halo_G = 0;
+    int32_t halo_lds_words = -1;      // -1: not built; -2: does not fit LDS
+    DevBuf<int2> d_adjL;
+    DevBuf<GdiHaloEntry> d_tab;
+    DevBuf<uint64_t> d_words, d_member, d_group;
 
     DevBuf<int32_t> d_rp, d_orig, d_cbeg, d_csz, d_P;
     DevBuf<int2> d_adj;
@@ -104,6 +114,7 @@ struct gdi_graph {
         d_rp.release(); d_orig.release(); d_cbeg.release(); d_csz.release(); d_P.release();
         d_adj.release(); d_spin.release(); d_io.release(); d_state.release(); d_red.release();
         d_trace.release(); d_thr.release(); d_bar.release();
+        d_adjL.release(); d_tab.release(); d_words.release(); d_member.release(); d_group.release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
     }
@@ -201,6 +212,8 @@ int lanes_for_degree(double avg_deg)
 const int64_t kSpinLimit = int64_t(1) << 22;
 const int32_t kWgMaxNodes = 65536;
 
+int build_halo(gdi_graph *g, int32_t G, int lds_budget);
+
 int pick_launch(gdi_graph *g, Choice *ch)
 {
     const gdi_tuning t = g->have_tune ? g->tune : gdi_tuning{};
@@ -212,32 +225,53 @@ int pick_launch(gdi_graph *g, Choice *ch)
     if (ch->block < 64 || ch->block > GDI_MAX_BLOCK || ch->block % 64 || ch->block < ch->lanes)
         return fail(GDI_EINVAL, "block must be a multiple of 64 in [64, 1024]");
     ch->scope = t.scope ? t.scope : (g->n_pad <= kWgMaxNodes ? GDI_SCOPE_WORKGROUP : GDI_SCOPE_GRID);
-    if (ch->scope != GDI_SCOPE_WORKGROUP && ch->scope != GDI_SCOPE_GRID)
+    if (ch->scope < GDI_SCOPE_WORKGROUP || ch->scope > GDI_SCOPE_GRID_FENCED)
         return fail(GDI_EINVAL, "unknown scope");
     ch->grid = 1;
     ch->spins_lds = false;
+    int dev = 0, lds_max = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
     if (ch->scope == GDI_SCOPE_WORKGROUP) {
-        int dev = 0, lds_max = 0;
-        HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-        HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
-                "hipDeviceGetAttribute");
         ch->spins_lds = gdi_wg_lds_bytes(g->n_pad, g->C, 1) + 64 <= lds_max;
         if (gdi_wg_lds_bytes(g->n_pad, g->C, 0) + 64 > lds_max)
             return fail(GDI_ERANGE, "too many colour classes for one workgroup's LDS");
-    } else {
-        int cap = 0;
-        int e = gdi_grid_capacity((int)ch->block, (int)ch->lanes, &cap);
-        if (e) return fail(GDI_EDEVICE, std::string("occupancy query: ") + gdi_hip_error_string(e));
-        int dev = 0, cus = 0;
-        HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-        HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
-        uint32_t want = t.grid ? t.grid : (uint32_t)std::min(cap, cus);
-        if (want < 1 || (int)want > cap)
-            return fail(GDI_EDEVICE, "grid of " + std::to_string(want) +
-                                         " workgroups cannot be co-resident (capacity " +
-                                         std::to_string(cap) + ")");
-        ch->grid = want;
+        return GDI_OK;
     }
+    if (ch->scope == GDI_SCOPE_GRID) {
+        // fence-free halo sweep: one node per thread, 1024-thread workgroups, grid a multiple of 8
+        const uint32_t block = t.block ? t.block : 1024u;
+        uint32_t G = t.grid ? t.grid : (uint32_t)std::min(cus, GDI_HALO_MAX_GRID) / 8u * 8u;
+        if (block < 256) return fail(GDI_EINVAL, "the grid sweep needs at least 256 threads per workgroup");
+        if (G < 8 || G % 8 || G > GDI_HALO_MAX_GRID)
+            return fail(GDI_EINVAL, "the grid sweep needs a grid that is a multiple of 8 in [8, 512]");
+        int rc = build_halo(g, (int32_t)G, lds_max - 256);
+        if (rc) return rc;
+        if (g->halo_lds_words >= 0) {
+            int cap = 0;
+            int e = gdi_halo_capacity((int)block, gdi_halo_lds_bytes(g->halo_lds_words, g->C, 2 * (GDI_HALO_THR_MAX + 1)), &cap);
+            if (e) return fail(GDI_EDEVICE, std::string("occupancy query: ") + gdi_hip_error_string(e));
+            if ((int)G > cap)
+                return fail(GDI_EDEVICE, "grid of " + std::to_string(G) + " workgroups cannot be co-resident (capacity " +
+                                             std::to_string(cap) + ")");
+            ch->grid = G;
+            ch->block = block;
+            ch->lanes = 1;
+            return GDI_OK;
+        }
+        if (t.scope == GDI_SCOPE_GRID)
+            return fail(GDI_ERANGE, "the spin windows of this graph do not fit one workgroup's LDS");
+        ch->scope = GDI_SCOPE_GRID_FENCED;  // automatic choice falls back
+    }
+    int cap = 0;
+    int e = gdi_grid_capacity((int)ch->block, (int)ch->lanes, &cap);
+    if (e) return fail(GDI_EDEVICE, std::string("occupancy query: ") + gdi_hip_error_string(e));
+    uint32_t want = t.grid ? t.grid : (uint32_t)std::min(cap, cus);
+    if (want < 1 || (int)want > cap)
+        return fail(GDI_EDEVICE, "grid of " + std::to_string(want) + " workgroups cannot be co-resident (capacity " +
+                                     std::to_string(cap) + ")");
+    ch->grid = want;
     return GDI_OK;
 }
 
@@ -293,6 +327,9 @@ int upload(gdi_graph *g, const int32_t *rp, const int32_t *col, const int32_t *w
         int64_t base = nrp[(size_t)v];
         for (size_t q = 0; q < row.size(); ++q) adj[(size_t)base + q] = make_int2(row[q].first, row[q].second);
     }
+    g->cls.assign((size_t)g->n_pad, -1);
+    for (int32_t c = 0; c < g->C; ++c)
+        for (int32_t k = 0; k < g->csz[(size_t)c]; ++k) g->cls[(size_t)(g->cbeg[(size_t)c] + k)] = c;
     HIP_TRY(g->d_rp.reserve(nrp.size()), "hipMalloc row_ptr");
     HIP_TRY(g->d_adj.reserve(adj.size()), "hipMalloc adjacency");
     HIP_TRY(g->d_orig.reserve(g->orig.size()), "hipMalloc orig");
@@ -312,6 +349,103 @@ int upload(gdi_graph *g, const int32_t *rp, const int32_t *col, const int32_t *w
     HIP_TRY(hipMemcpy(g->d_csz.p, g->csz.data(), g->csz.size() * 4, hipMemcpyHostToDevice), "upload classes");
     HIP_TRY(hipEventCreate(&g->ev0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&g->ev1), "hipEventCreate");
+    g->h_rp.swap(nrp);
+    g->h_adj.swap(adj);
+    return GDI_OK;
+}
+
+// Workgroup b handles chunk q(b) of every class; consecutive block ids are spread
+// over the 8 XCDs, so XCD x gets the contiguous chunk range [x*G/8, (x+1)*G/8).
+inline int32_t chunk_of_block(int32_t b, int32_t G) { return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b; }
+
+// Builds the halo layout for grid size G: own chunks, windows of the packed spin
+// array per (workgroup, class), LDS offsets and the CSR with LDS bit indices.
+int build_halo(gdi_graph *g, int32_t G, int lds_budget)
+{
+    if (g->halo_G == G && g->halo_lds_words != -1) return GDI_OK;
+    const int32_t C = g->C;
+    std::vector<int32_t> chunk((size_t)C), blk_of_q((size_t)G);
+    for (int32_t b = 0; b < G; ++b) blk_of_q[(size_t)chunk_of_block(b, G)] = b;
+    for (int32_t c = 0; c < C; ++c) {
+        const int64_t per = ((int64_t)g->csz[(size_t)c] + G - 1) / G;
+        chunk[(size_t)c] = (int32_t)std::max<int64_t>(GDI_CLASS_ALIGN, (per + GDI_CLASS_ALIGN - 1) / GDI_CLASS_ALIGN * GDI_CLASS_ALIGN);
+    }
+    const size_t GC = (size_t)G * (size_t)C;
+    std::vector<GdiHaloEntry> tab(GC);
+    std::vector<int32_t> wlo(GC, INT32_MAX), whi(GC, -1);
+    for (int32_t b = 0; b < G; ++b) {
+        const int32_t q = chunk_of_block(b, G);
+        for (int32_t c = 0; c < C; ++c) {
+            GdiHaloEntry &e = tab[(size_t)b * C + c];
+            std::memset(&e, 0, sizeof(e));
+            const int64_t lo = (int64_t)g->cbeg[(size_t)c] + (int64_t)q * chunk[(size_t)c];
+            const int64_t hi = std::min<int64_t>((int64_t)g->cbeg[(size_t)c] + g->csz[(size_t)c], lo + chunk[(size_t)c]);
+            if (lo < hi) {
+                e.node_lo = (int32_t)lo;
+                e.node_hi = (int32_t)hi;
+                const size_t i = (size_t)b * C + c;
+                wlo[i] = std::min<int32_t>(wlo[i], (int32_t)(lo >> 5));
+                whi[i] = std::max<int32_t>(whi[i], (int32_t)((hi + 31) >> 5));
+            }
+        }
+    }
+    auto owner = [&](int32_t v) {
+        const int32_t c = g->cls[(size_t)v];
+        return blk_of_q[(size_t)((v - g->cbeg[(size_t)c]) / chunk[(size_t)c])];
+    };
+    for (int32_t v = 0; v < g->n_pad; ++v) {
+        if (g->cls[(size_t)v] < 0) continue;
+        const int32_t b = owner(v);
+        for (int32_t k = g->h_rp[(size_t)v]; k < g->h_rp[(size_t)v + 1]; ++k) {
+            const int32_t j = g->h_adj[(size_t)k].x;
+            const size_t i = (size_t)b * C + g->cls[(size_t)j];
+            wlo[i] = std::min<int32_t>(wlo[i], j >> 5);
+            whi[i] = std::max<int32_t>(whi[i], (j >> 5) + 1);
+        }
+    }
+    int32_t lds_words = 0;
+    for (int32_t b = 0; b < G; ++b) {
+        int32_t off = 0;
+        for (int32_t c = 0; c < C; ++c) {
+            const size_t i = (size_t)b * C + c;
+            GdiHaloEntry &e = tab[i];
+            if (whi[i] < 0) {
+                e.win_lo = 0;
+                e.win_len = 0;
+            } else {
+                e.win_lo = wlo[i];
+                e.win_len = whi[i] - wlo[i];
+            }
+            e.lds_off = off;
+            off += e.win_len;
+        }
+        lds_words = std::max(lds_words, off);
+    }
+    g->halo_G = G;
+    if (gdi_halo_lds_bytes(lds_words, C, 0) > lds_budget) {
+        g->halo_lds_words = -2;
+        return GDI_OK;
+    }
+    std::vector<int2> adjL(g->h_adj.size());
+    for (int32_t v = 0; v < g->n_pad; ++v) {
+        if (g->cls[(size_t)v] < 0) continue;
+        const int32_t b = owner(v);
+        for (int32_t k = g->h_rp[(size_t)v]; k < g->h_rp[(size_t)v + 1]; ++k) {
+            const int32_t j = g->h_adj[(size_t)k].x;
+            const GdiHaloEntry &e = tab[(size_t)b * C + g->cls[(size_t)j]];
+            const int32_t lb = (e.lds_off + (j >> 5) - e.win_lo) * 32 + (j & 31);
+            adjL[(size_t)k] = make_int2(lb, g->h_adj[(size_t)k].y);
+        }
+    }
+    HIP_TRY(g->d_adjL.reserve(adjL.size()), "hipMalloc halo CSR");
+    HIP_TRY(g->d_tab.reserve(tab.size()), "hipMalloc halo table");
+    HIP_TRY(g->d_words.reserve((size_t)g->n_pad / 32 + 1), "hipMalloc packed spins");
+    HIP_TRY(g->d_member.reserve(8 * 64), "hipMalloc barrier");
+    HIP_TRY(g->d_group.reserve(2 * 8 * GDI_HALO_GROUP_PAD), "hipMalloc barrier");
+    if (!adjL.empty())
+        HIP_TRY(hipMemcpy(g->d_adjL.p, adjL.data(), adjL.size() * sizeof(int2), hipMemcpyHostToDevice), "upload halo CSR");
+    HIP_TRY(hipMemcpy(g->d_tab.p, tab.data(), tab.size() * sizeof(GdiHaloEntry), hipMemcpyHostToDevice), "upload halo table");
+    g->halo_lds_words = lds_words;
     return GDI_OK;
 }
 
@@ -399,7 +533,8 @@ int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host
     if ((rc = ensure_table(g, s, de_max))) return rc;
     const uint64_t phases = (uint64_t)(S - s->start_sweep) * (uint64_t)g->C;
     uint64_t bar_words = 0;
-    if (ch.scope == GDI_SCOPE_GRID) {
+    if (phases > (uint64_t(1) << 30)) return fail(GDI_ERANGE, "too many phases for one launch");
+    if (ch.scope == GDI_SCOPE_GRID_FENCED) {
         if (phases > (uint64_t(1) << 22)) return fail(GDI_ERANGE, "too many phases for one launch");
         bar_words = phases * (GDI_BAR_GROUPS + 1) * GDI_BAR_PAD;
         HIP_TRY(g->d_bar.reserve(bar_words), "hipMalloc barrier");
@@ -459,9 +594,30 @@ int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host
     a.snapshot = s->balance_mode == GDI_BAL_SNAPSHOT ? 1u : 0u;
     a.spin_limit = (g->have_tune && g->tune.spin_limit) ? (int64_t)g->tune.spin_limit : kSpinLimit;
 
+    GdiHaloArgs ha{};
+    if (ch.scope == GDI_SCOPE_GRID) {
+        ha.base = a;
+        ha.adjL = g->d_adjL.p;
+        ha.tab = g->d_tab.p;
+        ha.words = g->d_words.p;
+        ha.member = g->d_member.p;
+        ha.group = g->d_group.p;
+        ha.lds_words = g->halo_lds_words;
+        int lds_max = 0, dev = 0;
+        HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+        HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
+        ha.thr_in_lds = (g->thr_K <= GDI_HALO_THR_MAX &&
+                         gdi_halo_lds_bytes(g->halo_lds_words, g->C, 2 * (g->thr_K + 1)) <= lds_max) ? 1 : 0;
+        rc = gdi_launch_fill_u64(g->d_words.p, (int64_t)g->n_pad / 32 + 1, st);
+        if (!rc) rc = gdi_launch_fill_u64(g->d_member.p, 8 * 64, st);
+        if (!rc) rc = gdi_launch_fill_u64(g->d_group.p, 2 * 8 * GDI_HALO_GROUP_PAD, st);
+        if (rc) return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
+    }
     HIP_TRY(hipEventRecord(g->ev0, st), "hipEventRecord");
     if (ch.scope == GDI_SCOPE_WORKGROUP)
         rc = gdi_launch_sweep_wg(a, (int)ch.block, (int)ch.lanes, ch.spins_lds ? 1 : 0, st);
+    else if (ch.scope == GDI_SCOPE_GRID)
+        rc = gdi_launch_sweep_halo(ha, (int)ch.grid, (int)ch.block, st);
     else
         rc = gdi_launch_sweep_grid(a, (int)ch.grid, (int)ch.block, (int)ch.lanes, st);
     if (rc) return fail(GDI_EDEVICE, std::string("sweep launch: ") + gdi_hip_error_string(rc));

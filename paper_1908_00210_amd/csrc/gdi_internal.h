@@ -46,6 +46,34 @@ struct GdiSweepArgs {
     int64_t spin_limit;        // bounded waits: polls before giving up
 };
 
+// Halo layout of the fence-free grid sweep (k_sweep_halo). Each workgroup b owns,
+// for every class c, a 64-aligned chunk of nodes, and keeps in LDS the spin bits
+// of a window of the packed spin array that covers its own chunk and every
+// neighbour of its nodes in class c.
+#define GDI_HALO_MAX_GRID 512
+#define GDI_HALO_GROUP_PAD 16  // uint64 words between group words (128 bytes)
+#define GDI_HALO_PF 16         // CSR entries per node held in registers across a barrier
+#define GDI_HALO_THR_MAX 4096  // largest table width kept in LDS (two rows)
+
+struct GdiHaloEntry {          // one per (workgroup, class)
+    int32_t node_lo, node_hi;  // own nodes: new ids [node_lo, node_hi)
+    int32_t win_lo;            // first packed word of the window
+    int32_t win_len;           // words in the window
+    int32_t lds_off;           // LDS word where the window starts
+    int32_t pad0, pad1, pad2;
+};
+
+struct GdiHaloArgs {
+    GdiSweepArgs base;
+    const int2 *adjL;          // CSR with columns rewritten as LDS bit indices of the owner
+    const GdiHaloEntry *tab;   // grid x C entries
+    uint64_t *words;           // packed spins: (epoch << 32) | 32 spin bits (bit = 1 for +1)
+    uint64_t *member;          // 8 x 64 words: workgroup b posts (epoch << 32) | uint32(dM) at (b % 8) * 64 + b / 8
+    uint64_t *group;           // 2 x 8 words (phase parity x group), GDI_HALO_GROUP_PAD apart
+    int32_t lds_words;         // window words per workgroup (max over workgroups)
+    int32_t thr_in_lds;        // 1: the current and next threshold rows are staged in LDS
+};
+
 // host-side launchers (gdi_kernels.hip)
 int gdi_launch_init_spins(const int32_t *orig, const int8_t *init_orig, int8_t *spin, int32_t n_pad,
                           uint32_t key0, uint32_t key1, uint32_t replica, void *stream);
@@ -60,5 +88,8 @@ int gdi_launch_gather_in(const int32_t *orig, const int8_t *in_orig, int32_t n_p
 int gdi_launch_sweep_wg(const GdiSweepArgs &a, int block, int lanes, int spins_in_lds, void *stream);
 int gdi_launch_sweep_grid(const GdiSweepArgs &a, int grid, int block, int lanes, void *stream);
 int gdi_grid_capacity(int block, int lanes, int *max_grid);
+int gdi_launch_sweep_halo(const GdiHaloArgs &h, int grid, int block, void *stream);
+int gdi_halo_lds_bytes(int32_t lds_words, int32_t C, int32_t thr_words);
+int gdi_halo_capacity(int block, int lds_bytes, int *max_grid);
 int gdi_wg_lds_bytes(int32_t n_pad, int32_t C, int spins_in_lds);
 const char *gdi_hip_error_string(int code);

@@ -21,6 +21,22 @@
 
 #include "gdi_internal.h"
 
+// Optional per-phase timestamps for studying the grid sweep (off unless the
+// library is compiled with -DGDI_PHASE_TIMING; the product build has none).
+#ifdef GDI_PHASE_TIMING
+__device__ unsigned long long *g_tbuf;
+__device__ int g_tphases;
+#define GDI_TSTAMP(slot, cond)                                                                      \
+    do {                                                                                          \
+        if ((cond) && g_tbuf && (int)p < g_tphases)                                               \
+            g_tbuf[((size_t)p * gridDim.x + blockIdx.x) * 8 + (slot)] = __builtin_amdgcn_s_memrealtime(); \
+    } while (0)
+#else
+#define GDI_TSTAMP(slot, cond) \
+    do {                       \
+    } while (0)
+#endif
+
 namespace {
 
 // ------------------------------------------------------------------ Philox4x32-10
@@ -86,9 +102,38 @@ __device__ __forceinline__ PhaseView make_view(int32_t M0, int32_t P_c, int32_t 
     return v;
 }
 
+// Metropolis decision of one node given its local field h and spin sigma
+// (eq. 5 / eq. 6 flip cost with the gated balance term). Philox words are drawn
+// only when the gate or the threshold lookup needs them.
+__device__ __forceinline__ bool decide(const GdiSweepArgs &a, int32_t v, uint32_t t, int32_t sigma,
+                                       int32_t h, const PhaseView &pv, const uint32_t *thr_row)
+{
+    const bool need_gate = !a.snapshot && pv.D > 0 && sigma == pv.s;
+    uint32_t x0 = 0, x1 = 0;
+    bool have = false;
+    if (need_gate) {
+        const Words4 r = philox10((uint32_t)a.orig[v], t, a.replica, 0u, a.key0, a.key1);
+        x0 = r.w0;
+        x1 = r.w1;
+        have = true;
+    }
+    int32_t m_seen;
+    if (a.snapshot) {
+        m_seen = pv.M0;
+    } else {
+        const bool gated = need_gate && ((uint64_t)x1 * pv.O < ((uint64_t)(uint32_t)pv.D << 32));
+        m_seen = gated ? pv.M0 : 0;
+    }
+    const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
+    if (dE <= 0) return true;
+    if (dE > a.K) return false;
+    if (!have) x0 = philox10((uint32_t)a.orig[v], t, a.replica, 0u, a.key0, a.key1).w0;
+    return x0 < thr_row[dE];
+}
+
 // One node of the current class: L lanes share its CSR row. All L lanes return
 // the same decision; lane 0 of the subgroup performs the write.
-// SpinPtr is an LDS or a global int8 pointer.
+// sp is an LDS or a global int8 pointer.
 template <int L>
 __device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t *sp, int32_t v,
                                             int lane, uint32_t t, const PhaseView &pv,
@@ -107,35 +152,9 @@ __device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t 
         for (int off = L / 2; off > 0; off >>= 1) h += __shfl_xor(h, off, L);
     }
     const int32_t sigma = sp[v];
-    const bool need_gate = !a.snapshot && pv.D > 0 && sigma == pv.s;
-    uint32_t x0 = 0, x1 = 0;
-    bool have = false;
-    if (need_gate) {
-        const Words4 r = philox10((uint32_t)a.orig[v], t, a.replica, 0u, a.key0, a.key1);
-        x0 = r.w0;
-        x1 = r.w1;
-        have = true;
-    }
-    int32_t m_seen;
-    if (a.snapshot) {
-        m_seen = pv.M0;
-    } else {
-        const bool gated = need_gate && ((uint64_t)x1 * pv.O < ((uint64_t)(uint32_t)pv.D << 32));
-        m_seen = gated ? pv.M0 : 0;
-    }
-    const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
-    bool flip;
-    if (dE <= 0) {
-        flip = true;
-    } else if (dE > a.K) {
-        flip = false;
-    } else {
-        if (!have) x0 = philox10((uint32_t)a.orig[v], t, a.replica, 0u, a.key0, a.key1).w0;
-        flip = x0 < thr_row[dE];
-    }
     *h_out = h;
     *sigma_out = sigma;
-    return flip;
+    return decide(a, v, t, sigma, h, pv, thr_row);
 }
 
 // ------------------------------------------------------------------ workgroup scope
@@ -325,6 +344,363 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_grid(GdiSweepArgs a)
     }
     const int64_t w = wave_sum_i64(dcut_total);
     if ((tid & 63) == 0 && w != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)w);
+}
+
+// ------------------------------------------------------------------ grid scope, fence-free
+// Every value one workgroup hands to another travels in a self-describing 64-bit
+// word (epoch << 32 | payload) written and read with agent-scope atomics, so no
+// cache-wide release/acquire fence is needed: a reader that sees the epoch it
+// waits for sees the payload of the same store.
+//   * spins: after the phase of class c, each owner republishes every packed word
+//     of its chunk with the phase's epoch; readers poll only the words of their
+//     window of class c and copy the bits into LDS;
+//   * dM: each workgroup posts (epoch, dM) in its member word (the members of one
+//     group are contiguous, so a leader polls two cache lines); the leader of each
+//     group (workgroups b = x mod 8) sums its members' words and posts
+//     (epoch, group sum) in the group word of the phase's parity; everyone sums
+//     the 8 group words.
+// A word can only be overwritten after every reader has consumed it: member and
+// window words are rewritten at the earliest one full barrier later, group words
+// alternate by phase parity. All waits are bounded by spin_limit.
+
+__device__ __forceinline__ uint64_t ld_agent(const uint64_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void st_agent(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The abort flag lives in LDS; workgroup-scope atomics keep it an LDS access
+// (a volatile generic pointer would become a flat access whose wait also waits
+// for every outstanding global load of the wave).
+__device__ __forceinline__ bool aborted(int32_t *flag)
+{
+    return __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) != 0;
+}
+
+__device__ __forceinline__ void set_abort(int32_t *flag)
+{
+    __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ int32_t lds_spin(const uint32_t *bits, int32_t lb)
+{
+    return (int32_t)((bits[lb >> 5] >> (lb & 31)) & 1u) * 2 - 1;
+}
+
+// Polls the words of one window until they carry `epoch`, copying their bits to LDS.
+// Returns false when the bounded wait expires or another thread has aborted.
+__device__ __forceinline__ bool poll_window(const GdiHaloArgs &h, const GdiHaloEntry &e, uint32_t *bits,
+                                            uint32_t epoch, int first, int stride, int32_t *abort_sh)
+{
+    for (int32_t i = first; i < e.win_len; i += stride) {
+        const uint64_t *src = h.words + e.win_lo + i;
+        for (int64_t tries = 0;; ++tries) {
+            const uint64_t w = ld_agent(src);
+            if ((uint32_t)(w >> 32) >= epoch) {
+                bits[e.lds_off + i] = (uint32_t)w;
+                break;
+            }
+            if (tries >= h.base.spin_limit || aborted(abort_sh)) return false;
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    return true;
+}
+
+// Per-node state carried across barriers. Everything of a node's update that
+// does not depend on spins is loaded ahead: the row bounds and original id two
+// phases ahead (RowAhead), the CSR entries and Philox words one phase ahead
+// (NodePrefetch), so that no load issued while waiting depends on another.
+struct RowAhead {
+    int32_t r0, r1, id;
+};
+
+struct NodePrefetch {
+    int32_t r0, deg;
+    uint32_t x0, x1;
+    int2 e[GDI_HALO_PF];
+};
+
+__device__ __forceinline__ void load_row(const GdiSweepArgs &a, int32_t v, RowAhead &ra)
+{
+    ra.r0 = a.rp[v];
+    ra.r1 = a.rp[v + 1];
+    ra.id = a.orig[v];
+}
+
+__device__ __forceinline__ void load_entries(const GdiHaloArgs &h, const RowAhead &ra, uint32_t t,
+                                             NodePrefetch &pf)
+{
+    const GdiSweepArgs &a = h.base;
+    // draw the Philox words first: they only need the id loaded a phase ago, whereas
+    // waiting for it after issuing the CSR loads would wait for those loads as well
+    // (vector memory counters complete in order)
+    const Words4 w = philox10((uint32_t)ra.id, t, a.replica, 0u, a.key0, a.key1);
+    pf.x0 = w.w0;
+    pf.x1 = w.w1;
+    pf.r0 = ra.r0;
+    pf.deg = ra.r1 - ra.r0;
+#pragma unroll
+    for (int k = 0; k < GDI_HALO_PF; ++k) pf.e[k] = k < pf.deg ? h.adjL[ra.r0 + k] : make_int2(0, 0);
+}
+
+// Metropolis decision with the node's Philox words already drawn.
+__device__ __forceinline__ bool decide_words(const GdiSweepArgs &a, int32_t sigma, int32_t h,
+                                             const PhaseView &pv, const uint32_t *thr, uint32_t x0,
+                                             uint32_t x1)
+{
+    int32_t m_seen;
+    if (a.snapshot) {
+        m_seen = pv.M0;
+    } else {
+        const bool gated = pv.D > 0 && sigma == pv.s &&
+                           ((uint64_t)x1 * pv.O < ((uint64_t)(uint32_t)pv.D << 32));
+        m_seen = gated ? pv.M0 : 0;
+    }
+    const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
+    if (dE <= 0) return true;
+    if (dE > a.K) return false;
+    return x0 < thr[dE];
+}
+
+// Bounded poll of one epoch-tagged word; returns false on timeout or abort.
+__device__ __forceinline__ bool poll_word(const uint64_t *w, uint32_t epoch, int64_t limit,
+                                          int32_t *abort_v, int32_t *payload)
+{
+    for (int64_t tries = 0;; ++tries) {
+        const uint64_t v = ld_agent(w);
+        if ((uint32_t)(v >> 32) >= epoch) {
+            *payload = (int32_t)(uint32_t)v;
+            return true;
+        }
+        if (tries >= limit || aborted(abort_v)) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+__global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
+{
+    const GdiSweepArgs &a = h.base;
+    extern __shared__ uint32_t lds[];
+    uint32_t *bits = lds;                                                   // window bits
+    GdiHaloEntry *tab = reinterpret_cast<GdiHaloEntry *>(lds + h.lds_words); // C entries
+    int32_t *Psh = reinterpret_cast<int32_t *>(tab + a.C);                  // C counts of +1
+    int32_t *csz_sh = Psh + a.C;                                            // C class sizes
+    uint32_t *thr_sh = reinterpret_cast<uint32_t *>(csz_sh + a.C);          // 2 x (K+1) thresholds
+    __shared__ int32_t wg_acc;
+    __shared__ int32_t total_sh;
+    __shared__ int32_t abort_sh;
+
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int wave = tid >> 6, lane = tid & 63, nwaves = nth >> 6;
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    const uint32_t ngroups = G < 8u ? G : 8u;
+    const uint32_t x = b % ngroups;
+    const uint32_t gsz = G / ngroups + (x < G % ngroups ? 1u : 0u);
+    const bool leader = b < ngroups;
+    const int32_t K1 = a.K + 1;
+    const bool thr_lds = h.thr_in_lds != 0;
+    int32_t *abort_v = &abort_sh;
+    // roles: the last wave reads the group words, the wave before it collects the
+    // member words (leader workgroups only); both start polling as soon as a phase's
+    // nodes are done. All other waves ("workers") update nodes, prefetch and poll
+    // their window words.
+    const int nwork = (nwaves - 2) * 64;
+    const bool worker = tid < nwork;
+
+    for (int i = tid; i < a.C; i += nth) {
+        tab[i] = h.tab[(size_t)b * a.C + i];
+        Psh[i] = a.P[i];
+        csz_sh[i] = a.csz[i];
+    }
+    if (thr_lds && a.t0 < a.S)
+        for (int i = tid; i < K1; i += nth) thr_sh[(a.t0 & 1u) * K1 + i] = a.thr[(size_t)a.t0 * K1 + i];
+    if (tid == 0) {
+        wg_acc = 0;
+        total_sh = 0;
+        abort_sh = 0;
+    }
+    int32_t M = (int32_t)a.state[0];
+    __syncthreads();
+
+    // prologue: publish own words of every class with epoch 1, then fill all windows
+    for (int32_t c = 0; c < a.C; ++c) {
+        const GdiHaloEntry e = tab[c];
+        const int32_t w_lo = e.node_lo >> 5, w_hi = (e.node_hi + 31) >> 5;
+        for (int32_t wd = w_lo + tid; wd < w_hi && e.node_lo < e.node_hi; wd += nth) {
+            uint32_t word = 0;
+            for (int k = 0; k < 32; ++k) {
+                const int32_t v = wd * 32 + k;
+                if (v >= e.node_lo && v < e.node_hi && a.spin[v] > 0) word |= 1u << k;
+            }
+            bits[e.lds_off + wd - e.win_lo] = word;
+            st_agent(h.words + wd, (1ull << 32) | word);
+        }
+    }
+    // pipeline fill: phase 0 entries, phase 1 rows
+    NodePrefetch pf;
+    RowAhead ra;
+    {
+        const uint32_t t1 = a.C > 1 ? a.t0 : a.t0 + 1u;
+        const int32_t c1 = a.C > 1 ? 1 : 0;
+        if (worker && a.t0 < a.S && tab[0].node_lo + tid < tab[0].node_hi) {
+            load_row(a, tab[0].node_lo + tid, ra);
+            load_entries(h, ra, a.t0, pf);
+        }
+        if (worker && t1 < a.S && tab[c1].node_lo + tid < tab[c1].node_hi) load_row(a, tab[c1].node_lo + tid, ra);
+    }
+    bool ok = true;
+    if (worker)
+        for (int32_t c = 0; c < a.C && ok; ++c) ok = poll_window(h, tab[c], bits, 1u, tid, nwork, abort_v);
+    if (!ok) set_abort(abort_v);
+    __syncthreads();
+    if (abort_sh) {
+        if (tid == 0) __hip_atomic_store(&a.state[3], (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return;
+    }
+
+    int64_t dcut = 0, dcut_total = 0;
+    uint32_t p = 0;
+    for (uint32_t t = a.t0; t < a.S; ++t) {
+        const uint32_t *thr = thr_lds ? thr_sh + (t & 1u) * K1 : a.thr + (size_t)t * K1;
+        for (int32_t c = 0; c < a.C; ++c, ++p) {
+            const GdiHaloEntry e = tab[c];
+            const uint32_t epoch = p + 2u;
+            int32_t dM = 0;
+            GDI_TSTAMP(0, tid == 0);
+            if (worker) {
+                const PhaseView pv = make_view(M, Psh[c], csz_sh[c], a.C, a.n);
+                // wave-uniform trip count so that ballots see whole waves of 64 nodes;
+                // the first pass uses the prefetched rows, later passes load their own
+                for (int32_t base = e.node_lo; base < e.node_hi; base += nwork) {
+                    const int32_t v = base + tid;
+                    const bool active = v < e.node_hi;
+                    bool flip = false;
+                    int32_t sigma_l = 0;
+                    if (active) {
+                        NodePrefetch q;
+                        if (base != e.node_lo) {
+                            RowAhead rq;
+                            load_row(a, v, rq);
+                            load_entries(h, rq, t, q);
+                        } else {
+                            q = pf;
+                        }
+                        int32_t hv = 0;
+#pragma unroll
+                        for (int k = 0; k < GDI_HALO_PF; ++k) hv += q.e[k].y * lds_spin(bits, q.e[k].x);
+                        for (int32_t k = GDI_HALO_PF; k < q.deg; ++k) {
+                            const int2 en = h.adjL[q.r0 + k];
+                            hv += en.y * lds_spin(bits, en.x);
+                        }
+                        const int32_t lb = (e.lds_off + (v >> 5) - e.win_lo) * 32 + (v & 31);
+                        const int32_t sigma = lds_spin(bits, lb);
+                        flip = decide_words(a, sigma, hv, pv, thr, q.x0, q.x1);
+                        sigma_l = sigma;
+                        if (flip) dcut += (int64_t)sigma * hv;
+                    }
+                    const uint64_t fm = __ballot(flip);
+                    // flips of +1 spins lower M by 2, flips of -1 spins raise it by 2
+                    const uint64_t fm_minus = __ballot(flip && sigma_l < 0);
+                    dM += 2 * (__popcll(fm_minus) - __popcll(fm & ~fm_minus));
+                    const int32_t v0 = base + (wave << 6);
+                    if (lane == 0 && v0 < e.node_hi) {
+                        // own chunk words covered by this wave: flip their bits, republish both
+                        const int32_t wd = v0 >> 5;
+                        const int32_t w_end = (e.node_hi + 31) >> 5;
+                        uint32_t *lw = bits + e.lds_off + wd - e.win_lo;
+                        lw[0] ^= (uint32_t)fm;
+                        st_agent(h.words + wd, ((uint64_t)epoch << 32) | lw[0]);
+                        if (wd + 1 < w_end) {
+                            lw[1] ^= (uint32_t)(fm >> 32);
+                            st_agent(h.words + wd + 1, ((uint64_t)epoch << 32) | lw[1]);
+                        }
+                    }
+                }
+                if (lane == 0 && dM != 0) atomicAdd(&wg_acc, dM);
+            }
+            GDI_TSTAMP(1, tid == 0);
+            __syncthreads();
+            GDI_TSTAMP(2, tid == 0);
+            uint64_t *gw = h.group + (size_t)((p & 1u) * 8u) * GDI_HALO_GROUP_PAD;
+            bool good = true;
+            if (worker) {
+                // while the phase completes elsewhere: entries of phase p+1 (rows are
+                // already here), rows of phase p+2, next threshold row
+                const bool last_c = c + 1 == a.C;
+                const uint32_t t1 = last_c ? t + 1u : t;
+                const int32_t c1 = last_c ? 0 : c + 1;
+                const bool last_c1 = c1 + 1 == a.C;
+                const uint32_t t2 = last_c1 ? t1 + 1u : t1;
+                const int32_t c2 = last_c1 ? 0 : c1 + 1;
+                if (t1 < a.S) {
+                    if (last_c && thr_lds)
+                        for (int i = tid; i < K1; i += nwork) thr_sh[(t1 & 1u) * K1 + i] = a.thr[(size_t)t1 * K1 + i];
+                    if (tab[c1].node_lo + tid < tab[c1].node_hi) load_entries(h, ra, t1, pf);
+                }
+                if (t2 < a.S && tab[c2].node_lo + tid < tab[c2].node_hi) load_row(a, tab[c2].node_lo + tid, ra);
+                GDI_TSTAMP(6, tid == 0);
+                good = poll_window(h, e, bits, epoch, tid, nwork, abort_v);
+                GDI_TSTAMP(7, tid == 0);
+            } else if (wave == nwaves - 1) {
+                // this wave has no other memory traffic, so its store leaves at once
+                if (lane == 0) {
+                    st_agent(h.member + x * 64u + b / ngroups, ((uint64_t)epoch << 32) | (uint32_t)wg_acc);
+                    wg_acc = 0;
+                }
+                int32_t part = 0;
+                if ((uint32_t)lane < ngroups)
+                    good = poll_word(gw + (size_t)lane * GDI_HALO_GROUP_PAD, epoch, a.spin_limit, abort_v, &part);
+                part = wave_sum_i32(part);
+                if (lane == 0) total_sh = part;
+                GDI_TSTAMP(5, lane == 0);
+            } else if (leader) {
+                int32_t part = 0;
+                if ((uint32_t)lane < gsz)
+                    good = poll_word(h.member + x * 64u + (uint32_t)lane, epoch, a.spin_limit, abort_v, &part);
+                part = wave_sum_i32(part);
+                if (lane == 0) st_agent(gw + (size_t)x * GDI_HALO_GROUP_PAD, ((uint64_t)epoch << 32) | (uint32_t)part);
+                GDI_TSTAMP(4, lane == 0);
+            }
+            if (!good) set_abort(abort_v);
+            __syncthreads();
+            GDI_TSTAMP(3, tid == 0);
+            if (abort_sh) {
+                if (tid == 0) __hip_atomic_store(&a.state[3], (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
+            const int32_t tot = total_sh;
+            M += tot;
+            if (tid == 0 && a.C > 1) Psh[c] += tot / 2;
+        }
+        if (a.trace_m) {
+            if (b == 0 && tid == 0) a.trace_m[t] = M;
+            const int64_t w = wave_sum_i64(dcut);
+            if (lane == 0 && w != 0) atomicAdd((unsigned long long *)&a.trace_dcut[t], (unsigned long long)w);
+            dcut_total += dcut;
+            dcut = 0;
+        }
+    }
+    dcut_total += dcut;
+    __syncthreads();
+    // epilogue: own spins back to the int8 array
+    for (int32_t c = 0; c < a.C; ++c) {
+        const GdiHaloEntry e = tab[c];
+        for (int32_t v = e.node_lo + tid; v < e.node_hi; v += nth) {
+            const int32_t lb = (e.lds_off + (v >> 5) - e.win_lo) * 32 + (v & 31);
+            a.spin[v] = (int8_t)lds_spin(bits, lb);
+        }
+    }
+    if (b == 0) {
+        for (int i = tid; i < a.C; i += nth) a.P[i] = Psh[i];
+        if (tid == 0) a.state[0] = M;
+    }
+    const int64_t w = wave_sum_i64(dcut_total);
+    if (lane == 0 && w != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)w);
 }
 
 // ------------------------------------------------------------------ helpers
@@ -532,5 +908,44 @@ int gdi_launch_sweep_grid(const GdiSweepArgs &a, int grid, int block, int lanes,
     e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(block), args, (unsigned)lds, (hipStream_t)stream);
     return status(e);
 }
+
+int gdi_halo_lds_bytes(int32_t lds_words, int32_t C, int32_t thr_words)
+{
+    return lds_words * 4 + C * (int)sizeof(GdiHaloEntry) + C * 8 + thr_words * 4;
+}
+
+int gdi_halo_capacity(int block, int lds_bytes, int *max_grid)
+{
+    const void *f = (const void *)k_sweep_halo;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    int dev = 0, cus = 0, per_cu = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, block, lds_bytes);
+    if (e != hipSuccess) return status(e);
+    *max_grid = cus * per_cu;
+    return 0;
+}
+
+int gdi_launch_sweep_halo(const GdiHaloArgs &h, int grid, int block, void *stream)
+{
+    const void *f = (const void *)k_sweep_halo;
+    const int lds = gdi_halo_lds_bytes(h.lds_words, h.base.C, h.thr_in_lds ? 2 * (h.base.K + 1) : 0);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return status(e);
+    GdiHaloArgs copy = h;
+    void *args[] = {&copy};
+    e = hipLaunchCooperativeKernel(f, dim3(grid), dim3(block), args, (unsigned)lds, (hipStream_t)stream);
+    return status(e);
+}
+
+#ifdef GDI_PHASE_TIMING
+extern "C" int gdi_timing_setup(unsigned long long *buf, int phases)
+{
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_tbuf), &buf, sizeof(buf));
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_tphases), &phases, sizeof(int));
+    return (int)e;
+}
+#endif
 
 const char *gdi_hip_error_string(int code) { return hipGetErrorString((hipError_t)code); }

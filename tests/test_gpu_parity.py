@@ -59,7 +59,7 @@ SMALL = {
 
 @pytest.mark.parametrize("name", list(SMALL))
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("scope", [1, 2])
+@pytest.mark.parametrize("scope", [1, 2, 3])
 def test_small_graphs(gdi, oracle_lib, name, mode, scope):
     g = SMALL[name]()
     T = gs.geometric_temps(2.5, 0.05, 40)
@@ -74,11 +74,15 @@ def test_small_graphs(gdi, oracle_lib, name, mode, scope):
     dict(scope=1, lanes_per_node=1, block=64),
     dict(scope=1, lanes_per_node=4, block=256),
     dict(scope=1, lanes_per_node=64, block=1024),
-    dict(scope=2, lanes_per_node=1, block=64, grid=1),
-    dict(scope=2, lanes_per_node=2, block=128, grid=7),
-    dict(scope=2, lanes_per_node=16, block=512, grid=64),
-    dict(scope=2, lanes_per_node=8, block=1024, grid=256),
-    dict(scope=2, lanes_per_node=32, block=256, grid=300),
+    dict(scope=2, grid=8, block=256),
+    dict(scope=2, grid=64, block=512),
+    dict(scope=2, grid=256, block=1024),
+    dict(scope=2, grid=512, block=256),
+    dict(scope=3, lanes_per_node=1, block=64, grid=1),
+    dict(scope=3, lanes_per_node=2, block=128, grid=7),
+    dict(scope=3, lanes_per_node=16, block=512, grid=64),
+    dict(scope=3, lanes_per_node=8, block=1024, grid=256),
+    dict(scope=3, lanes_per_node=32, block=256, grid=300),
 ])
 def test_launch_shape_invariance(gdi, oracle_lib, tune):
     """Same trajectory for every scope, block, grid and lanes-per-node choice (ragged tails)."""
@@ -112,6 +116,14 @@ def test_rgg1m_full_schedule_bench_launch(gdi, oracle_lib):
     assert_same(ref, r)
 
 
+def test_rgg1m_fenced_grid_path(gdi, oracle_lib):
+    """The fenced grid sweep (global gathers) on the same graph, first 300 sweeps."""
+    g, T = gs.workload("rgg1m")
+    T = T[:300]
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, tune=dict(scope=3), label="rgg1m-fenced")
+    assert_same(ref, r)
+
+
 def test_odd_n_negative_weights_and_coefficients(gdi, oracle_lib):
     g = gs.er_graph(999, 0.01, 13, "pm1")
     T = gs.geometric_temps(4.0, 0.1, 50)
@@ -134,7 +146,7 @@ def test_degenerate_graphs(gdi, oracle_lib):
     # a star: one row of 4000 entries, 4000 rows of one entry; isolated nodes too
     a = np.zeros(4000, np.int64); b = np.arange(1, 4001)
     g = gs.from_edges(4100, a, b, np.ones(4000, np.int64))
-    for scope in (1, 2):
+    for scope in (1, 2, 3):
         ref, r, _ = run_both(gdi, oracle_lib, g, T, tune=dict(scope=scope), label="star")
         assert_same(ref, r)
 
@@ -207,14 +219,15 @@ def test_forced_barrier_timeout_reports_error_and_recovers(gdi, oracle_lib):
     g = gs.rgg_graph(20_000, 8.0, 19)
     T = gs.geometric_temps(3.0, 0.05, 20)
     with gdi.Annealer(g) as a:
-        a.tune(scope=2, grid=256, spin_limit=1)
-        with pytest.raises(gdi.GdiError) as e:
-            a.anneal(T, 1)
-        assert e.value.code == gdi.ETIMEOUT
-        a.tune(reset=True)
-        a.tune(scope=2)
-        r = a.anneal(T, 1)
-    assert np.array_equal(r["spins"], oracle_lib.anneal(g, T, 1)["spins"])
+        for scope in (2, 3):
+            a.tune(scope=scope, grid=256, spin_limit=1)
+            with pytest.raises(gdi.GdiError) as e:
+                a.anneal(T, 1)
+            assert e.value.code == gdi.ETIMEOUT
+            a.tune(reset=True)
+            a.tune(scope=scope)
+            r = a.anneal(T, 1)
+            assert np.array_equal(r["spins"], oracle_lib.anneal(g, T, 1)["spins"])
 
 
 def test_bad_schedule_is_rejected(gdi):
