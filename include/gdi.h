@@ -203,6 +203,51 @@ int gdi_threshold_table(const double *temps, uint32_t n_sweeps, int32_t width, u
  */
 int gdi_philox4x32_10(uint64_t seed, const uint32_t ctr[4], uint32_t out[4]);
 
+/* ------------------------------------------------------------------ batched form
+ * Many independent anneals (graph, replica) in ONE persistent launch: every
+ * workgroup repeatedly takes the next instance from a device-side queue (longest
+ * first) and runs all sweeps of that instance; the result of each instance is
+ * bit-identical to gdi_anneal on the same graph, schedule, seed and replica.
+ * The paper keeps the best of 10 independent runs per graph (Sec. VI-B); this is
+ * the device-side form of running many such runs at once.
+ */
+typedef struct {
+    gdi_graph *graph;          /* the instance's graph (must outlive the call) */
+    uint32_t replica;          /* Philox counter word 2 */
+    uint32_t pad;
+    int8_t *spins_out;         /* n spins, original order: host memory for gdi_anneal_batch, device
+                                  memory for gdi_anneal_batch_dev; NULL to skip */
+    int64_t magnetization;     /* out: final M */
+    int64_t cut_weighted;      /* out: final weighted cut */
+} gdi_instance;
+
+/*
+ * gdi_anneal_batch -- run all instances with one schedule (start_sweep must be 0,
+ * init_spins and traces NULL) and seed. tune: block, grid (workgroups) and
+ * lanes_per_node (0 = per-graph choice) of the launch, or NULL for the cached
+ * autotuned choice (gdi_autotune_batch runs on the first call for a batch shape).
+ * Blocks until the results are on the host; kernel_ms (may be NULL) receives the
+ * device time of the launch. Runs on the stream of the first instance's graph.
+ * Errors: GDI_EINVAL (empty batch, NULL graph, bad schedule), GDI_ERANGE (an instance
+ * does not fit one workgroup's LDS or its energy range int32), GDI_EDEVICE, GDI_ENOMEM.
+ */
+int gdi_anneal_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed,
+                     const gdi_tuning *tune, double *kernel_ms);
+
+/* gdi_anneal_batch_dev -- as gdi_anneal_batch with device spins_out pointers. */
+int gdi_anneal_batch_dev(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed,
+                         const gdi_tuning *tune, double *kernel_ms);
+
+/*
+ * gdi_autotune_batch -- time candidate launches (block size, workgroups per CU and
+ * lanes per node relative to each graph's mean degree) on the first probe_sweeps
+ * sweeps of the schedule and return the fastest in best (and its time in best_ms).
+ * The choice is cached per batch shape and used by gdi_anneal_batch with tune == NULL.
+ * Results never depend on the choice. Outputs of inst are not written.
+ */
+int gdi_autotune_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed,
+                       uint32_t probe_sweeps, gdi_tuning *best, double *best_ms);
+
 /* gdi_last_error -- thread-local message of the last failing call ("" if none). */
 const char *gdi_last_error(void);
 

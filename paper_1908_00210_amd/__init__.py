@@ -20,6 +20,7 @@ __all__ = [
     "SCOPE_GRID", "SCOPE_GRID_FENCED", "Schedule", "Tuning", "Result", "GraphInfo", "create", "destroy", "anneal",
     "anneal_dev", "cut", "cut_dev", "last_result", "set_stream", "set_tuning", "get_info",
     "get_colouring", "colour_csr", "threshold_table", "philox4x32_10", "version", "Annealer",
+    "Instance", "anneal_batch", "autotune_batch",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgdi.so")
@@ -74,6 +75,12 @@ class Result(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Instance(ctypes.Structure):
+    _fields_ = [("graph", ctypes.c_void_p), ("replica", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("spins_out", ctypes.c_void_p), ("magnetization", ctypes.c_int64),
+                ("cut_weighted", ctypes.c_int64)]
+
+
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("n_colours", ctypes.c_int32), ("nnz", ctypes.c_int64),
                 ("max_abs_wdeg", ctypes.c_int64), ("max_degree", ctypes.c_int32), ("pad", ctypes.c_int32)]
@@ -96,6 +103,13 @@ SIGNATURES = {
     "gdi_colour_csr": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
     "gdi_threshold_table": (ctypes.c_int, [_P, ctypes.c_uint32, ctypes.c_int32, _P]),
     "gdi_philox4x32_10": (ctypes.c_int, [ctypes.c_uint64, _P, _P]),
+    "gdi_anneal_batch": (ctypes.c_int, [ctypes.POINTER(Instance), ctypes.c_uint32, ctypes.POINTER(Schedule),
+                                        ctypes.c_uint64, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)]),
+    "gdi_anneal_batch_dev": (ctypes.c_int, [ctypes.POINTER(Instance), ctypes.c_uint32, ctypes.POINTER(Schedule),
+                                            ctypes.c_uint64, ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)]),
+    "gdi_autotune_batch": (ctypes.c_int, [ctypes.POINTER(Instance), ctypes.c_uint32, ctypes.POINTER(Schedule),
+                                          ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(Tuning),
+                                          ctypes.POINTER(ctypes.c_double)]),
     "gdi_last_error": (ctypes.c_char_p, []),
     "gdi_version": (ctypes.c_int, []),
 }
@@ -249,6 +263,54 @@ def philox4x32_10(seed: int, ctr) -> np.ndarray:
     out = np.zeros(4, dtype=np.uint32)
     _check(lib().gdi_philox4x32_10(ctypes.c_uint64(seed), _ptr(c), _ptr(out)))
     return out
+
+
+def anneal_batch(items, temps, seed: int, A: int = 1, B: int = 1, mode: int = BAL_GATED, tune: dict | None = None,
+                 outputs: bool = True, device_outputs=None) -> dict:
+    """gdi_anneal_batch over items = [(handle, n, replica), ...].
+
+    Returns dict(spins=[arrays or None], M=[...], cut=[...], kernel_ms). With
+    device_outputs (a list of device pointers) the spins land there instead.
+    """
+    k = len(items)
+    arr = (Instance * k)()
+    outs = []
+    for i, (h, n, rep) in enumerate(items):
+        arr[i].graph = h
+        arr[i].replica = rep
+        if device_outputs is not None:
+            arr[i].spins_out = device_outputs[i]
+            outs.append(None)
+        elif outputs:
+            o = np.zeros(n, dtype=np.int8)
+            outs.append(o)
+            arr[i].spins_out = o.ctypes.data
+        else:
+            outs.append(None)
+            arr[i].spins_out = None
+    s, T = _schedule(temps, A, B, 0, mode, 0, None, None, None)
+    t = None if tune is None else ctypes.byref(Tuning(tune.get("scope", 0), tune.get("block", 0), tune.get("grid", 0),
+                                                       tune.get("lanes_per_node", 0), 0, 0))
+    ms = ctypes.c_double()
+    fn = lib().gdi_anneal_batch_dev if device_outputs is not None else lib().gdi_anneal_batch
+    _check(fn(arr, k, ctypes.byref(s), ctypes.c_uint64(seed), t, ctypes.byref(ms)))
+    return dict(spins=outs, M=[arr[i].magnetization for i in range(k)], cut=[arr[i].cut_weighted for i in range(k)],
+                kernel_ms=ms.value)
+
+
+def autotune_batch(items, temps, seed: int, probe_sweeps: int, A: int = 1, B: int = 1, mode: int = BAL_GATED) -> tuple:
+    """gdi_autotune_batch: returns (tuning dict, probe ms)."""
+    k = len(items)
+    arr = (Instance * k)()
+    for i, (h, n, rep) in enumerate(items):
+        arr[i].graph = h
+        arr[i].replica = rep
+    s, T = _schedule(temps, A, B, 0, mode, 0, None, None, None)
+    best = Tuning()
+    ms = ctypes.c_double()
+    _check(lib().gdi_autotune_batch(arr, k, ctypes.byref(s), ctypes.c_uint64(seed), probe_sweeps, ctypes.byref(best),
+                                    ctypes.byref(ms)))
+    return dict(block=best.block, grid=best.grid, lanes_per_node=best.lanes_per_node), ms.value
 
 
 class Annealer:

@@ -10,6 +10,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -449,17 +451,13 @@ int build_halo(gdi_graph *g, int32_t G, int lds_budget)
     return GDI_OK;
 }
 
-// Threshold table for the schedule, cached on the handle by temperature content.
-int ensure_table(gdi_graph *g, const gdi_schedule *s, int64_t de_max)
+// Metropolis threshold table for a schedule: rows t < S, entries d = 0..K where K is
+// the largest d <= de_max whose threshold is non-zero at some sweep.
+int build_table(const double *temps, uint32_t S, int64_t de_max, int32_t *K_out, std::vector<uint32_t> &tab)
 {
-    const uint32_t S = s->n_sweeps;
-    if (g->thr_K >= 0 && g->thr_demax == de_max && g->thr_key.size() == S &&
-        std::memcmp(g->thr_key.data(), s->temps, S * sizeof(double)) == 0)
-        return GDI_OK;
-    // width K: largest d <= de_max with a non-zero threshold at some sweep
     int64_t K = 0;
     for (uint32_t t = 0; t < S; ++t) {
-        const double T = s->temps[t];
+        const double T = temps[t];
         // thr(d) >= 1 iff 2^32 exp(-d/T) >= 1, i.e. d <= 32 ln2 T; probe around that bound exactly
         int64_t d = (int64_t)std::min<double>((double)de_max, std::floor(32.0 * 0.6931471805599453 * T) + 2.0);
         if (threshold_of(d, T) != 0) {
@@ -471,18 +469,33 @@ int ensure_table(gdi_graph *g, const gdi_schedule *s, int64_t de_max)
     }
     if (K > (int64_t)64 * 1024 * 1024 / std::max<uint32_t>(S, 1))
         return fail(GDI_ERANGE, "threshold table too large (temperatures too high for the graph size)");
-    std::vector<uint32_t> tab((size_t)S * (size_t)(K + 1));
+    tab.assign((size_t)S * (size_t)(K + 1), 0u);
     for (uint32_t t = 0; t < S; ++t) {
         uint32_t *row = tab.data() + (size_t)t * (size_t)(K + 1);
         row[0] = 0xFFFFFFFFu;
-        for (int64_t d = 1; d <= K; ++d) row[d] = threshold_of(d, s->temps[t]);
+        for (int64_t d = 1; d <= K; ++d) row[d] = threshold_of(d, temps[t]);
     }
+    *K_out = (int32_t)K;
+    return GDI_OK;
+}
+
+// Threshold table for the schedule, cached on the handle by temperature content.
+int ensure_table(gdi_graph *g, const gdi_schedule *s, int64_t de_max)
+{
+    const uint32_t S = s->n_sweeps;
+    if (g->thr_K >= 0 && g->thr_demax == de_max && g->thr_key.size() == S &&
+        std::memcmp(g->thr_key.data(), s->temps, S * sizeof(double)) == 0)
+        return GDI_OK;
+    std::vector<uint32_t> tab;
+    int32_t K = 0;
+    int rc = build_table(s->temps, S, de_max, &K, tab);
+    if (rc) return rc;
     HIP_TRY(g->d_thr.reserve(tab.size()), "hipMalloc thresholds");
     HIP_TRY(hipMemcpyAsync(g->d_thr.p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, g->stream),
             "upload thresholds");
     HIP_TRY(hipStreamSynchronize(g->stream), "upload thresholds");
     g->thr_key.assign(s->temps, s->temps + S);
-    g->thr_K = (int32_t)K;
+    g->thr_K = K;
     g->thr_demax = de_max;
     return GDI_OK;
 }
@@ -692,6 +705,256 @@ int cut_impl(gdi_graph *g, const int8_t *spins, bool dev, int64_t *cw, int64_t *
     return GDI_OK;
 }
 
+// ------------------------------------------------------------------ batched form
+std::mutex g_tune_mu;
+std::map<std::string, gdi_tuning> g_tune_cache;
+
+std::string batch_key(const gdi_instance *inst, uint32_t n_inst)
+{
+    int64_t sn = 0, snnz = 0;
+    int32_t mx = 0, mc = 0;
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        sn += inst[i].graph->n;
+        snnz += inst[i].graph->nnz;
+        mx = std::max(mx, inst[i].graph->n_pad);
+        mc = std::max(mc, inst[i].graph->C);
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    return std::to_string(dev) + ":" + std::to_string(n_inst) + ":" + std::to_string(sn) + ":" +
+           std::to_string(snnz) + ":" + std::to_string(mx) + ":" + std::to_string(mc);
+}
+
+int check_batch(const gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s)
+{
+    if (!inst || n_inst == 0) return fail(GDI_EINVAL, "empty batch");
+    if (!s || !s->temps || s->n_sweeps < 1) return fail(GDI_EINVAL, "bad schedule");
+    if (s->start_sweep != 0 || s->init_spins || s->trace_m || s->trace_cut)
+        return fail(GDI_EINVAL, "batched anneals start fresh and take no traces");
+    if (s->balance_mode > GDI_BAL_SNAPSHOT) return fail(GDI_EINVAL, "unknown balance_mode");
+    for (uint32_t t = 0; t < s->n_sweeps; ++t)
+        if (!(s->temps[t] > 0.0)) return fail(GDI_EINVAL, "temperatures must be > 0");
+    for (uint32_t i = 0; i < n_inst; ++i)
+        if (!inst[i].graph) return fail(GDI_EINVAL, "NULL graph in batch");
+    return GDI_OK;
+}
+
+// One batched launch. probe_S > 0 runs only the first probe_S sweeps and writes no
+// outputs (autotuning); otherwise results go to inst[].
+int run_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed, const gdi_tuning &tn,
+              bool dev_out, uint32_t probe_S, double *kernel_ms)
+{
+    int rc = check_batch(inst, n_inst, s);
+    if (rc) return rc;
+    for (uint32_t i = 0; i < n_inst; ++i)
+        if ((rc = finish_pending(inst[i].graph))) return rc;
+    const uint32_t S = probe_S ? std::min(probe_S, s->n_sweeps) : s->n_sweeps;
+    int64_t de_max = 0;
+    int32_t lds = 0;
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        const gdi_graph *g = inst[i].graph;
+        de_max = std::max<int64_t>(de_max, std::llabs((long long)s->B) * g->max_abs_wdeg +
+                                               4 * std::llabs((long long)s->A) * ((int64_t)g->n + 1));
+        lds = std::max(lds, gdi_batch_lds_bytes(g->n_pad, g->C));
+    }
+    if (de_max >= (int64_t(1) << 31)) return fail(GDI_ERANGE, "|B|*max_wdeg + 4|A|(n+1) must be < 2^31");
+    int dev = 0, lds_max = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+    if (lds > lds_max) return fail(GDI_ERANGE, "an instance does not fit one workgroup's LDS");
+    const uint32_t block = tn.block ? tn.block : 256u;
+    if (block < 64 || block > GDI_MAX_BLOCK || block % 64) return fail(GDI_EINVAL, "block must be a multiple of 64 in [64, 1024]");
+    if (tn.lanes_per_node && (tn.lanes_per_node > 64 || (tn.lanes_per_node & (tn.lanes_per_node - 1))))
+        return fail(GDI_EINVAL, "lanes_per_node must be a power of two in [1, 64]");
+    int per_cu = 0;
+    int e = gdi_batch_occupancy((int)block, lds, &per_cu);
+    if (e || per_cu < 1) return fail(GDI_EDEVICE, "batched sweep cannot be launched with this block size");
+    uint32_t grid = tn.grid ? tn.grid : (uint32_t)(cus * per_cu);
+    grid = std::max<uint32_t>(1, std::min<uint32_t>(grid, n_inst));
+
+    std::vector<uint32_t> tab;
+    int32_t K = 0;
+    if ((rc = build_table(s->temps, S, de_max, &K, tab))) return rc;
+
+    // longest instances first
+    std::vector<uint32_t> order(n_inst);
+    for (uint32_t i = 0; i < n_inst; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        const int64_t wx = inst[x].graph->nnz + inst[x].graph->n, wy = inst[y].graph->nnz + inst[y].graph->n;
+        return wx > wy;
+    });
+    DevBuf<GdiBatchInstance> d_inst;
+    DevBuf<uint64_t> d_queue;
+    DevBuf<int64_t> d_res;
+    DevBuf<int8_t> d_out;
+    DevBuf<uint32_t> d_thr;
+    struct Release {
+        DevBuf<GdiBatchInstance> &a; DevBuf<uint64_t> &b; DevBuf<int64_t> &c; DevBuf<int8_t> &d; DevBuf<uint32_t> &e;
+        ~Release() { a.release(); b.release(); c.release(); d.release(); e.release(); }
+    } rel{d_inst, d_queue, d_res, d_out, d_thr};
+    std::vector<size_t> out_off(n_inst, 0);
+    size_t out_total = 0;
+    if (!probe_S && !dev_out)
+        for (uint32_t i = 0; i < n_inst; ++i) {
+            out_off[i] = out_total;
+            if (inst[i].spins_out) out_total += (size_t)inst[i].graph->n;
+        }
+    HIP_TRY(d_inst.reserve(n_inst), "hipMalloc batch");
+    HIP_TRY(d_queue.reserve(1), "hipMalloc batch");
+    HIP_TRY(d_res.reserve(2 * (size_t)n_inst), "hipMalloc batch");
+    HIP_TRY(d_thr.reserve(tab.size()), "hipMalloc batch thresholds");
+    if (out_total) HIP_TRY(d_out.reserve(out_total), "hipMalloc batch outputs");
+    std::vector<GdiBatchInstance> h_inst(n_inst);
+    for (uint32_t q = 0; q < n_inst; ++q) {
+        const uint32_t i = order[q];
+        const gdi_graph *g = inst[i].graph;
+        GdiBatchInstance &b = h_inst[q];
+        b.rp = g->d_rp.p;
+        b.adj = g->d_adj.p;
+        b.orig = g->d_orig.p;
+        b.cbeg = g->d_cbeg.p;
+        b.csz = g->d_csz.p;
+        b.out = nullptr;
+        if (!probe_S && inst[i].spins_out) b.out = dev_out ? inst[i].spins_out : d_out.p + out_off[i];
+        b.result = d_res.p + 2 * (size_t)i;
+        b.n = g->n;
+        b.n_pad = g->n_pad;
+        b.C = g->C;
+        b.lanes = tn.lanes_per_node ? (int32_t)tn.lanes_per_node
+                                    : lanes_for_degree(g->n ? (double)g->nnz / g->n : 0.0);
+        b.replica = inst[i].replica;
+        b.pad = 0;
+    }
+    hipStream_t st = inst[0].graph->stream;
+    HIP_TRY(hipMemcpyAsync(d_inst.p, h_inst.data(), h_inst.size() * sizeof(GdiBatchInstance), hipMemcpyHostToDevice, st),
+            "upload batch");
+    HIP_TRY(hipMemcpyAsync(d_thr.p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, st), "upload thresholds");
+    if ((e = gdi_launch_fill_u64(d_queue.p, 1, st))) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
+    GdiBatchArgs ba{};
+    ba.inst = d_inst.p;
+    ba.queue = reinterpret_cast<int32_t *>(d_queue.p);
+    ba.thr = d_thr.p;
+    ba.n_inst = (int32_t)n_inst;
+    ba.K = K;
+    ba.S = S;
+    ba.A4 = 4 * s->A;
+    ba.B = s->B;
+    ba.key0 = (uint32_t)seed;
+    ba.key1 = (uint32_t)(seed >> 32);
+    ba.snapshot = s->balance_mode == GDI_BAL_SNAPSHOT ? 1u : 0u;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
+    struct Ev {
+        hipEvent_t &a, &b;
+        ~Ev() { if (a) (void)hipEventDestroy(a); if (b) (void)hipEventDestroy(b); }
+    } ev{e0, e1};
+    HIP_TRY(hipEventRecord(e0, st), "hipEventRecord");
+    if ((e = gdi_launch_sweep_batch(ba, (int)grid, (int)block, lds, st)))
+        return fail(GDI_EDEVICE, std::string("batched sweep launch: ") + gdi_hip_error_string(e));
+    HIP_TRY(hipEventRecord(e1, st), "hipEventRecord");
+    HIP_TRY(hipStreamSynchronize(st), "batched sweep");
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    if (kernel_ms) *kernel_ms = ms;
+    if (probe_S) return GDI_OK;
+    std::vector<int64_t> res(2 * (size_t)n_inst);
+    HIP_TRY(hipMemcpy(res.data(), d_res.p, res.size() * 8, hipMemcpyDeviceToHost), "download batch results");
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        inst[i].magnetization = res[2 * i];
+        inst[i].cut_weighted = res[2 * i + 1];
+    }
+    if (out_total) {
+        std::vector<int8_t> h(out_total);
+        HIP_TRY(hipMemcpy(h.data(), d_out.p, out_total, hipMemcpyDeviceToHost), "download batch spins");
+        for (uint32_t i = 0; i < n_inst; ++i)
+            if (inst[i].spins_out) std::memcpy(inst[i].spins_out, h.data() + out_off[i], (size_t)inst[i].graph->n);
+    }
+    return GDI_OK;
+}
+
+int autotune_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed, uint32_t probe,
+                   gdi_tuning *best, double *best_ms)
+{
+    int rc = check_batch(inst, n_inst, s);
+    if (rc) return rc;
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
+    probe = std::max<uint32_t>(1, std::min(probe, s->n_sweeps));
+    gdi_tuning cur{};
+    cur.block = 256;
+    double cur_ms = 1e300;
+    auto timed = [&](const gdi_tuning &t, double *ms) -> int {
+        double a = 0, b = 0;
+        int r = run_batch(inst, n_inst, s, seed, t, false, probe, &a);  // the first run also warms caches
+        if (r) return r;
+        r = run_batch(inst, n_inst, s, seed, t, false, probe, &b);
+        if (r) return r;
+        *ms = std::min(a, b);
+        return GDI_OK;
+    };
+    // coordinate descent: block size, then lanes per node, then workgroups per CU
+    const uint32_t blocks[] = {128, 256, 512, 1024};
+    const uint32_t lanes[] = {0, 1, 2, 4, 8, 16, 32};
+    for (uint32_t b : blocks) {
+        gdi_tuning t = cur;
+        t.block = b;
+        double ms = 0;
+        int r = timed(t, &ms);
+        if (r == GDI_EDEVICE) continue;
+        if (r) return r;
+        if (ms < cur_ms) { cur_ms = ms; cur = t; }
+    }
+    for (uint32_t l : lanes) {
+        gdi_tuning t = cur;
+        t.lanes_per_node = l;
+        if (l > t.block) continue;
+        double ms = 0;
+        int r = timed(t, &ms);
+        if (r) return r;
+        if (ms < cur_ms) { cur_ms = ms; cur = t; }
+    }
+    for (uint32_t per : {1u, 2u, 4u, 8u}) {
+        gdi_tuning t = cur;
+        t.grid = per * (uint32_t)cus;
+        double ms = 0;
+        int r = timed(t, &ms);
+        if (r) return r;
+        if (ms < cur_ms) { cur_ms = ms; cur = t; }
+    }
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[batch_key(inst, n_inst)] = cur;
+    return GDI_OK;
+}
+
+int anneal_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed, const gdi_tuning *tune,
+                 double *kernel_ms, bool dev_out)
+{
+    int rc = check_batch(inst, n_inst, s);
+    if (rc) return rc;
+    gdi_tuning t{};
+    if (tune) {
+        t = *tune;
+    } else {
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(batch_key(inst, n_inst));
+            if (it != g_tune_cache.end()) { t = it->second; have = true; }
+        }
+        if (!have) {
+            double ms = 0;
+            rc = autotune_batch(inst, n_inst, s, seed, std::max<uint32_t>(1, s->n_sweeps / 50), &t, &ms);
+            if (rc) return rc;
+        }
+    }
+    return run_batch(inst, n_inst, s, seed, t, dev_out, 0, kernel_ms);
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -847,6 +1110,37 @@ int gdi_cut_dev(gdi_graph *g, const int8_t *d_spins, int64_t *cut_weighted, int6
 {
     try {
         return cut_impl(g, d_spins, true, cut_weighted, cut_edges, magnetization);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_anneal_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed,
+                     const gdi_tuning *tune, double *kernel_ms)
+{
+    try {
+        return anneal_batch(inst, n_inst, s, seed, tune, kernel_ms, false);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_anneal_batch_dev(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed,
+                         const gdi_tuning *tune, double *kernel_ms)
+{
+    try {
+        return anneal_batch(inst, n_inst, s, seed, tune, kernel_ms, true);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_autotune_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed,
+                       uint32_t probe_sweeps, gdi_tuning *best, double *best_ms)
+{
+    if (!best) return fail(GDI_EINVAL, "NULL best");
+    try {
+        return autotune_batch(inst, n_inst, s, seed, probe_sweeps, best, best_ms);
     } catch (const std::bad_alloc &) {
         return fail(GDI_ENOMEM, "out of host memory");
     }

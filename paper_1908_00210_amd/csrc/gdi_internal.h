@@ -74,6 +74,31 @@ struct GdiHaloArgs {
     int32_t thr_in_lds;        // 1: the current and next threshold rows are staged in LDS
 };
 
+// Batched form: one instance (graph, replica) per queue entry.
+struct GdiBatchInstance {
+    const int32_t *rp;
+    const int2 *adj;
+    const int32_t *orig;
+    const int32_t *cbeg;
+    const int32_t *csz;
+    int8_t *out;               // n spins in original order (device) or null
+    int64_t *result;           // [0] final M, [1] tracked weighted cut
+    int32_t n, n_pad, C, lanes;
+    uint32_t replica, pad;
+};
+
+struct GdiBatchArgs {
+    const GdiBatchInstance *inst;  // queue order
+    int32_t *queue;                // next instance to take (zeroed before launch)
+    const uint32_t *thr;           // S rows of (K+1) thresholds
+    int32_t n_inst;
+    int32_t K;
+    uint32_t S;
+    int32_t A4, B;
+    uint32_t key0, key1;
+    uint32_t snapshot;
+};
+
 // host-side launchers (gdi_kernels.hip)
 int gdi_launch_init_spins(const int32_t *orig, const int8_t *init_orig, int8_t *spin, int32_t n_pad,
                           uint32_t key0, uint32_t key1, uint32_t replica, void *stream);
@@ -92,4 +117,7 @@ int gdi_launch_sweep_halo(const GdiHaloArgs &h, int grid, int block, void *strea
 int gdi_halo_lds_bytes(int32_t lds_words, int32_t C, int32_t thr_words);
 int gdi_halo_capacity(int block, int lds_bytes, int *max_grid);
 int gdi_wg_lds_bytes(int32_t n_pad, int32_t C, int spins_in_lds);
+int gdi_batch_lds_bytes(int32_t n_pad, int32_t C);
+int gdi_launch_sweep_batch(const GdiBatchArgs &ba, int grid, int block, int lds_bytes, void *stream);
+int gdi_batch_occupancy(int block, int lds_bytes, int *per_cu);
 const char *gdi_hip_error_string(int code);

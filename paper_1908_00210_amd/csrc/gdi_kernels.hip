@@ -158,26 +158,18 @@ __device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t 
 }
 
 // ------------------------------------------------------------------ workgroup scope
-template <int L, bool SPIN_LDS>
-__global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_wg(GdiSweepArgs a)
+// All sweeps of one instance inside one workgroup: phases are separated by
+// s_barrier, dM is summed in an LDS triple buffer (one barrier per phase).
+// sp points to the instance's spins (LDS, or global for large instances),
+// Psh to its per-class +1 counts in LDS, acc to three zeroed LDS words.
+template <int L>
+__device__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp, int32_t *Psh, int32_t *acc, int32_t &M,
+                              int64_t &dcut_total)
 {
-    extern __shared__ int32_t dyn[];
-    __shared__ int32_t acc[3];
-    int32_t *Psh = dyn;
-    const int c_round = (a.C + 3) & ~3;
-    int8_t *sp = SPIN_LDS ? reinterpret_cast<int8_t *>(dyn + c_round) : a.spin;
-
     const int tid = threadIdx.x;
     const int nth = blockDim.x;
-    for (int i = tid; i < a.C; i += nth) Psh[i] = a.P[i];
-    if (SPIN_LDS)
-        for (int i = tid; i < a.n_pad; i += nth) sp[i] = a.spin[i];
-    if (tid < 3) acc[tid] = 0;
-    int32_t M = (int32_t)a.state[0];
-    __syncthreads();
-
     const int sub = tid / L, lane = tid % L, nsub = nth / L;
-    int64_t dcut = 0, dcut_total = 0;
+    int64_t dcut = 0;
     uint32_t p = 0;
     for (uint32_t t = a.t0; t < a.S; ++t) {
         const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)(a.K + 1);
@@ -215,6 +207,29 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_wg(GdiSweepArgs a)
         }
     }
     dcut_total += dcut;
+}
+
+template <int L, bool SPIN_LDS>
+__global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_wg(GdiSweepArgs a)
+{
+    extern __shared__ int32_t dyn[];
+    __shared__ int32_t acc[3];
+    int32_t *Psh = dyn;
+    const int c_round = (a.C + 3) & ~3;
+    int8_t *sp = SPIN_LDS ? reinterpret_cast<int8_t *>(dyn + c_round) : a.spin;
+
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    for (int i = tid; i < a.C; i += nth) Psh[i] = a.P[i];
+    if (SPIN_LDS)
+        for (int i = tid; i < a.n_pad; i += nth) sp[i] = a.spin[i];
+    if (tid < 3) acc[tid] = 0;
+    int32_t M = (int32_t)a.state[0];
+    __syncthreads();
+
+    int64_t dcut_total = 0;
+    wg_run_sweeps<L>(a, sp, Psh, acc, M, dcut_total);
+
     __syncthreads();
     if (SPIN_LDS)
         for (int i = tid; i < a.n_pad; i += nth) a.spin[i] = sp[i];
@@ -222,6 +237,124 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_wg(GdiSweepArgs a)
     if (tid == 0) a.state[0] = M;
     const int64_t w = wave_sum_i64(dcut_total);
     if ((tid & 63) == 0 && w != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)w);
+}
+
+// ------------------------------------------------------------------ batched form
+// One persistent launch over many independent instances (graph, replica): each
+// workgroup takes the next instance from an atomic queue (the host orders the
+// queue longest first), builds its initial state in LDS (Philox spins, M, per-class
+// counts, cut), runs every sweep with the same per-phase code as k_sweep_wg, and
+// writes spins (original order), M and the tracked cut. Workgroups never wait on
+// each other, so the launch needs no co-residency and always drains.
+__device__ __forceinline__ int32_t class_of(const int32_t *cbeg, int32_t C, int32_t v)
+{
+    int32_t lo = 0, hi = C - 1;  // last c with cbeg[c] <= v
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (cbeg[mid] <= v) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_batch(GdiBatchArgs ba)
+{
+    extern __shared__ int32_t dyn[];
+    __shared__ int32_t acc[3];
+    __shared__ int32_t next_idx;
+    __shared__ int64_t red[2];
+    const int tid = threadIdx.x;
+    const int nth = blockDim.x;
+    for (;;) {
+        if (tid == 0) next_idx = atomicAdd(ba.queue, 1);
+        __syncthreads();
+        const int32_t idx = next_idx;
+        __syncthreads();
+        if (idx >= ba.n_inst) return;
+        const GdiBatchInstance in = ba.inst[idx];
+
+        GdiSweepArgs a{};
+        a.rp = in.rp;
+        a.adj = in.adj;
+        a.orig = in.orig;
+        a.cbeg = in.cbeg;
+        a.csz = in.csz;
+        a.thr = ba.thr;
+        a.n = in.n;
+        a.n_pad = in.n_pad;
+        a.C = in.C;
+        a.K = ba.K;
+        a.t0 = 0;
+        a.S = ba.S;
+        a.A4 = ba.A4;
+        a.B = ba.B;
+        a.key0 = ba.key0;
+        a.key1 = ba.key1;
+        a.replica = in.replica;
+        a.snapshot = ba.snapshot;
+
+        int32_t *Psh = dyn;
+        const int c_round = (in.C + 3) & ~3;
+        int8_t *sp = reinterpret_cast<int8_t *>(dyn + c_round);
+
+        // initial state: Philox spins (counter (id, 0, replica, 1))
+        for (int32_t v = tid; v < in.n_pad; v += nth) {
+            const int32_t o = in.orig[v];
+            int8_t s0 = 0;
+            if (o >= 0) s0 = (philox10((uint32_t)o, 0u, in.replica, 1u, ba.key0, ba.key1).w0 & 1u) ? 1 : -1;
+            sp[v] = s0;
+        }
+        for (int i = tid; i < in.C; i += nth) Psh[i] = 0;
+        if (tid < 3) acc[tid] = 0;
+        if (tid < 2) red[tid] = 0;
+        __syncthreads();
+        int64_t m = 0, cw = 0;
+        for (int32_t v = tid; v < in.n_pad; v += nth) {
+            const int32_t s0 = sp[v];
+            if (s0 == 0) continue;
+            m += s0;
+            if (s0 > 0) atomicAdd(&Psh[class_of(in.cbeg, in.C, v)], 1);
+            for (int32_t k = in.rp[v]; k < in.rp[v + 1]; ++k) {
+                const int2 e = in.adj[k];
+                if (sp[e.x] != s0) cw += e.y;
+            }
+        }
+        m = wave_sum_i64(m);
+        cw = wave_sum_i64(cw);
+        if ((tid & 63) == 0) {
+            if (m) atomicAdd((unsigned long long *)&red[0], (unsigned long long)m);
+            if (cw) atomicAdd((unsigned long long *)&red[1], (unsigned long long)cw);
+        }
+        __syncthreads();
+        int32_t M = (int32_t)red[0];
+        const int64_t cut0 = red[1] / 2;
+
+        int64_t dcut_total = 0;
+        switch (in.lanes) {
+        case 1: wg_run_sweeps<1>(a, sp, Psh, acc, M, dcut_total); break;
+        case 2: wg_run_sweeps<2>(a, sp, Psh, acc, M, dcut_total); break;
+        case 4: wg_run_sweeps<4>(a, sp, Psh, acc, M, dcut_total); break;
+        case 8: wg_run_sweeps<8>(a, sp, Psh, acc, M, dcut_total); break;
+        case 16: wg_run_sweeps<16>(a, sp, Psh, acc, M, dcut_total); break;
+        case 32: wg_run_sweeps<32>(a, sp, Psh, acc, M, dcut_total); break;
+        default: wg_run_sweeps<64>(a, sp, Psh, acc, M, dcut_total); break;
+        }
+        __syncthreads();
+        if (in.out)
+            for (int32_t v = tid; v < in.n_pad; v += nth) {
+                const int32_t o = in.orig[v];
+                if (o >= 0) in.out[o] = sp[v];
+            }
+        if (tid < 2) red[tid] = 0;
+        __syncthreads();
+        const int64_t w = wave_sum_i64(dcut_total);
+        if ((tid & 63) == 0 && w != 0) atomicAdd((unsigned long long *)&red[1], (unsigned long long)w);
+        __syncthreads();
+        if (tid == 0) {
+            in.result[0] = M;
+            in.result[1] = cut0 + red[1];
+        }
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------ grid scope
@@ -947,5 +1080,29 @@ extern "C" int gdi_timing_setup(unsigned long long *buf, int phases)
     return (int)e;
 }
 #endif
+
+int gdi_batch_lds_bytes(int32_t n_pad, int32_t C)
+{
+    return ((C + 3) & ~3) * 4 + n_pad;
+}
+
+int gdi_launch_sweep_batch(const GdiBatchArgs &ba, int grid, int block, int lds_bytes, void *stream)
+{
+    const void *f = (const void *)k_sweep_batch;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e != hipSuccess) return status(e);
+    GdiBatchArgs copy = ba;
+    void *args[] = {&copy};
+    e = hipLaunchKernel(f, dim3(grid), dim3(block), args, (size_t)lds_bytes, (hipStream_t)stream);
+    return status(e);
+}
+
+int gdi_batch_occupancy(int block, int lds_bytes, int *per_cu)
+{
+    const void *f = (const void *)k_sweep_batch;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, block, lds_bytes);
+    return status(e);
+}
 
 const char *gdi_hip_error_string(int code) { return hipGetErrorString((hipError_t)code); }
