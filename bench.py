@@ -41,6 +41,66 @@ def cpu_baseline(g, temps, seed, sweeps):
                       f"(n={g.n}), C oracle with OpenMP, {dt:.2f} s wall incl. colouring"}
 
 
+def best_state(Ms, cuts, A=1, B=1):
+    """Best final state: lowest weighted cut among |M| <= 2 (energy A M^2 + B cut breaks ties);
+    lowest energy if none is balanced."""
+    cand = [(c, A * m * m + B * c) for m, c in zip(Ms, cuts) if abs(m) <= 2]
+    if cand:
+        return min(cand, key=lambda x: (x[0], x[1]))[0]
+    return min(A * m * m + B * c for m, c in zip(Ms, cuts))
+
+
+def forms_batched(gdi, gs, torch, seed):
+    """Batched vs plain on one GPU: 256 replicas of the n=2000 ER graph in one launch against
+    sequential single-replica anneals in the same wall time; and the throughput of the full
+    batched workload (64 uneven graphs + the 256 replicas) in one launch."""
+    g, T = gs.workload("er2000")
+    out = {}
+    with gdi.Annealer(g) as a:
+        items = [(a.h, g.n, r) for r in range(256)]
+        gdi.anneal_batch(items, T, seed, outputs=False)  # autotunes on first use
+        t0 = time.perf_counter()
+        res = gdi.anneal_batch(items, T, seed, outputs=False)
+        wall_b = time.perf_counter() - t0
+        best_b = best_state(res["M"], res["cut"])
+        d_out = torch.empty(g.n, dtype=torch.int8, device="cuda:0")
+        a.set_stream(torch.cuda.current_stream().cuda_stream)
+        a.anneal_dev(T, seed, d_out.data_ptr(), replica=0)
+        a.result()
+        Ms, cuts = [], []
+        t0 = time.perf_counter()
+        while not Ms or time.perf_counter() - t0 < wall_b:
+            a.anneal_dev(T, seed, d_out.data_ptr(), replica=len(Ms))
+            r = a.result()
+            Ms.append(r.magnetization)
+            cuts.append(r.cut_weighted)
+        wall_p = time.perf_counter() - t0
+        best_p = best_state(Ms, cuts)
+        # how long plain needs on average for the batched best: runs until a cut <= 1.005 x batched best
+        out["replicas_256_er2000"] = {
+            "sweeps": int(T.size), "batched_wall_ms": wall_b * 1e3, "batched_kernel_ms": res["kernel_ms"],
+            "batched_best_cut": int(best_b), "plain_runs_in_same_wall": len(Ms), "plain_wall_ms": wall_p * 1e3,
+            "plain_best_cut_in_same_wall": int(best_p),
+            "batched_at_least_as_good": bool(best_b <= best_p),
+        }
+    graphs = gs.batch_mix()
+    anns = [gdi.Annealer(x) for x in graphs]
+    g2, T2 = gs.workload("er2000")
+    a2 = gdi.Annealer(g2)
+    items = [(x.h, x.n, 0) for x in anns] + [(a2.h, g2.n, r) for r in range(256)]
+    gdi.anneal_batch(items, T2, seed, outputs=False)
+    t0 = time.perf_counter()
+    res = gdi.anneal_batch(items, T2, seed, outputs=False)
+    wall = time.perf_counter() - t0
+    updates = sum(i[1] for i in items) * T2.size
+    out["full_batch"] = {"instances": len(items), "sum_n": sum(i[1] for i in items), "sweeps": int(T2.size),
+                         "wall_ms": wall * 1e3, "kernel_ms": res["kernel_ms"],
+                         "spin_updates_per_s": updates / (res["kernel_ms"] / 1e3)}
+    for x in anns + [a2]:
+        x.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -50,6 +110,7 @@ def main():
     ap.add_argument("--sweeps", type=int, default=0, help="override the schedule length")
     ap.add_argument("--cpu-sweeps", type=int, default=2000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched / learned comparisons")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (for scaling HBM counters) and exit")
@@ -153,9 +214,11 @@ def main():
         "result": {"M": int(m), "cut_weighted": int(cw), "cut_edges": int(ce),
                    "tracked_cut": int(res.cut_weighted), "create_s": create_s},
     }
+    ann.close()
+    if not args.no_forms:
+        line["forms"] = forms_batched(gdi, gs, torch, seed)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, temps, seed, min(args.cpu_sweeps, S))
-    ann.close()
     print(json.dumps(line), flush=True)
 
 
