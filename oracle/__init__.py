@@ -75,7 +75,7 @@ def lib():
                                         ctypes.c_int32]
         L.oracle_flip_delta.restype = ctypes.c_int64
         L.oracle_anneal.argtypes = [ctypes.c_int32, P, P, P, P, ctypes.POINTER(_Params), P, P, P, P,
-                                    P, P, P, P]
+                                    P, P, P, P, P, P]
         L.oracle_anneal.restype = ctypes.c_int
         L.oracle_max_threads.restype = ctypes.c_int
         _lib = L
@@ -142,8 +142,12 @@ def flip_delta(g, spins, A: int, B: int, i: int) -> int:
 
 def anneal(g, temps, seed: int, A: int = 1, B: int = 1, replica: int = 0, mode: int = MODE_GATED,
            start_sweep: int = 0, init=None, n_threads: int = 0, trace: bool = False,
-           phase_trace: bool = False, phase_spins: bool = False) -> dict:
-    """Runs the oracle schedule; returns a dict with spins, M, cut, C, flips and optional traces."""
+           phase_trace: bool = False, phase_spins: bool = False, skip=None, last_flip=None) -> dict:
+    """Runs the oracle schedule; returns a dict with spins, M, cut, C, flips and optional traces.
+
+    skip (n bools): nodes that make no decision in these sweeps; last_flip (int32
+    array of n, updated in place): sweep of each node's last flip.
+    """
     T = np.ascontiguousarray(temps, dtype=np.float64)
     S = T.size
     rp, col, w = _i32(g.row_ptr), _i32(g.col), _i32(g.w)
@@ -158,8 +162,12 @@ def anneal(g, temps, seed: int, A: int = 1, B: int = 1, replica: int = 0, mode: 
     pc = np.zeros(S * C, dtype=np.int64) if phase_trace else None
     ps = np.zeros((S * C, g.n), dtype=np.int8) if phase_spins else None
     res = np.zeros(4, dtype=np.int64)
+    sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.uint8)
+    if last_flip is not None and (last_flip.dtype != np.int32 or not last_flip.flags.c_contiguous):
+        raise TypeError("last_flip must be a contiguous int32 array")
     rc = lib().oracle_anneal(g.n, _p(rp), _p(col), _p(w), _p(T), ctypes.byref(prm), _p(init_a),
-                             _p(spins), _p(tm), _p(tc), _p(pm), _p(pc), _p(ps), _p(res))
+                             _p(spins), _p(tm), _p(tc), _p(pm), _p(pc), _p(ps), _p(res), _p(sk),
+                             _p(last_flip))
     if rc != 0:
         raise RuntimeError(f"oracle_anneal failed: {rc}")
     out = dict(spins=spins, M=int(res[0]), cut=int(res[1]), C=int(res[2]), flips=int(res[3]))

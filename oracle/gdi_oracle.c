@@ -197,12 +197,16 @@ typedef struct {
  *   phase_m/phase_cut  optional, n_sweeps*C entries: M and cut after each phase
  *   phase_spins optional, n_sweeps*C*n spins after each phase (small n only)
  *   result[0..3] = final M, final cut (tracked), number of colours, total flips
+ *   skip        optional, n bytes: a node with a non-zero byte makes no decision in
+ *               these sweeps (it keeps its spin and draws nothing) but still counts
+ *               in M and in its class's over-side count
+ *   last_flip   optional, n entries, updated in place: the sweep of each node's last flip
  */
 int oracle_anneal(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *w,
                   const double *T, const oracle_params *p, const int8_t *init,
                   int8_t *spins_out, int64_t *trace_m, int64_t *trace_cut,
                   int64_t *phase_m, int64_t *phase_cut, int8_t *phase_spins,
-                  int64_t *result)
+                  int64_t *result, const uint8_t *skip, int32_t *last_flip)
 {
     if (n < 2 || p->n_sweeps < 1 || p->start_sweep < 0 || p->start_sweep > p->n_sweeps)
         return OR_EINVAL;
@@ -292,6 +296,10 @@ int oracle_anneal(int32_t n, const int32_t *row_ptr, const int32_t *col, const i
             #pragma omp parallel for schedule(static) num_threads(p->n_threads > 0 ? p->n_threads : omp_get_max_threads())
             for (int64_t q = cls_off[c]; q < cls_off[c + 1]; ++q) {
                 const int32_t i = members[q];
+                if (skip && skip[i]) {
+                    flip[q] = 0;
+                    continue;
+                }
                 uint32_t ctr[4] = {(uint32_t)i, (uint32_t)t, p->replica, 0u}, x[4];
                 oracle_philox4x32_10(k0, k1, ctr, x);
                 int64_t h = 0;
@@ -320,6 +328,7 @@ int oracle_anneal(int32_t n, const int32_t *row_ptr, const int32_t *col, const i
                 M -= 2 * (int64_t)s[i];
                 P[c] -= s[i];
                 s[i] = (int8_t)-s[i];
+                if (last_flip) last_flip[i] = t;
                 total_flips++;
             }
             if (phase_m) phase_m[(int64_t)t * C + c] = M;

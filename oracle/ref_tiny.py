@@ -52,8 +52,13 @@ def colouring(n, adj):
 
 
 def anneal(n, edges, temps, seed, A=1, B=1, replica=0, gated=True, init=None, start_sweep=0,
-           visit_seed=None):
-    """edges: list of (i, j, w) with i != j, each undirected edge once. Returns (spins, M, cut)."""
+           visit_seed=None, skip=(), last_flip=None):
+    """edges: list of (i, j, w) with i != j, each undirected edge once. Returns (spins, M, cut).
+
+    Nodes in ``skip`` make no decision (their spins stay, they still count in the
+    magnetisation); ``last_flip`` (a list of n ints) receives each flip's sweep.
+    """
+    skip = set(skip)
     adj = [[] for _ in range(n)]
     for i, j, w in edges:
         adj[i].append((j, w))
@@ -79,6 +84,8 @@ def anneal(n, edges, temps, seed, A=1, B=1, replica=0, gated=True, init=None, st
             over = sum(1 for i in classes[c] if s[i] == sg) if sg != 0 else 0
             flips = []
             for i in classes[c]:
+                if i in skip:
+                    continue
                 x = philox4x32_10(seed, (i, t, replica, 0))
                 h = sum(w * s[j] for j, w in adj[i])
                 if gated:
@@ -90,6 +97,8 @@ def anneal(n, edges, temps, seed, A=1, B=1, replica=0, gated=True, init=None, st
                     flips.append(i)
             for i in flips:
                 s[i] = -s[i]
+                if last_flip is not None:
+                    last_flip[i] = t
     M = sum(s)
     cut = sum(w for i, j, w in edges if s[i] != s[j])
     return s, M, cut
