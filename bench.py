@@ -101,6 +101,86 @@ def forms_batched(gdi, gs, torch, seed):
     return out
 
 
+def forms_learned(gdi, gs, torch, seed, k_full=8, p_skip=0.9, heuristic_k=8, replicas=8):
+    """Learned frozen-node proposal on one GPU: collect traces from the plain annealer on
+    the eight training RGGs, train the network with the library's kernels, then on the
+    n=200k evaluation RGG run plain, network and heuristic anneals replica by replica and
+    report the wall time each needs to reach a balanced cut within 0.5% of the best plain
+    cut over the same number of replicas."""
+    import numpy as np
+
+    out = {}
+    S, every, k_label = 2000, 50, k_full - 1
+    T = gs.geometric_temps(3.0, 0.05, S)
+    graphs = gs.training_graphs()
+    snaps = len(range(every - 1, S - k_label, every))
+    rows = sum(g.n for g in graphs) * snaps
+    dx = torch.zeros(rows * 8, dtype=torch.bfloat16, device="cuda:0")
+    dy = torch.zeros(rows, dtype=torch.uint8, device="cuda:0")
+    t0 = time.perf_counter()
+    off = 0
+    for g in graphs:
+        with gdi.Annealer(g) as a:
+            cnt = a.collect_traces(T, seed, every, k_label, dx.data_ptr() + off * 16, dy.data_ptr() + off, snaps)
+        off += cnt * g.n
+    torch.cuda.synchronize()
+    t_collect = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    w, losses = gdi.mlp_train(dx.data_ptr(), dy.data_ptr(), off, gdi.mlp_init(seed), epochs=3, batch=4096, lr=2e-3,
+                              seed=seed)
+    t_train = time.perf_counter() - t0
+    ybar = float(dy[:off].float().mean().item())
+    out["training"] = {"graphs": [g.n for g in graphs], "rows": off, "frozen_fraction": ybar,
+                       "collect_s": t_collect, "train_s": t_train, "epoch_loss": [float(x) for x in losses],
+                       "constant_predictor_loss": float(-(ybar * np.log(ybar) + (1 - ybar) * np.log(1 - ybar)))}
+    del dx, dy
+    g, Te = gs.workload("rgg200k")
+    runs = {}
+    with gdi.Annealer(g) as a:
+        a.anneal(Te[:10], seed)  # warm-up: threshold table, launch choice
+        methods = {
+            "plain": lambda r: a.anneal_learned(Te, seed, k_full, replica=r),
+            "network": lambda r: a.anneal_learned(Te, seed, k_full, replica=r, skip_mode=gdi.SKIP_MLP, weights=w,
+                                                  skip_threshold=p_skip),
+            "heuristic": lambda r: a.anneal_learned(Te, seed, k_full, replica=r, skip_mode=gdi.SKIP_HEURISTIC,
+                                                    heuristic_k=heuristic_k),
+        }
+        # the plain reference: gdi_anneal, one launch per anneal
+        plain_ms, Ms, cuts = [], [], []
+        for r in range(replicas):
+            t0 = time.perf_counter()
+            res = a.anneal(Te, seed, replica=r)
+            plain_ms.append((time.perf_counter() - t0) * 1e3)
+            Ms.append(res["M"])
+            cuts.append(res["cut"])
+        runs["plain_one_launch"] = (plain_ms, Ms, cuts, [0.0] * replicas)
+        for name, fn in methods.items():
+            ms, Ms, cuts, skip = [], [], [], []
+            for r in range(replicas):
+                t0 = time.perf_counter()
+                res = fn(r)
+                ms.append((time.perf_counter() - t0) * 1e3)
+                Ms.append(res["M"])
+                cuts.append(res["cut"])
+                rr = res["result"]
+                skip.append(rr["node_skips"] / max(1, rr["node_skips"] + rr["node_visits"]))
+            runs[name] = (ms, Ms, cuts, skip)
+    best_plain = best_state(runs["plain_one_launch"][1], runs["plain_one_launch"][2])
+    target = best_plain * 1.005 if best_plain >= 0 else best_plain * 0.995
+    for name, (ms, Ms, cuts, skip) in runs.items():
+        reach = None
+        for i, (m, c) in enumerate(zip(Ms, cuts)):
+            if abs(m) <= 2 and c <= target:
+                reach = float(np.sum(ms[:i + 1]))
+                break
+        out[name] = {"mean_ms": float(np.mean(ms)), "best_cut": int(best_state(Ms, cuts)),
+                     "mean_cut": float(np.mean(cuts)), "balanced": int(sum(abs(m) <= 2 for m in Ms)),
+                     "skipped_fraction": float(np.mean(skip)), "ms_to_within_0.5pct_of_plain_best": reach}
+    out["eval"] = {"graph": g.name, "n": g.n, "sweeps": int(Te.size), "replicas": replicas, "k_full": k_full,
+                   "skip_threshold": p_skip, "heuristic_k": heuristic_k, "plain_best_cut": int(best_plain)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,6 +297,7 @@ def main():
     ann.close()
     if not args.no_forms:
         line["forms"] = forms_batched(gdi, gs, torch, seed)
+        line["forms"]["learned_rgg200k"] = forms_learned(gdi, gs, torch, seed)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, temps, seed, min(args.cpu_sweeps, S))
     print(json.dumps(line), flush=True)

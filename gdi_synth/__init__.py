@@ -31,6 +31,7 @@ __all__ = [
     "from_edges",
     "geometric_temps",
     "batch_mix",
+    "training_graphs",
     "workload",
     "WORKLOADS",
 ]
@@ -204,6 +205,18 @@ def batch_mix(n_graphs: int = 64, seed: int = 300, n_lo: int = 800, n_hi: int = 
             out.append(er_graph(n, d / (n - 1), gseed, weights=kind))
         else:
             out.append(rgg_graph(n, d, gseed, weights=kind))
+    return out
+
+
+def training_graphs(n_graphs: int = 8, seed0: int = 200, n_lo: int = 10_000, n_hi: int = 100_000,
+                    mean_degree: float = 8.0) -> list:
+    """Training graphs for the learned proposal: random geometric graphs of mean degree 8,
+    unit weights, n log-uniform in [n_lo, n_hi], graph seeds seed0 .. seed0 + n_graphs - 1."""
+    out = []
+    for k in range(n_graphs):
+        rng = np.random.default_rng(seed0 + k)
+        n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+        out.append(rgg_graph(n, mean_degree, seed0 + k, "unit"))
     return out
 
 

@@ -248,6 +248,97 @@ int gdi_anneal_batch_dev(gdi_instance *inst, uint32_t n_inst, const gdi_schedule
 int gdi_autotune_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed,
                        uint32_t probe_sweeps, gdi_tuning *best, double *best_ms);
 
+/* ------------------------------------------------------------------ learned proposal
+ * A network predicts which nodes stay frozen at the current temperature; masked
+ * sweeps skip them and a full sweep runs every k_full sweeps. The network is
+ * 6 -> 64 -> 64 -> 1 (ReLU, logistic output), BF16 weights and FP32 accumulation
+ * on the GPU (dense layers on MFMA). Per-node features, computed on the device
+ * after each full sweep t (FP32, then rounded to BF16):
+ *   f0 = degree/16, f1 = sum_j |w_ij| / 16, f2 = fraction of neighbours on the other side,
+ *   f3 = clamp(B s_i h_i / T_t, -16, 16) / 4, f4 = min(|4A(1 - s_i M)| / T_t, 64) / 16,
+ *   f5 = min(t - last flip of i, 255) / 64  (last flip = start_sweep - 1 before any flip).
+ * Not in the paper: this is a systems form built on top of its annealer.
+ */
+#define GDI_MLP_FEATURES 6
+#define GDI_MLP_HIDDEN 64
+
+typedef struct {
+    float w1[64][6];           /* hidden x feature */
+    float b1[64];
+    float w2[64][64];          /* output hidden x input hidden */
+    float b2[64];
+    float w3[64];
+    float b3;
+} gdi_mlp_weights;             /* FP32 master weights; the device uses BF16 copies of w1, w2 */
+
+#define GDI_SKIP_NONE 0u       /* every sweep is full (same trajectory as gdi_anneal) */
+#define GDI_SKIP_MLP 1u        /* skip nodes with p(frozen) > skip_threshold */
+#define GDI_SKIP_HEURISTIC 2u  /* skip nodes that did not flip in the last heuristic_k sweeps */
+
+typedef struct {
+    uint32_t k_full;           /* sweeps start_sweep, start_sweep + k_full, ... are full sweeps */
+    uint32_t skip_mode;        /* GDI_SKIP_* */
+    float skip_threshold;      /* GDI_SKIP_MLP: probability threshold in (0, 1) */
+    uint32_t heuristic_k;      /* GDI_SKIP_HEURISTIC */
+    uint8_t *mask_trace;       /* host or NULL: ceil((S - start_sweep) / k_full) x n bytes, original order:
+                                  1 = node skipped in the masked sweeps after that full sweep */
+} gdi_learned_cfg;
+
+typedef struct {
+    int64_t magnetization;
+    int64_t cut_weighted;
+    double total_ms;           /* device time of all launches of the anneal */
+    uint64_t node_visits;      /* decisions made */
+    uint64_t node_skips;       /* decisions skipped by the proposal */
+} gdi_learned_result;
+
+/*
+ * gdi_anneal_learned -- the schedule of gdi_anneal (same RNG counters, same
+ * acceptance) with nodes flagged by the proposal skipped in the masked sweeps: a
+ * skipped node keeps its spin and draws nothing; the phase's magnetisation and
+ * class counts are those of all nodes. w may be NULL unless skip_mode is
+ * GDI_SKIP_MLP. Blocks until spins_out (host, original order) is written.
+ */
+int gdi_anneal_learned(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_mlp_weights *w,
+                       const gdi_learned_cfg *cfg, int8_t *spins_out, gdi_learned_result *res);
+
+/*
+ * gdi_collect_traces -- training data from a plain anneal: after each sweep
+ * t_s = every-1, 2*every-1, ... with t_s + k_label < S, the features of all n
+ * nodes are written to d_x (device, BF16 rows of 8: six features and two zeros,
+ * row = snapshot * n + original id) and d_y (device, 1 = the node does not flip in
+ * sweeps t_s+1 .. t_s+k_label). At most max_snapshots snapshots; *n_snapshots
+ * receives the number written.
+ */
+int gdi_collect_traces(gdi_graph *g, const gdi_schedule *s, uint64_t seed, uint32_t every, uint32_t k_label,
+                       void *d_x, uint8_t *d_y, uint32_t max_snapshots, uint32_t *n_snapshots);
+
+typedef struct {
+    uint32_t epochs;
+    uint32_t batch;            /* minibatch rows */
+    float lr, beta1, beta2, eps;   /* Adam */
+    uint64_t seed;             /* minibatch shuffling */
+} gdi_train_cfg;
+
+/* gdi_mlp_init -- He-uniform initial weights from a seeded splitmix64 stream (host). */
+int gdi_mlp_init(gdi_mlp_weights *w, uint64_t seed);
+
+/*
+ * gdi_mlp_train -- minimise the mean logistic loss on (d_x, d_y) (device rows as
+ * written by gdi_collect_traces) with the library's forward / backward / Adam
+ * kernels; w holds the initial weights and receives the trained ones;
+ * epoch_loss (host, epochs entries) may be NULL. Runs on hip_stream.
+ */
+int gdi_mlp_train(const void *d_x, const uint8_t *d_y, uint64_t n, gdi_mlp_weights *w, const gdi_train_cfg *cfg,
+                  float *epoch_loss, void *hip_stream);
+
+/* gdi_mlp_forward -- logits of n device rows into d_logits (device); for checking the kernels. */
+int gdi_mlp_forward(const gdi_mlp_weights *w, const void *d_x, uint32_t n, float *d_logits, void *hip_stream);
+
+/* gdi_mlp_gradient -- mean logistic loss of n device rows and its gradient (host outputs). */
+int gdi_mlp_gradient(const gdi_mlp_weights *w, const void *d_x, const uint8_t *d_y, uint32_t n,
+                     gdi_mlp_weights *grad, float *loss, void *hip_stream);
+
 /* gdi_last_error -- thread-local message of the last failing call ("" if none). */
 const char *gdi_last_error(void);
 

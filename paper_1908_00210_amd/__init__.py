@@ -20,7 +20,9 @@ __all__ = [
     "SCOPE_GRID", "SCOPE_GRID_FENCED", "Schedule", "Tuning", "Result", "GraphInfo", "create", "destroy", "anneal",
     "anneal_dev", "cut", "cut_dev", "last_result", "set_stream", "set_tuning", "get_info",
     "get_colouring", "colour_csr", "threshold_table", "philox4x32_10", "version", "Annealer",
-    "Instance", "anneal_batch", "autotune_batch",
+    "Instance", "anneal_batch", "autotune_batch", "MLP_PARAMS", "SKIP_NONE", "SKIP_MLP", "SKIP_HEURISTIC",
+    "LearnedCfg", "LearnedResult", "TrainCfg", "anneal_learned", "collect_traces", "mlp_init", "mlp_train",
+    "mlp_forward", "mlp_gradient", "mlp_unflatten",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgdi.so")
@@ -86,6 +88,31 @@ class GraphInfo(ctypes.Structure):
                 ("max_abs_wdeg", ctypes.c_int64), ("max_degree", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
+# network weights travel as one flat float32 array in gdi_mlp_weights order:
+# w1[64][6], b1[64], w2[64][64], b2[64], w3[64], b3
+MLP_PARAMS = 64 * 6 + 64 + 64 * 64 + 64 + 64 + 1
+SKIP_NONE, SKIP_MLP, SKIP_HEURISTIC = 0, 1, 2
+
+
+class LearnedCfg(ctypes.Structure):
+    _fields_ = [("k_full", ctypes.c_uint32), ("skip_mode", ctypes.c_uint32), ("skip_threshold", ctypes.c_float),
+                ("heuristic_k", ctypes.c_uint32), ("mask_trace", ctypes.c_void_p)]
+
+
+class LearnedResult(ctypes.Structure):
+    _fields_ = [("magnetization", ctypes.c_int64), ("cut_weighted", ctypes.c_int64), ("total_ms", ctypes.c_double),
+                ("node_visits", ctypes.c_uint64), ("node_skips", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("seed", ctypes.c_uint64)]
+
+
 # every symbol include/gdi.h declares, with (restype, argtypes)
 _P = ctypes.c_void_p
 SIGNATURES = {
@@ -110,6 +137,14 @@ SIGNATURES = {
     "gdi_autotune_batch": (ctypes.c_int, [ctypes.POINTER(Instance), ctypes.c_uint32, ctypes.POINTER(Schedule),
                                           ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(Tuning),
                                           ctypes.POINTER(ctypes.c_double)]),
+    "gdi_anneal_learned": (ctypes.c_int, [_P, ctypes.POINTER(Schedule), ctypes.c_uint64, _P,
+                                          ctypes.POINTER(LearnedCfg), _P, ctypes.POINTER(LearnedResult)]),
+    "gdi_collect_traces": (ctypes.c_int, [_P, ctypes.POINTER(Schedule), ctypes.c_uint64, ctypes.c_uint32,
+                                          ctypes.c_uint32, _P, _P, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
+    "gdi_mlp_init": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "gdi_mlp_train": (ctypes.c_int, [_P, _P, ctypes.c_uint64, _P, ctypes.POINTER(TrainCfg), _P, _P]),
+    "gdi_mlp_forward": (ctypes.c_int, [_P, _P, ctypes.c_uint32, _P, _P]),
+    "gdi_mlp_gradient": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint32, _P, ctypes.POINTER(ctypes.c_float), _P]),
     "gdi_last_error": (ctypes.c_char_p, []),
     "gdi_version": (ctypes.c_int, []),
 }
@@ -313,6 +348,85 @@ def autotune_batch(items, temps, seed: int, probe_sweeps: int, A: int = 1, B: in
     return dict(block=best.block, grid=best.grid, lanes_per_node=best.lanes_per_node), ms.value
 
 
+def _weights(w) -> np.ndarray:
+    a = np.ascontiguousarray(w, dtype=np.float32)
+    if a.size != MLP_PARAMS:
+        raise ValueError(f"network weights must hold {MLP_PARAMS} floats")
+    return a
+
+
+def mlp_unflatten(w) -> dict:
+    """Views of a flat weight array as w1 (64x6), b1, w2 (64x64), b2, w3, b3."""
+    w = np.asarray(w)
+    o, d = 0, {}
+    for name, shape in (("w1", (64, 6)), ("b1", (64,)), ("w2", (64, 64)), ("b2", (64,)), ("w3", (64,)), ("b3", ())):
+        k = int(np.prod(shape)) if shape else 1
+        d[name] = w[o:o + k].reshape(shape) if shape else w[o]
+        o += k
+    return d
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    w = np.zeros(MLP_PARAMS, dtype=np.float32)
+    _check(lib().gdi_mlp_init(_ptr(w), ctypes.c_uint64(seed)))
+    return w
+
+
+def anneal_learned(h, n: int, temps, seed: int, k_full: int, skip_mode: int = SKIP_NONE, weights=None,
+                   skip_threshold: float = 0.5, heuristic_k: int = 1, A: int = 1, B: int = 1, replica: int = 0,
+                   mode: int = BAL_GATED, start_sweep: int = 0, init=None, mask_trace: bool = False) -> dict:
+    """gdi_anneal_learned: dict(spins, M, cut, result, [masks (blocks x n uint8)])."""
+    T = np.ascontiguousarray(temps, dtype=np.float64)
+    init_a = None if init is None else np.ascontiguousarray(init, dtype=np.int8)
+    s, T = _schedule(T, A, B, replica, mode, start_sweep, init_a, None, None)
+    w = None if weights is None else _weights(weights)
+    rows = (T.size - start_sweep + k_full - 1) // k_full if k_full > 0 else 0
+    masks = np.zeros((rows, n), dtype=np.uint8) if mask_trace else None
+    cfg = LearnedCfg(k_full, skip_mode, skip_threshold, heuristic_k, None if masks is None else masks.ctypes.data)
+    out = np.zeros(n, dtype=np.int8)
+    res = LearnedResult()
+    _check(lib().gdi_anneal_learned(h, ctypes.byref(s), ctypes.c_uint64(seed), _ptr(w), ctypes.byref(cfg), _ptr(out),
+                                    ctypes.byref(res)))
+    d = dict(spins=out, M=res.magnetization, cut=res.cut_weighted, result=res.as_dict())
+    if mask_trace:
+        d["masks"] = masks
+    return d
+
+
+def collect_traces(h, temps, seed: int, every: int, k_label: int, d_x: int, d_y: int, max_snapshots: int,
+                   A: int = 1, B: int = 1, replica: int = 0, mode: int = BAL_GATED) -> int:
+    """gdi_collect_traces into device buffers (d_x: max_snapshots*n*8 bf16, d_y: max_snapshots*n bytes)."""
+    s, T = _schedule(temps, A, B, replica, mode, 0, None, None, None)
+    cnt = ctypes.c_uint32()
+    _check(lib().gdi_collect_traces(h, ctypes.byref(s), ctypes.c_uint64(seed), every, k_label, ctypes.c_void_p(d_x),
+                                    ctypes.c_void_p(d_y), max_snapshots, ctypes.byref(cnt)))
+    return cnt.value
+
+
+def mlp_train(d_x: int, d_y: int, n: int, weights, epochs: int, batch: int, lr: float = 1e-3, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8, seed: int = 0, stream: int | None = None) -> tuple:
+    """gdi_mlp_train: returns (trained flat weights, per-epoch mean loss)."""
+    w = _weights(weights).copy()
+    cfg = TrainCfg(epochs, batch, lr, beta1, beta2, eps, seed)
+    losses = np.zeros(epochs, dtype=np.float32)
+    _check(lib().gdi_mlp_train(ctypes.c_void_p(d_x), ctypes.c_void_p(d_y), ctypes.c_uint64(n), _ptr(w),
+                               ctypes.byref(cfg), _ptr(losses), stream))
+    return w, losses
+
+
+def mlp_forward(weights, d_x: int, n: int, d_logits: int, stream: int | None = None):
+    _check(lib().gdi_mlp_forward(_ptr(_weights(weights)), ctypes.c_void_p(d_x), n, ctypes.c_void_p(d_logits), stream))
+
+
+def mlp_gradient(weights, d_x: int, d_y: int, n: int, stream: int | None = None) -> tuple:
+    """gdi_mlp_gradient: (flat gradient, mean loss)."""
+    g = np.zeros(MLP_PARAMS, dtype=np.float32)
+    loss = ctypes.c_float()
+    _check(lib().gdi_mlp_gradient(_ptr(_weights(weights)), ctypes.c_void_p(d_x), ctypes.c_void_p(d_y), n, _ptr(g),
+                                  ctypes.byref(loss), stream))
+    return g, loss.value
+
+
 class Annealer:
     """Owns one gdi_graph handle for a graph with fields n, row_ptr, col, w."""
 
@@ -358,6 +472,12 @@ class Annealer:
 
     def set_stream(self, stream_ptr):
         set_stream(self.h, stream_ptr)
+
+    def anneal_learned(self, temps, seed, k_full, **kw) -> dict:
+        return anneal_learned(self.h, self.n, temps, seed, k_full, **kw)
+
+    def collect_traces(self, temps, seed, every, k_label, d_x, d_y, max_snapshots, **kw) -> int:
+        return collect_traces(self.h, temps, seed, every, k_label, d_x, d_y, max_snapshots, **kw)
 
     def colouring(self):
         return get_colouring(self.h, self.n, self.info.n_colours)

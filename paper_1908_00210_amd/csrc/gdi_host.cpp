@@ -522,7 +522,18 @@ int finish_pending(gdi_graph *g)
     return GDI_OK;
 }
 
-int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host_out, int8_t *dev_out)
+// One anneal in progress: the launch choice and the argument block shared by all
+// of its sweep launches (a learned anneal launches sweep ranges repeatedly).
+struct RunCtx {
+    Choice ch;
+    GdiSweepArgs a;
+    int thr_in_lds;
+    uint64_t bar_words;
+};
+
+// Validates the schedule, builds the threshold table, writes the initial state
+// (spins, M, per-class counts, cut) and fills the launch arguments.
+int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out, RunCtx &r)
 {
     if (!g) return fail(GDI_ESTATE, "NULL handle");
     if (!s) return fail(GDI_EINVAL, "NULL schedule");
@@ -541,21 +552,19 @@ int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host
         return fail(GDI_ERANGE, "|B|*max_wdeg + 4|A|(n+1) must be < 2^31");
     const bool trace = s->trace_m || s->trace_cut;
 
-    Choice ch;
-    if ((rc = pick_launch(g, &ch))) return rc;
+    if ((rc = pick_launch(g, &r.ch))) return rc;
     if ((rc = ensure_table(g, s, de_max))) return rc;
     const uint64_t phases = (uint64_t)(S - s->start_sweep) * (uint64_t)g->C;
-    uint64_t bar_words = 0;
+    r.bar_words = 0;
     if (phases > (uint64_t(1) << 30)) return fail(GDI_ERANGE, "too many phases for one launch");
-    if (ch.scope == GDI_SCOPE_GRID_FENCED) {
+    if (r.ch.scope == GDI_SCOPE_GRID_FENCED) {
         if (phases > (uint64_t(1) << 22)) return fail(GDI_ERANGE, "too many phases for one launch");
-        bar_words = phases * (GDI_BAR_GROUPS + 1) * GDI_BAR_PAD;
-        HIP_TRY(g->d_bar.reserve(bar_words), "hipMalloc barrier");
+        r.bar_words = phases * (GDI_BAR_GROUPS + 1) * GDI_BAR_PAD;
+        HIP_TRY(g->d_bar.reserve(r.bar_words), "hipMalloc barrier");
     }
     if (trace) HIP_TRY(g->d_trace.reserve(2 * (size_t)S), "hipMalloc trace");
 
     hipStream_t st = g->stream;
-    // initial state
     if (s->init_spins) {
         HIP_TRY(hipMemcpyAsync(g->d_io.p, s->init_spins, (size_t)g->n, hipMemcpyHostToDevice, st), "upload spins");
         if ((rc = gdi_launch_gather_in(g->d_orig.p, g->d_io.p, g->n_pad, g->d_spin.p, st)))
@@ -569,7 +578,6 @@ int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_red.p), 4, st);
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_P.p), (g->C + 2) / 2, st);
     if (!rc && trace) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_trace.p), 2 * (int64_t)S, st);
-    if (!rc && bar_words) rc = gdi_launch_fill_u64(g->d_bar.p, (int64_t)bar_words, st);
     if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->d_cbeg.p, g->d_csz.p,
                                     g->C, g->d_red.p, g->d_P.p, st);
     // the sweep kernels read the initial M from state[0]
@@ -579,7 +587,8 @@ int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host
     }
     if (rc) return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
 
-    GdiSweepArgs a{};
+    GdiSweepArgs &a = r.a;
+    a = GdiSweepArgs{};
     a.rp = g->d_rp.p;
     a.adj = g->d_adj.p;
     a.orig = g->d_orig.p;
@@ -591,8 +600,6 @@ int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host
     a.P = g->d_P.p;
     a.trace_m = trace ? g->d_trace.p : nullptr;
     a.trace_dcut = trace ? g->d_trace.p + S : nullptr;
-    a.bar_grp = bar_words ? g->d_bar.p : nullptr;
-    a.bar_glob = bar_words ? g->d_bar.p + phases * GDI_BAR_GROUPS * GDI_BAR_PAD : nullptr;
     a.n = g->n;
     a.n_pad = g->n_pad;
     a.C = g->C;
@@ -606,9 +613,40 @@ int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host
     a.replica = s->replica;
     a.snapshot = s->balance_mode == GDI_BAL_SNAPSHOT ? 1u : 0u;
     a.spin_limit = (g->have_tune && g->tune.spin_limit) ? (int64_t)g->tune.spin_limit : kSpinLimit;
+    r.thr_in_lds = 0;
+    if (r.ch.scope == GDI_SCOPE_GRID) {
+        int lds_max = 0, dev = 0;
+        HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+        HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
+        r.thr_in_lds = (g->thr_K <= GDI_HALO_THR_MAX &&
+                        gdi_halo_lds_bytes(g->halo_lds_words, g->C, 2 * (g->thr_K + 1)) <= lds_max) ? 1 : 0;
+    }
+    g->last = gdi_result{};
+    g->last.n_colours = (uint32_t)g->C;
+    g->last.scope = r.ch.scope;
+    g->last.grid = r.ch.grid;
+    g->last.block = r.ch.block;
+    g->last.lanes_per_node = r.ch.lanes;
+    g->last.table_width = (uint32_t)g->thr_K;
+    g->last_valid = false;
+    return GDI_OK;
+}
 
-    GdiHaloArgs ha{};
-    if (ch.scope == GDI_SCOPE_GRID) {
+// Launches sweeps [t_from, t_to) continuing from the device state; mask (bit set =
+// skip) and last_flip are optional.
+int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const uint32_t *mask, int32_t *last_flip)
+{
+    hipStream_t st = g->stream;
+    GdiSweepArgs a = r.a;
+    a.t0 = t_from;
+    a.S = t_to;
+    a.mask = mask;
+    a.last_flip = last_flip;
+    int rc = 0;
+    if (r.ch.scope == GDI_SCOPE_WORKGROUP) {
+        rc = gdi_launch_sweep_wg(a, (int)r.ch.block, (int)r.ch.lanes, r.ch.spins_lds ? 1 : 0, st);
+    } else if (r.ch.scope == GDI_SCOPE_GRID) {
+        GdiHaloArgs ha{};
         ha.base = a;
         ha.adjL = g->d_adjL.p;
         ha.tab = g->d_tab.p;
@@ -616,34 +654,33 @@ int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host
         ha.member = g->d_member.p;
         ha.group = g->d_group.p;
         ha.lds_words = g->halo_lds_words;
-        int lds_max = 0, dev = 0;
-        HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
-        HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
-        ha.thr_in_lds = (g->thr_K <= GDI_HALO_THR_MAX &&
-                         gdi_halo_lds_bytes(g->halo_lds_words, g->C, 2 * (g->thr_K + 1)) <= lds_max) ? 1 : 0;
+        ha.thr_in_lds = r.thr_in_lds;
         rc = gdi_launch_fill_u64(g->d_words.p, (int64_t)g->n_pad / 32 + 1, st);
         if (!rc) rc = gdi_launch_fill_u64(g->d_member.p, 8 * 64, st);
         if (!rc) rc = gdi_launch_fill_u64(g->d_group.p, 2 * 8 * GDI_HALO_GROUP_PAD, st);
-        if (rc) return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
+        if (!rc) rc = gdi_launch_sweep_halo(ha, (int)r.ch.grid, (int)r.ch.block, st);
+    } else {
+        const uint64_t phases = (uint64_t)(t_to - t_from) * (uint64_t)g->C;
+        const uint64_t words = phases * (GDI_BAR_GROUPS + 1) * GDI_BAR_PAD;
+        a.bar_grp = g->d_bar.p;
+        a.bar_glob = g->d_bar.p + phases * GDI_BAR_GROUPS * GDI_BAR_PAD;
+        rc = gdi_launch_fill_u64(g->d_bar.p, (int64_t)words, st);
+        if (!rc) rc = gdi_launch_sweep_grid(a, (int)r.ch.grid, (int)r.ch.block, (int)r.ch.lanes, st);
     }
-    HIP_TRY(hipEventRecord(g->ev0, st), "hipEventRecord");
-    if (ch.scope == GDI_SCOPE_WORKGROUP)
-        rc = gdi_launch_sweep_wg(a, (int)ch.block, (int)ch.lanes, ch.spins_lds ? 1 : 0, st);
-    else if (ch.scope == GDI_SCOPE_GRID)
-        rc = gdi_launch_sweep_halo(ha, (int)ch.grid, (int)ch.block, st);
-    else
-        rc = gdi_launch_sweep_grid(a, (int)ch.grid, (int)ch.block, (int)ch.lanes, st);
     if (rc) return fail(GDI_EDEVICE, std::string("sweep launch: ") + gdi_hip_error_string(rc));
-    HIP_TRY(hipEventRecord(g->ev1, st), "hipEventRecord");
+    return GDI_OK;
+}
 
-    g->last = gdi_result{};
-    g->last.n_colours = (uint32_t)g->C;
-    g->last.scope = ch.scope;
-    g->last.grid = ch.grid;
-    g->last.block = ch.block;
-    g->last.lanes_per_node = ch.lanes;
-    g->last.table_width = (uint32_t)g->thr_K;
-    g->last_valid = false;
+int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host_out, int8_t *dev_out)
+{
+    RunCtx r;
+    int rc = prepare_run(g, s, seed, dev_out != nullptr, r);
+    if (rc) return rc;
+    hipStream_t st = g->stream;
+    const uint32_t S = s->n_sweeps;
+    HIP_TRY(hipEventRecord(g->ev0, st), "hipEventRecord");
+    if ((rc = launch_range(g, r, s->start_sweep, S, nullptr, nullptr))) return rc;
+    HIP_TRY(hipEventRecord(g->ev1, st), "hipEventRecord");
 
     int8_t *out_dev = dev_out ? dev_out : g->d_io.p;
     if ((rc = gdi_launch_scatter_out(g->d_orig.p, g->d_spin.p, g->n_pad, out_dev, st)))
@@ -653,7 +690,7 @@ int anneal_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, int8_t *host
 
     if ((rc = finish_pending(g))) return rc;
     HIP_TRY(hipMemcpy(host_out, g->d_io.p, (size_t)g->n, hipMemcpyDeviceToHost), "download spins");
-    if (trace) {
+    if (s->trace_m || s->trace_cut) {
         std::vector<int64_t> tr(2 * (size_t)S);
         HIP_TRY(hipMemcpy(tr.data(), g->d_trace.p, tr.size() * 8, hipMemcpyDeviceToHost), "download trace");
         int64_t cut = g->last_cut0;
@@ -955,6 +992,211 @@ int anneal_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uin
     return run_batch(inst, n_inst, s, seed, t, dev_out, 0, kernel_ms);
 }
 
+// ------------------------------------------------------------------ learned proposal
+// splitmix64: seeded stream for weight initialisation and minibatch shuffling.
+uint64_t splitmix64(uint64_t &x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+struct MlpDevice {
+    DevBuf<float> master;
+    DevBuf<GdiMlpDev> packed;
+    ~MlpDevice() { master.release(); packed.release(); }
+};
+
+// Uploads FP32 master weights and packs the BF16 device copy on the stream.
+int upload_mlp(const gdi_mlp_weights *w, MlpDevice &m, hipStream_t st)
+{
+    static_assert(sizeof(gdi_mlp_weights) == GDI_MLP_PARAMS * sizeof(float), "packed parameter layout");
+    HIP_TRY(m.master.reserve(GDI_MLP_PARAMS), "hipMalloc network");
+    HIP_TRY(m.packed.reserve(1), "hipMalloc network");
+    HIP_TRY(hipMemcpyAsync(m.master.p, w, sizeof(gdi_mlp_weights), hipMemcpyHostToDevice, st), "upload network");
+    int e = gdi_launch_mlp_pack(m.master.p, m.packed.p, st);
+    if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
+    return GDI_OK;
+}
+
+int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_mlp_weights *w,
+                 const gdi_learned_cfg *cfg, int8_t *spins_out, gdi_learned_result *res)
+{
+    if (!cfg || !spins_out) return fail(GDI_EINVAL, "NULL argument");
+    if (cfg->k_full < 1) return fail(GDI_EINVAL, "k_full must be >= 1");
+    if (cfg->skip_mode > GDI_SKIP_HEURISTIC) return fail(GDI_EINVAL, "unknown skip_mode");
+    if (cfg->skip_mode == GDI_SKIP_MLP && (!w || !(cfg->skip_threshold > 0.0f && cfg->skip_threshold < 1.0f)))
+        return fail(GDI_EINVAL, "the network proposal needs weights and a threshold in (0, 1)");
+    if (cfg->skip_mode == GDI_SKIP_HEURISTIC && cfg->heuristic_k < 1) return fail(GDI_EINVAL, "heuristic_k must be >= 1");
+    if (s && (s->trace_m || s->trace_cut)) return fail(GDI_EINVAL, "the learned anneal takes no traces");
+    RunCtx r;
+    int rc = prepare_run(g, s, seed, false, r);
+    if (rc) return rc;
+    hipStream_t st = g->stream;
+    const uint32_t S = s->n_sweeps, t_start = s->start_sweep, k = cfg->k_full;
+    DevBuf<int32_t> lf;
+    DevBuf<uint32_t> mask;
+    DevBuf<uint64_t> X, skipped;
+    MlpDevice net;
+    struct Rel {
+        DevBuf<int32_t> &a; DevBuf<uint32_t> &b; DevBuf<uint64_t> &c, &d;
+        ~Rel() { a.release(); b.release(); c.release(); d.release(); }
+    } rel{lf, mask, X, skipped};
+    HIP_TRY(lf.reserve((size_t)g->n_pad), "hipMalloc learned");
+    // n_pad is a multiple of 64: n_pad / 32 mask words, an even count, cleared as u64 pairs
+    HIP_TRY(mask.reserve((size_t)g->n_pad / 32), "hipMalloc learned");
+    HIP_TRY(skipped.reserve(1), "hipMalloc learned");
+    int e = gdi_launch_fill_i32(lf.p, g->n_pad, (int32_t)t_start - 1, st);
+    if (!e) e = gdi_launch_fill_u64(skipped.p, 1, st);
+    if (!e) e = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(mask.p), (int64_t)g->n_pad / 64, st);
+    if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
+    float thr_logit = 0.0f;
+    if (cfg->skip_mode == GDI_SKIP_MLP) {
+        HIP_TRY(X.reserve((size_t)g->n_pad * 2), "hipMalloc features");
+        if ((e = gdi_launch_fill_u64(X.p, (int64_t)g->n_pad * 2, st))) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
+        if ((rc = upload_mlp(w, net, st))) return rc;
+        thr_logit = std::log(cfg->skip_threshold / (1.0f - cfg->skip_threshold));
+    }
+    std::vector<uint32_t> hmask;
+    if (cfg->mask_trace)
+        std::memset(cfg->mask_trace, 0, (size_t)((S - t_start + k - 1) / k) * (size_t)g->n);
+    HIP_TRY(hipEventRecord(g->ev0, st), "hipEventRecord");
+    for (uint32_t b = t_start; b < S; b += k) {
+        if ((rc = launch_range(g, r, b, b + 1, nullptr, lf.p))) return rc;
+        if (b + 1 >= S) break;
+        const uint32_t end = std::min<uint32_t>(b + k, S);
+        const uint32_t *mp = nullptr;
+        if (cfg->skip_mode == GDI_SKIP_MLP) {
+            e = gdi_launch_features(g->d_rp.p, g->d_adj.p, g->d_spin.p, lf.p, g->n_pad, g->d_state.p,
+                                    (float)s->temps[b], (int32_t)b, s->A, s->B, g->d_orig.p, X.p, -1, 0, st);
+            if (!e) e = gdi_launch_mlp_infer(X.p, g->n_pad, net.packed.p, thr_logit, mask.p, nullptr, st);
+            mp = mask.p;
+        } else if (cfg->skip_mode == GDI_SKIP_HEURISTIC) {
+            e = gdi_launch_mask_heuristic(lf.p, g->n_pad, (int32_t)b, (int32_t)cfg->heuristic_k, mask.p, st);
+            mp = mask.p;
+        }
+        if (!e && mp) e = gdi_launch_mask_finish(mask.p, g->d_orig.p, g->n_pad, skipped.p, end - b - 1, st);
+        if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
+        if (cfg->mask_trace) {
+            const size_t words = (size_t)g->n_pad / 32;
+            hmask.assign(words, 0u);
+            if (mp) HIP_TRY(hipMemcpyAsync(hmask.data(), mask.p, words * 4, hipMemcpyDeviceToHost, st), "download mask");
+            HIP_TRY(hipStreamSynchronize(st), "download mask");
+            uint8_t *row = cfg->mask_trace + (size_t)((b - t_start) / k) * (size_t)g->n;
+            for (int32_t v = 0; v < g->n_pad; ++v) {
+                const int32_t o = g->orig[(size_t)v];
+                if (o >= 0) row[o] = (uint8_t)((hmask[(size_t)v >> 5] >> (v & 31)) & 1u);
+            }
+        }
+        if ((rc = launch_range(g, r, b + 1, end, mp, lf.p))) return rc;
+    }
+    HIP_TRY(hipEventRecord(g->ev1, st), "hipEventRecord");
+    if ((rc = gdi_launch_scatter_out(g->d_orig.p, g->d_spin.p, g->n_pad, g->d_io.p, st)))
+        return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
+    g->pending = true;
+    if ((rc = finish_pending(g))) return rc;
+    HIP_TRY(hipMemcpy(spins_out, g->d_io.p, (size_t)g->n, hipMemcpyDeviceToHost), "download spins");
+    uint64_t nskip = 0;
+    HIP_TRY(hipMemcpy(&nskip, skipped.p, 8, hipMemcpyDeviceToHost), "download counts");
+    if (res) {
+        res->magnetization = g->last.magnetization;
+        res->cut_weighted = g->last.cut_weighted;
+        res->total_ms = g->last.sweep_ms;
+        res->node_skips = nskip;
+        res->node_visits = (uint64_t)g->n * (uint64_t)(S - t_start) - nskip;
+    }
+    return GDI_OK;
+}
+
+int traces_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, uint32_t every, uint32_t k_label, void *d_x,
+                uint8_t *d_y, uint32_t max_snapshots, uint32_t *n_snapshots)
+{
+    if (!d_x || !d_y || !n_snapshots) return fail(GDI_EINVAL, "NULL argument");
+    if (k_label < 1 || every <= k_label) return fail(GDI_EINVAL, "need every > k_label >= 1");
+    if (s && (s->trace_m || s->trace_cut)) return fail(GDI_EINVAL, "no traces here");
+    RunCtx r;
+    int rc = prepare_run(g, s, seed, false, r);
+    if (rc) return rc;
+    hipStream_t st = g->stream;
+    DevBuf<int32_t> lf;
+    HIP_TRY(lf.reserve((size_t)g->n_pad), "hipMalloc traces");
+    int e = gdi_launch_fill_i32(lf.p, g->n_pad, (int32_t)s->start_sweep - 1, st);
+    if (e) { lf.release(); return fail(GDI_EDEVICE, gdi_hip_error_string(e)); }
+    uint32_t t_cur = s->start_sweep, count = 0;
+    for (uint32_t ts = every - 1; ts + k_label < s->n_sweeps && count < max_snapshots; ts += every) {
+        if (ts < s->start_sweep) continue;
+        if ((rc = launch_range(g, r, t_cur, ts + 1, nullptr, lf.p))) { lf.release(); return rc; }
+        e = gdi_launch_features(g->d_rp.p, g->d_adj.p, g->d_spin.p, lf.p, g->n_pad, g->d_state.p,
+                                (float)s->temps[ts], (int32_t)ts, s->A, s->B, g->d_orig.p, d_x, 1,
+                                (int64_t)count * g->n, st);
+        if (e) { lf.release(); return fail(GDI_EDEVICE, gdi_hip_error_string(e)); }
+        if ((rc = launch_range(g, r, ts + 1, ts + k_label + 1, nullptr, lf.p))) { lf.release(); return rc; }
+        e = gdi_launch_labels(lf.p, g->d_orig.p, g->n_pad, (int32_t)ts, d_y, (int64_t)count * g->n, st);
+        if (e) { lf.release(); return fail(GDI_EDEVICE, gdi_hip_error_string(e)); }
+        t_cur = ts + k_label + 1;
+        ++count;
+    }
+    hipError_t he = hipStreamSynchronize(st);
+    lf.release();
+    if (he != hipSuccess) return hip_fail(he, "trace collection");
+    int64_t st8[8];
+    HIP_TRY(hipMemcpy(st8, g->d_state.p, sizeof(st8), hipMemcpyDeviceToHost), "read state");
+    if (st8[3] != 0) return fail(GDI_ETIMEOUT, "a device-side barrier wait expired; traces are invalid");
+    *n_snapshots = count;
+    return GDI_OK;
+}
+
+int train_impl(const void *d_x, const uint8_t *d_y, uint64_t n, gdi_mlp_weights *w, const gdi_train_cfg *cfg,
+               float *epoch_loss, hipStream_t st)
+{
+    if (!d_x || !d_y || !w || !cfg || n == 0) return fail(GDI_EINVAL, "bad argument");
+    if (cfg->batch < 16 || n > (uint64_t)INT32_MAX) return fail(GDI_EINVAL, "batch must be >= 16, n < 2^31");
+    MlpDevice net;
+    DevBuf<float> grad, mo, ve, loss;
+    DevBuf<int32_t> perm;
+    struct Rel {
+        DevBuf<float> &a, &b, &c, &d; DevBuf<int32_t> &e;
+        ~Rel() { a.release(); b.release(); c.release(); d.release(); e.release(); }
+    } rel{grad, mo, ve, loss, perm};
+    int rc = upload_mlp(w, net, st);
+    if (rc) return rc;
+    HIP_TRY(grad.reserve(GDI_MLP_PARAMS + 1), "hipMalloc training");
+    HIP_TRY(mo.reserve(GDI_MLP_PARAMS + 1), "hipMalloc training");
+    HIP_TRY(ve.reserve(GDI_MLP_PARAMS + 1), "hipMalloc training");
+    HIP_TRY(loss.reserve(2), "hipMalloc training");
+    HIP_TRY(perm.reserve((size_t)n), "hipMalloc training");
+    HIP_TRY(hipMemsetAsync(mo.p, 0, (GDI_MLP_PARAMS + 1) * 4, st), "zero Adam state");
+    HIP_TRY(hipMemsetAsync(ve.p, 0, (GDI_MLP_PARAMS + 1) * 4, st), "zero Adam state");
+    std::vector<int32_t> hp((size_t)n);
+    uint64_t rng = cfg->seed;
+    uint64_t step = 0;
+    for (uint32_t ep = 0; ep < cfg->epochs; ++ep) {
+        for (uint64_t i = 0; i < n; ++i) hp[i] = (int32_t)i;
+        for (uint64_t i = n - 1; i > 0; --i) std::swap(hp[i], hp[splitmix64(rng) % (i + 1)]);
+        HIP_TRY(hipMemcpyAsync(perm.p, hp.data(), n * 4, hipMemcpyHostToDevice, st), "upload minibatch order");
+        HIP_TRY(hipMemsetAsync(loss.p, 0, 8, st), "zero loss");
+        for (uint64_t off = 0; off < n; off += cfg->batch) {
+            const int32_t cnt = (int32_t)std::min<uint64_t>(cfg->batch, n - off);
+            ++step;
+            HIP_TRY(hipMemsetAsync(grad.p, 0, (GDI_MLP_PARAMS + 1) * 4, st), "zero gradient");
+            int e = gdi_launch_mlp_grad(d_x, d_y, perm.p + off, cnt, net.packed.p, 1.0f / (float)cnt, grad.p, loss.p, st);
+            const float bc1 = 1.0f - std::pow(cfg->beta1, (float)step), bc2 = 1.0f - std::pow(cfg->beta2, (float)step);
+            if (!e) e = gdi_launch_adam(net.master.p, grad.p, mo.p, ve.p, GDI_MLP_PARAMS, cfg->lr, cfg->beta1, cfg->beta2,
+                                        cfg->eps, bc1, bc2, st);
+            if (!e) e = gdi_launch_mlp_pack(net.master.p, net.packed.p, st);
+            if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
+        }
+        float l = 0.0f;
+        HIP_TRY(hipMemcpyAsync(&l, loss.p, 4, hipMemcpyDeviceToHost, st), "download loss");
+        HIP_TRY(hipStreamSynchronize(st), "training");
+        if (epoch_loss) epoch_loss[ep] = l / (float)n;
+    }
+    HIP_TRY(hipMemcpyAsync(w, net.master.p, sizeof(gdi_mlp_weights), hipMemcpyDeviceToHost, st), "download network");
+    HIP_TRY(hipStreamSynchronize(st), "training");
+    return GDI_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1144,6 +1386,91 @@ int gdi_autotune_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *
     } catch (const std::bad_alloc &) {
         return fail(GDI_ENOMEM, "out of host memory");
     }
+}
+
+int gdi_anneal_learned(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_mlp_weights *w,
+                       const gdi_learned_cfg *cfg, int8_t *spins_out, gdi_learned_result *res)
+{
+    try {
+        return learned_impl(g, s, seed, w, cfg, spins_out, res);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_collect_traces(gdi_graph *g, const gdi_schedule *s, uint64_t seed, uint32_t every, uint32_t k_label,
+                       void *d_x, uint8_t *d_y, uint32_t max_snapshots, uint32_t *n_snapshots)
+{
+    try {
+        return traces_impl(g, s, seed, every, k_label, d_x, d_y, max_snapshots, n_snapshots);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_mlp_init(gdi_mlp_weights *w, uint64_t seed)
+{
+    if (!w) return fail(GDI_EINVAL, "NULL weights");
+    uint64_t x = seed;
+    auto uni = [&](float a) { return (float)((double)(splitmix64(x) >> 11) * 0x1.0p-53 * 2.0 - 1.0) * a; };
+    for (int h = 0; h < 64; ++h)
+        for (int f = 0; f < 6; ++f) w->w1[h][f] = uni(std::sqrt(6.0f / 6.0f));
+    for (int h = 0; h < 64; ++h)
+        for (int k = 0; k < 64; ++k) w->w2[h][k] = uni(std::sqrt(6.0f / 64.0f));
+    for (int h = 0; h < 64; ++h) {
+        w->b1[h] = 0.0f;
+        w->b2[h] = 0.0f;
+        w->w3[h] = uni(std::sqrt(3.0f / 64.0f));
+    }
+    w->b3 = 0.0f;
+    return GDI_OK;
+}
+
+int gdi_mlp_train(const void *d_x, const uint8_t *d_y, uint64_t n, gdi_mlp_weights *w, const gdi_train_cfg *cfg,
+                  float *epoch_loss, void *hip_stream)
+{
+    try {
+        return train_impl(d_x, d_y, n, w, cfg, epoch_loss, (hipStream_t)hip_stream);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_mlp_forward(const gdi_mlp_weights *w, const void *d_x, uint32_t n, float *d_logits, void *hip_stream)
+{
+    if (!w || !d_x || !d_logits || n == 0) return fail(GDI_EINVAL, "bad argument");
+    hipStream_t st = (hipStream_t)hip_stream;
+    MlpDevice net;
+    int rc = upload_mlp(w, net, st);
+    if (rc) return rc;
+    int e = gdi_launch_mlp_infer(d_x, (int32_t)n, net.packed.p, 0.0f, nullptr, d_logits, st);
+    if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
+    HIP_TRY(hipStreamSynchronize(st), "network forward");
+    return GDI_OK;
+}
+
+int gdi_mlp_gradient(const gdi_mlp_weights *w, const void *d_x, const uint8_t *d_y, uint32_t n,
+                     gdi_mlp_weights *grad, float *loss, void *hip_stream)
+{
+    if (!w || !d_x || !d_y || !grad || n == 0) return fail(GDI_EINVAL, "bad argument");
+    hipStream_t st = (hipStream_t)hip_stream;
+    MlpDevice net;
+    DevBuf<float> gbuf;
+    int rc = upload_mlp(w, net, st);
+    if (rc) return rc;
+    HIP_TRY(gbuf.reserve(GDI_MLP_PARAMS + 2), "hipMalloc gradient");
+    HIP_TRY(hipMemsetAsync(gbuf.p, 0, (GDI_MLP_PARAMS + 2) * 4, st), "zero gradient");
+    int e = gdi_launch_mlp_grad(d_x, d_y, nullptr, (int32_t)n, net.packed.p, 1.0f / (float)n, gbuf.p,
+                                gbuf.p + GDI_MLP_PARAMS + 1, st);
+    if (e) { gbuf.release(); return fail(GDI_EDEVICE, gdi_hip_error_string(e)); }
+    std::vector<float> h(GDI_MLP_PARAMS + 2);
+    hipError_t he = hipMemcpyAsync(h.data(), gbuf.p, h.size() * 4, hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    gbuf.release();
+    if (he != hipSuccess) return hip_fail(he, "network gradient");
+    std::memcpy(grad, h.data(), sizeof(gdi_mlp_weights));
+    if (loss) *loss = h[GDI_MLP_PARAMS + 1] / (float)n;
+    return GDI_OK;
 }
 
 int gdi_get_info(const gdi_graph *g, gdi_graph_info *out)

@@ -44,6 +44,8 @@ struct GdiSweepArgs {
     uint32_t replica;
     uint32_t snapshot;         // 1 = SNAPSHOT balance mode
     int64_t spin_limit;        // bounded waits: polls before giving up
+    const uint32_t *mask;      // n_pad/32 words, bit set = node skipped in this launch, or null
+    int32_t *last_flip;        // n_pad entries: sweep of each node's last flip, or null
 };
 
 // Halo layout of the fence-free grid sweep (k_sweep_halo). Each workgroup b owns,
@@ -99,6 +101,14 @@ struct GdiBatchArgs {
     uint32_t snapshot;
 };
 
+// Learned proposal: BF16 network parameters on the device (transposed weights).
+struct GdiMlpDev {
+    __bf16 w1t[64 * 16];       // [hidden][feature], features 6..15 zero
+    __bf16 w2t[64 * 64];       // [output hidden][input hidden]
+    float b1[64], b2[64], w3[64], b3, pad[3];
+};
+#define GDI_MLP_PARAMS (64 * 6 + 64 + 64 * 64 + 64 + 64 + 1)  // packed FP32 master parameters
+
 // host-side launchers (gdi_kernels.hip)
 int gdi_launch_init_spins(const int32_t *orig, const int8_t *init_orig, int8_t *spin, int32_t n_pad,
                           uint32_t key0, uint32_t key1, uint32_t replica, void *stream);
@@ -121,3 +131,22 @@ int gdi_batch_lds_bytes(int32_t n_pad, int32_t C);
 int gdi_launch_sweep_batch(const GdiBatchArgs &ba, int grid, int block, int lds_bytes, void *stream);
 int gdi_batch_occupancy(int block, int lds_bytes, int *per_cu);
 const char *gdi_hip_error_string(int code);
+
+// learned proposal (gdi_learned.hip)
+int gdi_launch_features(const int32_t *rp, const int2 *adj, const int8_t *spin, const int32_t *last_flip,
+                        int32_t n_pad, const int64_t *state, float T, int32_t t, int32_t A, int32_t B,
+                        const int32_t *orig, void *X, int32_t dataset_rows, int64_t x_base, void *stream);
+int gdi_launch_labels(const int32_t *last_flip, const int32_t *orig, int32_t n_pad, int32_t t_cut, uint8_t *y,
+                      int64_t y_base, void *stream);
+int gdi_launch_mask_heuristic(const int32_t *last_flip, int32_t n_pad, int32_t t, int32_t k, uint32_t *mask,
+                              void *stream);
+int gdi_launch_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad, uint64_t *skipped, uint32_t weight,
+                           void *stream);
+int gdi_launch_fill_i32(int32_t *p, int64_t n, int32_t value, void *stream);
+int gdi_launch_mlp_infer(const void *X, int32_t count, const GdiMlpDev *p, float thr_logit, uint32_t *mask,
+                         float *logits, void *stream);
+int gdi_launch_mlp_grad(const void *X, const uint8_t *Y, const int32_t *idx, int32_t count, const GdiMlpDev *p,
+                        float inv_batch, float *grad, float *loss, void *stream);
+int gdi_launch_adam(float *w, const float *g, float *m, float *v, int32_t P, float lr, float b1, float b2, float eps,
+                    float bc1, float bc2, void *stream);
+int gdi_launch_mlp_pack(const float *w, GdiMlpDev *p, void *stream);

@@ -180,12 +180,14 @@ __device__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp, int32_t *Psh, i
             int32_t dM = 0;
             for (int32_t j = sub; j < size; j += nsub) {
                 const int32_t v = beg + j;
+                if (a.mask && ((a.mask[v >> 5] >> (v & 31)) & 1u)) continue;  // skipped node
                 int32_t h, sigma;
                 const bool flip = node_decide<L>(a, sp, v, lane, t, pv, thr_row, &h, &sigma);
                 if (flip && lane == 0) {
                     sp[v] = (int8_t)(-sigma);
                     dM -= 2 * sigma;
                     dcut += (int64_t)sigma * h;
+                    if (a.last_flip) a.last_flip[v] = (int32_t)t;
                 }
             }
             dM = wave_sum_i32(dM);
@@ -434,12 +436,14 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_grid(GdiSweepArgs a)
             int32_t dM = 0;
             for (int32_t j = lo + sub; j < hi; j += nsub) {
                 const int32_t v = beg + j;
+                if (a.mask && ((a.mask[v >> 5] >> (v & 31)) & 1u)) continue;  // skipped node
                 int32_t h, sigma;
                 const bool flip = node_decide<L>(a, a.spin, v, lane, t, pv, thr_row, &h, &sigma);
                 if (flip && lane == 0) {
                     a.spin[v] = (int8_t)(-sigma);
                     dM -= 2 * sigma;
                     dcut += (int64_t)sigma * h;
+                    if (a.last_flip) a.last_flip[v] = (int32_t)t;
                 }
             }
             dM = wave_sum_i32(dM);
@@ -714,7 +718,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                     const bool active = v < e.node_hi;
                     bool flip = false;
                     int32_t sigma_l = 0;
-                    if (active) {
+                    if (active && !(a.mask && ((a.mask[v >> 5] >> (v & 31)) & 1u))) {
                         NodePrefetch q;
                         if (base != e.node_lo) {
                             RowAhead rq;
@@ -734,7 +738,10 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                         const int32_t sigma = lds_spin(bits, lb);
                         flip = decide_words(a, sigma, hv, pv, thr, q.x0, q.x1);
                         sigma_l = sigma;
-                        if (flip) dcut += (int64_t)sigma * hv;
+                        if (flip) {
+                            dcut += (int64_t)sigma * hv;
+                            if (a.last_flip) a.last_flip[v] = (int32_t)t;
+                        }
                     }
                     const uint64_t fm = __ballot(flip);
                     // flips of +1 spins lower M by 2, flips of -1 spins raise it by 2

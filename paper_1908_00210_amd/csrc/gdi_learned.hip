@@ -1,0 +1,506 @@
+// gdi_learned.hip -- kernels of the learned frozen-node proposal (gfx950).
+//
+// A small network predicts, from six per-node features, whether a node will stay
+// frozen for the next sweeps; masked sweeps then skip the nodes it flags, and a
+// full sweep runs every k sweeps. The network is 6 -> 64 -> 64 -> 1 with ReLU
+// hidden layers and a logistic output, BF16 weights and FP32 accumulation; both
+// dense layers run on MFMA (v_mfma_f32_16x16x16_bf16).
+//
+// The layers are evaluated transposed, hidden x node: for a tile of 16 nodes,
+// layer 1 computes H1^T = W1^T X^T and layer 2 H2^T = W2^T H1^T. With the
+// 16x16x16 MFMA, lane l holds accumulator rows 4(l/16)..4(l/16)+3 of column
+// l%16, which is exactly the B-operand layout (k rows 4(l/16).., column l%16) of
+// the next product, so activations stay in registers between the layers.
+//
+// Training computes the mean logistic loss on a minibatch and its gradients
+// with the same MFMA layout (dH1 = W2 dPre2 directly in registers; the weight
+// gradients, sums over nodes, through per-wave LDS tiles), then Adam updates
+// FP32 master weights that are re-packed to BF16.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "gdi_internal.h"
+
+namespace {
+
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ floatx4 mfma16(bf16x4 a, bf16x4 b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+}
+
+// ------------------------------------------------------------------ features
+// Six features per node (new-id order), rounded to BF16, two zero pads:
+//   f0 = degree / 16, f1 = sum |w| / 16, f2 = fraction of neighbours on the other side,
+//   f3 = clamp(B s h / T, -16, 16) / 4 (local field in units of T, positive = stable),
+//   f4 = min(|4A(1 - s M)| / T, 64) / 16 (balance cost of a flip in units of T),
+//   f5 = min(t - last_flip, 255) / 64 (sweeps since the last flip).
+__global__ void k_features(const int32_t *rp, const int2 *adj, const int8_t *spin, const int32_t *last_flip,
+                           int32_t n_pad, const int64_t *state, float T, int32_t t, int32_t A, int32_t B,
+                           const int32_t *orig, __bf16 *X, int32_t x_stride_rows, int64_t x_base)
+{
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_pad) return;
+    const int32_t o = orig[v];
+    if (o < 0) return;  // padding id
+    const int32_t s = spin[v];
+    const int32_t M = (int32_t)state[0];
+    int32_t deg = 0, wabs = 0, other = 0, h = 0;
+    for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
+        const int2 e = adj[k];
+        const int32_t sj = spin[e.x];
+        ++deg;
+        wabs += e.y < 0 ? -e.y : e.y;
+        other += sj != s;
+        h += e.y * sj;
+    }
+    float f[8];
+    f[0] = deg / 16.0f;
+    f[1] = wabs / 16.0f;
+    f[2] = deg ? (float)other / (float)deg : 0.0f;
+    f[3] = fminf(fmaxf((float)(B * s * h) / T, -16.0f), 16.0f) / 4.0f;
+    const int32_t bal = 4 * A * (1 - s * M);
+    f[4] = fminf(fabsf((float)bal) / T, 64.0f) / 16.0f;
+    f[5] = (float)min(t - last_flip[v], 255) / 64.0f;
+    f[6] = 0.0f;
+    f[7] = 0.0f;
+    // x_stride_rows < 0: row = new id (inference); otherwise row = x_base + original id (dataset)
+    const int64_t row = x_stride_rows < 0 ? (int64_t)v : x_base + o;
+    __bf16 *dst = X + row * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) dst[i] = (__bf16)f[i];
+}
+
+// Nodes not flipped since sweep t_cut get label 1 (frozen); original-id rows.
+__global__ void k_labels(const int32_t *last_flip, const int32_t *orig, int32_t n_pad, int32_t t_cut,
+                         uint8_t *y, int64_t y_base)
+{
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_pad) return;
+    const int32_t o = orig[v];
+    if (o < 0) return;
+    y[y_base + o] = last_flip[v] <= t_cut ? 1 : 0;
+}
+
+// Heuristic proposal: skip nodes that have not flipped for at least k sweeps.
+__global__ void k_mask_heuristic(const int32_t *last_flip, int32_t n_pad, int32_t t, int32_t k, uint32_t *mask)
+{
+    const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w * 32 >= n_pad) return;
+    uint32_t bits = 0;
+    for (int i = 0; i < 32; ++i) {
+        const int32_t v = w * 32 + i;
+        if (v < n_pad && t - last_flip[v] >= k) bits |= 1u << i;
+    }
+    mask[w] = bits;
+}
+
+// Clears the bits of padding ids and counts the skipped node visits (bits x weight).
+__global__ void k_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad, unsigned long long *skipped,
+                              uint32_t weight)
+{
+    const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t bits = 0;
+    if (w * 32 < n_pad) {
+        bits = mask[w];
+        for (int i = 0; i < 32; ++i) {
+            const int32_t v = w * 32 + i;
+            if (v >= n_pad || orig[v] < 0) bits &= ~(1u << i);
+        }
+        mask[w] = bits;
+    }
+    unsigned long long c = (unsigned long long)__popc(bits) * weight;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(skipped, c);
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t value)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+// ------------------------------------------------------------------ MLP parameters
+struct MlpLds {
+    __bf16 w1t[64 * 16];
+    __bf16 w2t[64 * 64];
+    float b1[64], b2[64], w3[64], b3;
+};
+
+__device__ void load_params(const GdiMlpDev *p, MlpLds *m)
+{
+    for (int i = threadIdx.x; i < 64 * 16; i += blockDim.x) m->w1t[i] = p->w1t[i];
+    for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) m->w2t[i] = p->w2t[i];
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+        m->b1[i] = p->b1[i];
+        m->b2[i] = p->b2[i];
+        m->w3[i] = p->w3[i];
+    }
+    if (threadIdx.x == 0) m->b3 = p->b3;
+    __syncthreads();
+}
+
+// Forward pass of one 16-node tile. Lane l: g = l/16 (row group), r = l%16 (node).
+// xb: B operand of layer 1 (features 4g..4g+3 of node r). Outputs the H1 B operands,
+// the layer-2 pre-activations and the logit (identical in the four lanes of a node).
+struct TileFwd {
+    bf16x4 h1[4];      // H1^T rows 16m + 4g + i, node r (BF16, post-ReLU)
+    floatx4 pre2[4];   // layer-2 pre-activations rows 16m + 4g + i
+    float z;
+};
+
+__device__ __forceinline__ void tile_forward(const MlpLds *m, bf16x4 xb, int g, int r, TileFwd &o)
+{
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        bf16x4 a;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) a[j] = m->w1t[(16 * mb + r) * 16 + 4 * g + j];
+        const floatx4 acc = mfma16(a, xb, floatx4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+        for (int i = 0; i < 4; ++i) o.h1[mb][i] = (__bf16)fmaxf(acc[i] + m->b1[16 * mb + 4 * g + i], 0.0f);
+    }
+    float part = 0.0f;
+#pragma unroll
+    for (int mo = 0; mo < 4; ++mo) {
+        floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            bf16x4 a;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) a[j] = m->w2t[(16 * mo + r) * 64 + 16 * kb + 4 * g + j];
+            acc = mfma16(a, o.h1[kb], acc);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int hrow = 16 * mo + 4 * g + i;
+            acc[i] += m->b2[hrow];
+            part += m->w3[hrow] * fmaxf(acc[i], 0.0f);
+        }
+        o.pre2[mo] = acc;
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    o.z = part + m->b3;
+}
+
+__device__ __forceinline__ bf16x4 load_xb(const __bf16 *X, const int32_t *idx, int64_t node, int64_t count, int g)
+{
+    bf16x4 xb;
+    const bool ok = node < count && g < 2;
+    const int64_t row = ok ? (idx ? (int64_t)idx[node] : node) : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) xb[j] = ok ? X[row * 8 + 4 * g + j] : (__bf16)0.0f;
+    return xb;
+}
+
+// ------------------------------------------------------------------ inference
+// Logit per node; mask bit = logit > thr_logit (32 nodes per mask word).
+__global__ void __launch_bounds__(256) k_mlp_infer(const __bf16 *X, int32_t count, const GdiMlpDev *p,
+                                                    float thr_logit, uint32_t *mask, float *logits)
+{
+    __shared__ MlpLds m;
+    load_params(p, &m);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int64_t words = ((int64_t)count + 31) / 32;
+    for (int64_t w = (int64_t)blockIdx.x * 4 + wave; w < words; w += (int64_t)gridDim.x * 4) {
+        uint32_t bits = 0;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int64_t node = w * 32 + 16 * half + r;
+            TileFwd f;
+            tile_forward(&m, load_xb(X, nullptr, node, count, g), g, r, f);
+            const bool frozen = g == 0 && node < count && f.z > thr_logit;
+            if (g == 0 && node < count && logits) logits[node] = f.z;
+            const uint64_t b = __ballot(frozen);
+            bits |= (uint32_t)(b & 0xFFFFu) << (16 * half);
+        }
+        if (lane == 0 && mask) mask[w] = bits;
+    }
+}
+
+// ------------------------------------------------------------------ gradients
+// Mean logistic loss over the minibatch rows idx[0..count) and its gradient with
+// respect to the packed FP32 parameters (layout of gdi_mlp_weights: w1[64][6], b1,
+// w2[64][64], b2, w3, b3), accumulated with atomics into grad (zeroed by the caller).
+struct WaveTiles {
+    __bf16 dp2[64 * 16];  // dPre2^T [o][node]
+    __bf16 h1[64 * 16];   // H1^T [k][node]
+    __bf16 dp1[64 * 16];  // dPre1^T [k][node]
+    __bf16 xt[16 * 16];   // X^T [f][node]
+};
+
+__device__ __forceinline__ bf16x4 lds4(const __bf16 *base)
+{
+    bf16x4 v;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = base[j];
+    return v;
+}
+
+__global__ void __launch_bounds__(256) k_mlp_grad(const __bf16 *X, const uint8_t *Y, const int32_t *idx,
+                                                   int32_t count, const GdiMlpDev *p, float inv_batch,
+                                                   float *grad, float *loss)
+{
+    __shared__ MlpLds m;
+    __shared__ WaveTiles tiles[4];
+    load_params(p, &m);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    WaveTiles &T = tiles[wave];
+
+    floatx4 acc_w2[4][4];
+    floatx4 acc_w1[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        acc_w1[a] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc_w2[a][b] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    float gb1[4][4], gb2[4][4], gw3[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gb1[a][b] = gb2[a][b] = gw3[a][b] = 0.0f;
+    float gb3 = 0.0f, lsum = 0.0f;
+
+    const int64_t tiles_n = ((int64_t)count + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < tiles_n; tile += (int64_t)gridDim.x * 4) {
+        const int64_t node = tile * 16 + r;
+        const bool valid = node < count;
+        const bf16x4 xb = load_xb(X, idx, node, count, g);
+        TileFwd f;
+        tile_forward(&m, xb, g, r, f);
+        const float y = valid ? (float)Y[idx ? idx[node] : node] : 0.0f;
+        const float pz = 1.0f / (1.0f + expf(-f.z));
+        const float dz = valid ? (pz - y) * inv_batch : 0.0f;
+        if (valid && g == 0) {
+            // numerically stable logistic loss: softplus(z) - y z
+            const float sp = fmaxf(f.z, 0.0f) + log1pf(expf(-fabsf(f.z)));
+            lsum += sp - y * f.z;
+            gb3 += dz;
+        }
+        // layer 2 backward: dPre2 = dz w3 [pre2 > 0]
+        bf16x4 dp2b[4];
+#pragma unroll
+        for (int mo = 0; mo < 4; ++mo) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int hrow = 16 * mo + 4 * g + i;
+                const float pre = f.pre2[mo][i];
+                const float h2 = fmaxf(pre, 0.0f);
+                gw3[mo][i] += dz * h2;
+                const float d = pre > 0.0f ? dz * m.w3[hrow] : 0.0f;
+                gb2[mo][i] += d;
+                dp2b[mo][i] = (__bf16)d;
+                T.dp2[hrow * 16 + r] = dp2b[mo][i];
+                T.h1[(16 * mo + 4 * g + i) * 16 + r] = f.h1[mo][i];
+            }
+        }
+        // dH1^T = W2 dPre2^T: A[k][o] = w2t[o][k]
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) {
+            floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int mo = 0; mo < 4; ++mo) {
+                bf16x4 a;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) a[j] = m.w2t[(16 * mo + 4 * g + j) * 64 + 16 * kb + r];
+                acc = mfma16(a, dp2b[mo], acc);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int krow = 16 * kb + 4 * g + i;
+                const float d = (float)f.h1[kb][i] > 0.0f ? acc[i] : 0.0f;
+                gb1[kb][i] += d;
+                T.dp1[krow * 16 + r] = (__bf16)d;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            // X^T tile: feature 4g + j of node r (features >= 8 are zero)
+            T.xt[(4 * g + j) * 16 + r] = g < 2 ? xb[j] : (__bf16)0.0f;
+        }
+        wave_lds_sync();
+        // dW2^T[o][k] += sum_node dPre2^T[o][node] H1^T[k][node]
+#pragma unroll
+        for (int mo = 0; mo < 4; ++mo) {
+            const bf16x4 a = lds4(&T.dp2[(16 * mo + r) * 16 + 4 * g]);
+#pragma unroll
+            for (int kb = 0; kb < 4; ++kb) acc_w2[mo][kb] = mfma16(a, lds4(&T.h1[(16 * kb + r) * 16 + 4 * g]), acc_w2[mo][kb]);
+        }
+        // dW1^T[k][f] += sum_node dPre1^T[k][node] X^T[f][node]
+        const bf16x4 bx = lds4(&T.xt[r * 16 + 4 * g]);
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb) acc_w1[kb] = mfma16(lds4(&T.dp1[(16 * kb + r) * 16 + 4 * g]), bx, acc_w1[kb]);
+        wave_lds_sync();
+    }
+    // flush: D layout row = 16a + 4g + i, column = 16b + r
+    float *gw1 = grad, *gb1p = grad + 64 * 6, *gw2 = gb1p + 64, *gb2p = gw2 + 64 * 64, *gw3p = gb2p + 64,
+          *gb3p = gw3p + 64;
+#pragma unroll
+    for (int mo = 0; mo < 4; ++mo)
+#pragma unroll
+        for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float v = acc_w2[mo][kb][i];
+                if (v != 0.0f) atomicAdd(&gw2[(16 * mo + 4 * g + i) * 64 + 16 * kb + r], v);
+            }
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float v = acc_w1[kb][i];
+            if (r < 6 && v != 0.0f) atomicAdd(&gw1[(16 * kb + 4 * g + i) * 6 + r], v);
+        }
+    // per-hidden-unit sums over nodes: reduce the 16 node lanes of each row group
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            float v1 = gb1[a][i], v2 = gb2[a][i], v3 = gw3[a][i];
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                v1 += __shfl_xor(v1, off, 64);
+                v2 += __shfl_xor(v2, off, 64);
+                v3 += __shfl_xor(v3, off, 64);
+            }
+            if (r == 0) {
+                const int hrow = 16 * a + 4 * g + i;
+                if (v1 != 0.0f) atomicAdd(&gb1p[hrow], v1);
+                if (v2 != 0.0f) atomicAdd(&gb2p[hrow], v2);
+                if (v3 != 0.0f) atomicAdd(&gw3p[hrow], v3);
+            }
+        }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        gb3 += __shfl_xor(gb3, off, 64);
+        lsum += __shfl_xor(lsum, off, 64);
+    }
+    if (lane == 0) {
+        if (gb3 != 0.0f) atomicAdd(gb3p, gb3);
+        if (loss) atomicAdd(loss, lsum);
+    }
+}
+
+// ------------------------------------------------------------------ optimiser
+// Adam on the FP32 master parameters, then repack the BF16 device weights.
+__global__ void k_adam(float *w, const float *gr, float *mo, float *ve, int32_t P, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P) return;
+    const float gi = gr[i];
+    const float m1 = b1 * mo[i] + (1.0f - b1) * gi;
+    const float v1 = b2 * ve[i] + (1.0f - b2) * gi * gi;
+    mo[i] = m1;
+    ve[i] = v1;
+    w[i] -= lr * (m1 / bc1) / (sqrtf(v1 / bc2) + eps);
+}
+
+__global__ void k_mlp_pack(const float *w, GdiMlpDev *p)
+{
+    const float *w1 = w, *b1 = w + 64 * 6, *w2 = b1 + 64, *b2 = w2 + 64 * 64, *w3 = b2 + 64, *b3 = w3 + 64;
+    for (int i = threadIdx.x; i < 64 * 16; i += blockDim.x) {
+        const int h = i / 16, f = i % 16;
+        p->w1t[i] = (__bf16)(f < 6 ? w1[h * 6 + f] : 0.0f);
+    }
+    for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) p->w2t[i] = (__bf16)w2[i];
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+        p->b1[i] = b1[i];
+        p->b2[i] = b2[i];
+        p->w3[i] = w3[i];
+    }
+    if (threadIdx.x == 0) p->b3 = b3[0];
+}
+
+inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+int gdi_launch_features(const int32_t *rp, const int2 *adj, const int8_t *spin, const int32_t *last_flip,
+                        int32_t n_pad, const int64_t *state, float T, int32_t t, int32_t A, int32_t B,
+                        const int32_t *orig, void *X, int32_t dataset_rows, int64_t x_base, void *stream)
+{
+    hipLaunchKernelGGL(k_features, dim3(nblk(n_pad, 256)), dim3(256), 0, (hipStream_t)stream, rp, adj, spin,
+                       last_flip, n_pad, state, T, t, A, B, orig, (__bf16 *)X, dataset_rows, x_base);
+    return (int)hipGetLastError();
+}
+
+int gdi_launch_labels(const int32_t *last_flip, const int32_t *orig, int32_t n_pad, int32_t t_cut, uint8_t *y,
+                      int64_t y_base, void *stream)
+{
+    hipLaunchKernelGGL(k_labels, dim3(nblk(n_pad, 256)), dim3(256), 0, (hipStream_t)stream, last_flip, orig, n_pad,
+                       t_cut, y, y_base);
+    return (int)hipGetLastError();
+}
+
+int gdi_launch_mask_heuristic(const int32_t *last_flip, int32_t n_pad, int32_t t, int32_t k, uint32_t *mask,
+                              void *stream)
+{
+    hipLaunchKernelGGL(k_mask_heuristic, dim3(nblk((n_pad + 31) / 32, 256)), dim3(256), 0, (hipStream_t)stream,
+                       last_flip, n_pad, t, k, mask);
+    return (int)hipGetLastError();
+}
+
+int gdi_launch_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad, uint64_t *skipped, uint32_t weight,
+                           void *stream)
+{
+    hipLaunchKernelGGL(k_mask_finish, dim3(nblk((n_pad + 31) / 32, 256)), dim3(256), 0, (hipStream_t)stream, mask, orig,
+                       n_pad, (unsigned long long *)skipped, weight);
+    return (int)hipGetLastError();
+}
+
+int gdi_launch_fill_i32(int32_t *p, int64_t n, int32_t value, void *stream)
+{
+    if (n <= 0) return 0;
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n, 256)), dim3(256), 0, (hipStream_t)stream, p, n, value);
+    return (int)hipGetLastError();
+}
+
+int gdi_launch_mlp_infer(const void *X, int32_t count, const GdiMlpDev *p, float thr_logit, uint32_t *mask,
+                         float *logits, void *stream)
+{
+    const int64_t words = ((int64_t)count + 31) / 32;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((words + 3) / 4, 4096));
+    hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const __bf16 *)X, count, p,
+                       thr_logit, mask, logits);
+    return (int)hipGetLastError();
+}
+
+int gdi_launch_mlp_grad(const void *X, const uint8_t *Y, const int32_t *idx, int32_t count, const GdiMlpDev *p,
+                        float inv_batch, float *grad, float *loss, void *stream)
+{
+    const int64_t tiles = ((int64_t)count + 15) / 16;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 1024));
+    hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const __bf16 *)X, Y, idx, count,
+                       p, inv_batch, grad, loss);
+    return (int)hipGetLastError();
+}
+
+int gdi_launch_adam(float *w, const float *g, float *m, float *v, int32_t P, float lr, float b1, float b2, float eps,
+                    float bc1, float bc2, void *stream)
+{
+    hipLaunchKernelGGL(k_adam, dim3(nblk(P, 256)), dim3(256), 0, (hipStream_t)stream, w, g, m, v, P, lr, b1, b2, eps,
+                       bc1, bc2);
+    return (int)hipGetLastError();
+}
+
+int gdi_launch_mlp_pack(const float *w, GdiMlpDev *p, void *stream)
+{
+    hipLaunchKernelGGL(k_mlp_pack, dim3(1), dim3(256), 0, (hipStream_t)stream, w, p);
+    return (int)hipGetLastError();
+}
