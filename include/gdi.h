@@ -282,6 +282,9 @@ typedef struct {
     uint32_t heuristic_k;      /* GDI_SKIP_HEURISTIC */
     uint8_t *mask_trace;       /* host or NULL: ceil((S - start_sweep) / k_full) x n bytes, original order:
                                   1 = node skipped in the masked sweeps after that full sweep */
+    int32_t active_max;        /* masked sweeps with at most this many active nodes run in one
+                                  workgroup over the active nodes only (spins as LDS bits);
+                                  0 = automatic, < 0 = never (the full-graph kernel skips nodes) */
 } gdi_learned_cfg;
 
 typedef struct {

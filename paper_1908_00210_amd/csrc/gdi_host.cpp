@@ -634,7 +634,10 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
 
 // Launches sweeps [t_from, t_to) continuing from the device state; mask (bit set =
 // skip) and last_flip are optional.
-int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const uint32_t *mask, int32_t *last_flip)
+// With gate set, the launch runs only if more than active_max nodes are active (the
+// active-set kernel takes the other case).
+int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const uint32_t *mask, int32_t *last_flip,
+                 const uint64_t *gate = nullptr, int32_t active_max = 0)
 {
     hipStream_t st = g->stream;
     GdiSweepArgs a = r.a;
@@ -642,6 +645,9 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
     a.S = t_to;
     a.mask = mask;
     a.last_flip = last_flip;
+    a.skip_count = reinterpret_cast<const unsigned long long *>(gate);
+    a.active_max = active_max;
+    a.gate_small = 0;
     int rc = 0;
     if (r.ch.scope == GDI_SCOPE_WORKGROUP) {
         rc = gdi_launch_sweep_wg(a, (int)r.ch.block, (int)r.ch.lanes, r.ch.spins_lds ? 1 : 0, st);
@@ -1038,17 +1044,28 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
     DevBuf<int32_t> lf;
     DevBuf<uint32_t> mask;
     DevBuf<uint64_t> X, skipped;
+    DevBuf<GdiActiveRec> rec;
     MlpDevice net;
     struct Rel {
-        DevBuf<int32_t> &a; DevBuf<uint32_t> &b; DevBuf<uint64_t> &c, &d;
-        ~Rel() { a.release(); b.release(); c.release(); d.release(); }
-    } rel{lf, mask, X, skipped};
+        DevBuf<int32_t> &a; DevBuf<uint32_t> &b; DevBuf<uint64_t> &c, &d; DevBuf<GdiActiveRec> &e;
+        ~Rel() { a.release(); b.release(); c.release(); d.release(); e.release(); }
+    } rel{lf, mask, X, skipped, rec};
+    // masked sweeps with few active nodes: one workgroup over the active set, if every
+    // spin fits its LDS as a bit
+    int dev = 0, lds_max = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
+    int32_t amax = cfg->active_max;
+    if (amax == 0) amax = r.ch.scope == GDI_SCOPE_WORKGROUP ? g->n : (int32_t)std::min<int64_t>(g->n, 4096LL * g->C);
+    const bool use_active = cfg->skip_mode != GDI_SKIP_NONE && amax > 0 &&
+                            gdi_active_lds_bytes(g->n_pad, g->C) + 512 <= lds_max;
+    if (use_active) HIP_TRY(rec.reserve((size_t)g->n_pad), "hipMalloc learned");
     HIP_TRY(lf.reserve((size_t)g->n_pad), "hipMalloc learned");
     // n_pad is a multiple of 64: n_pad / 32 mask words, an even count, cleared as u64 pairs
     HIP_TRY(mask.reserve((size_t)g->n_pad / 32), "hipMalloc learned");
-    HIP_TRY(skipped.reserve(1), "hipMalloc learned");
+    HIP_TRY(skipped.reserve(2), "hipMalloc learned");  // [0] all skipped visits, [1] skipped nodes of a block
     int e = gdi_launch_fill_i32(lf.p, g->n_pad, (int32_t)t_start - 1, st);
-    if (!e) e = gdi_launch_fill_u64(skipped.p, 1, st);
+    if (!e) e = gdi_launch_fill_u64(skipped.p, 2, st);
     if (!e) e = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(mask.p), (int64_t)g->n_pad / 64, st);
     if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
     float thr_logit = 0.0f;
@@ -1076,7 +1093,8 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
             e = gdi_launch_mask_heuristic(lf.p, g->n_pad, (int32_t)b, (int32_t)cfg->heuristic_k, mask.p, st);
             mp = mask.p;
         }
-        if (!e && mp) e = gdi_launch_mask_finish(mask.p, g->d_orig.p, g->n_pad, skipped.p, end - b - 1, st);
+        if (!e && mp) e = gdi_launch_fill_u64(skipped.p + 1, 1, st);
+        if (!e && mp) e = gdi_launch_mask_finish(mask.p, g->d_orig.p, g->n_pad, skipped.p, end - b - 1, skipped.p + 1, st);
         if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
         if (cfg->mask_trace) {
             const size_t words = (size_t)g->n_pad / 32;
@@ -1089,7 +1107,20 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
                 if (o >= 0) row[o] = (uint8_t)((hmask[(size_t)v >> 5] >> (v & 31)) & 1u);
             }
         }
-        if ((rc = launch_range(g, r, b + 1, end, mp, lf.p))) return rc;
+        if (mp && use_active) {
+            GdiSweepArgs a = r.a;
+            a.t0 = b + 1;
+            a.S = end;
+            a.mask = mp;
+            a.last_flip = lf.p;
+            a.skip_count = reinterpret_cast<const unsigned long long *>(skipped.p + 1);
+            a.active_max = amax;
+            a.gate_small = 1;
+            if ((e = gdi_launch_sweep_active(a, rec.p, st))) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
+            if ((rc = launch_range(g, r, b + 1, end, mp, lf.p, skipped.p + 1, amax))) return rc;
+        } else if ((rc = launch_range(g, r, b + 1, end, mp, lf.p))) {
+            return rc;
+        }
     }
     HIP_TRY(hipEventRecord(g->ev1, st), "hipEventRecord");
     if ((rc = gdi_launch_scatter_out(g->d_orig.p, g->d_spin.p, g->n_pad, g->d_io.p, st)))

@@ -46,6 +46,18 @@ struct GdiSweepArgs {
     int64_t spin_limit;        // bounded waits: polls before giving up
     const uint32_t *mask;      // n_pad/32 words, bit set = node skipped in this launch, or null
     int32_t *last_flip;        // n_pad entries: sweep of each node's last flip, or null
+    // launch gate (null = always run): with k = n - *skip_count nodes active, the launch
+    // runs iff (k <= active_max) == (gate_small != 0); the decision is uniform over the grid
+    const unsigned long long *skip_count;
+    int32_t active_max;
+    int32_t gate_small;
+};
+
+// Record of one active node of a masked launch (k_sweep_active).
+struct GdiActiveRec {
+    int32_t v;                 // new id
+    int32_t r0, r1;            // CSR row
+    int32_t orig;              // original id (Philox counter)
 };
 
 // Halo layout of the fence-free grid sweep (k_sweep_halo). Each workgroup b owns,
@@ -120,6 +132,8 @@ int gdi_launch_scatter_out(const int32_t *orig, const int8_t *spin, int32_t n_pa
                            void *stream);
 int gdi_launch_gather_in(const int32_t *orig, const int8_t *in_orig, int32_t n_pad, int8_t *spin,
                          void *stream);
+int gdi_active_lds_bytes(int32_t n_pad, int32_t C);
+int gdi_launch_sweep_active(const GdiSweepArgs &a, GdiActiveRec *rec, void *stream);
 int gdi_launch_sweep_wg(const GdiSweepArgs &a, int block, int lanes, int spins_in_lds, void *stream);
 int gdi_launch_sweep_grid(const GdiSweepArgs &a, int grid, int block, int lanes, void *stream);
 int gdi_grid_capacity(int block, int lanes, int *max_grid);
@@ -141,7 +155,7 @@ int gdi_launch_labels(const int32_t *last_flip, const int32_t *orig, int32_t n_p
 int gdi_launch_mask_heuristic(const int32_t *last_flip, int32_t n_pad, int32_t t, int32_t k, uint32_t *mask,
                               void *stream);
 int gdi_launch_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad, uint64_t *skipped, uint32_t weight,
-                           void *stream);
+                           uint64_t *block_skips, void *stream);
 int gdi_launch_fill_i32(int32_t *p, int64_t n, int32_t value, void *stream);
 int gdi_launch_mlp_infer(const void *X, int32_t count, const GdiMlpDev *p, float thr_logit, uint32_t *mask,
                          float *logits, void *stream);

@@ -102,17 +102,17 @@ __device__ __forceinline__ PhaseView make_view(int32_t M0, int32_t P_c, int32_t 
     return v;
 }
 
-// Metropolis decision of one node given its local field h and spin sigma
-// (eq. 5 / eq. 6 flip cost with the gated balance term). Philox words are drawn
-// only when the gate or the threshold lookup needs them.
-__device__ __forceinline__ bool decide(const GdiSweepArgs &a, int32_t v, uint32_t t, int32_t sigma,
-                                       int32_t h, const PhaseView &pv, const uint32_t *thr_row)
+// Metropolis decision of one node (original id o) given its local field h and spin
+// sigma (eq. 5 / eq. 6 flip cost with the gated balance term). Philox words are
+// drawn only when the gate or the threshold lookup needs them.
+__device__ __forceinline__ bool decide_id(const GdiSweepArgs &a, uint32_t o, uint32_t t, int32_t sigma,
+                                          int32_t h, const PhaseView &pv, const uint32_t *thr_row)
 {
     const bool need_gate = !a.snapshot && pv.D > 0 && sigma == pv.s;
     uint32_t x0 = 0, x1 = 0;
     bool have = false;
     if (need_gate) {
-        const Words4 r = philox10((uint32_t)a.orig[v], t, a.replica, 0u, a.key0, a.key1);
+        const Words4 r = philox10(o, t, a.replica, 0u, a.key0, a.key1);
         x0 = r.w0;
         x1 = r.w1;
         have = true;
@@ -127,8 +127,24 @@ __device__ __forceinline__ bool decide(const GdiSweepArgs &a, int32_t v, uint32_
     const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
     if (dE <= 0) return true;
     if (dE > a.K) return false;
-    if (!have) x0 = philox10((uint32_t)a.orig[v], t, a.replica, 0u, a.key0, a.key1).w0;
+    if (!have) x0 = philox10(o, t, a.replica, 0u, a.key0, a.key1).w0;
     return x0 < thr_row[dE];
+}
+
+__device__ __forceinline__ bool decide(const GdiSweepArgs &a, int32_t v, uint32_t t, int32_t sigma,
+                                       int32_t h, const PhaseView &pv, const uint32_t *thr_row)
+{
+    return decide_id(a, (uint32_t)a.orig[v], t, sigma, h, pv, thr_row);
+}
+
+// Launch gate of the masked sweeps: the active-set kernel and the full-graph
+// kernels are both enqueued and exactly one of them runs, chosen on the device from
+// the number of active nodes (the same value for every workgroup).
+__device__ __forceinline__ bool gate_open(const GdiSweepArgs &a)
+{
+    if (!a.skip_count) return true;
+    const int64_t active = (int64_t)a.n - (int64_t)*a.skip_count;
+    return (active <= a.active_max) == (a.gate_small != 0);
 }
 
 // One node of the current class: L lanes share its CSR row. All L lanes return
@@ -214,6 +230,7 @@ __device__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp, int32_t *Psh, i
 template <int L, bool SPIN_LDS>
 __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_wg(GdiSweepArgs a)
 {
+    if (!gate_open(a)) return;
     extern __shared__ int32_t dyn[];
     __shared__ int32_t acc[3];
     int32_t *Psh = dyn;
@@ -241,13 +258,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_wg(GdiSweepArgs a)
     if ((tid & 63) == 0 && w != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)w);
 }
 
-// ------------------------------------------------------------------ batched form
-// One persistent launch over many independent instances (graph, replica): each
-// workgroup takes the next instance from an atomic queue (the host orders the
-// queue longest first), builds its initial state in LDS (Philox spins, M, per-class
-// counts, cut), runs every sweep with the same per-phase code as k_sweep_wg, and
-// writes spins (original order), M and the tracked cut. Workgroups never wait on
-// each other, so the launch needs no co-residency and always drains.
+// Class of new id v: the last c with cbeg[c] <= v.
 __device__ __forceinline__ int32_t class_of(const int32_t *cbeg, int32_t C, int32_t v)
 {
     int32_t lo = 0, hi = C - 1;  // last c with cbeg[c] <= v
@@ -258,6 +269,140 @@ __device__ __forceinline__ int32_t class_of(const int32_t *cbeg, int32_t C, int3
     return lo;
 }
 
+// ------------------------------------------------------------------ active-set sweeps
+// Masked sweeps of the learned proposal in one workgroup when few nodes are active:
+// every spin of the graph is one bit in LDS (so neighbour reads never leave the CU),
+// the active nodes (mask bit clear, real ids) are compacted at the start into
+// records {new id, row, original id} in class order, and a class with no active node
+// takes no phase at all -- nothing in it can change, so M and the class counts stay.
+// The decisions are those of the full-graph kernels with the mask applied.
+__global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_active(GdiSweepArgs a, GdiActiveRec *rec)
+{
+    if (!gate_open(a)) return;
+    extern __shared__ uint32_t lds[];
+    const int32_t nw = a.n_pad >> 5;
+    uint32_t *bits = lds;                                           // n_pad spin bits (1 = +1)
+    int32_t *abeg = reinterpret_cast<int32_t *>(lds + nw);          // C + 1 record offsets
+    int32_t *Psh = abeg + a.C + 1;                                  // C counts of +1
+    __shared__ int32_t acc[3];
+    __shared__ int32_t wtot[GDI_MAX_BLOCK / 64];
+    __shared__ int32_t base_sh;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = nth >> 6;
+
+    // spins -> bits, 64 ids per wave step (n_pad is a multiple of 64)
+    for (int32_t b0 = wave * 64; b0 < a.n_pad; b0 += nwaves * 64) {
+        const uint64_t b = __ballot(a.spin[b0 + lane] > 0);
+        if (lane == 0) {
+            bits[b0 >> 5] = (uint32_t)b;
+            bits[(b0 >> 5) + 1] = (uint32_t)(b >> 32);
+        }
+    }
+    for (int i = tid; i < a.C; i += nth) Psh[i] = a.P[i];
+    if (tid < 3) acc[tid] = 0;
+    if (tid == 0) base_sh = 0;
+    int32_t M = (int32_t)a.state[0];
+    __syncthreads();
+
+    // compaction: one 64-id chunk per thread per round; chunks never straddle classes
+    const int32_t nch = a.n_pad >> 6;
+    for (int32_t r0 = 0; r0 < nch; r0 += nth) {
+        const int32_t ch = r0 + tid;
+        uint64_t act = 0;
+        int32_t c = -1;
+        if (ch < nch) {
+            const int32_t v0 = ch << 6;
+            c = class_of(a.cbeg, a.C, v0);
+            const int32_t nv = min(64, max(0, a.cbeg[c] + a.csz[c] - v0));
+            const uint64_t valid = nv == 64 ? ~0ull : ((1ull << nv) - 1ull);
+            const uint64_t m = a.mask ? ((uint64_t)a.mask[2 * ch] | ((uint64_t)a.mask[2 * ch + 1] << 32)) : 0ull;
+            act = valid & ~m;
+            if (v0 != a.cbeg[c]) c = -1;  // c >= 0 only on the first chunk of a class
+        }
+        const int32_t cnt = __popcll(act);
+        int32_t incl = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wtot[wave] = incl;
+        __syncthreads();
+        int32_t before = 0, round_total = 0;
+        for (int w = 0; w < nwaves; ++w) {
+            before += w < wave ? wtot[w] : 0;
+            round_total += wtot[w];
+        }
+        int32_t pos = base_sh + before + incl - cnt;
+        if (c >= 0) abeg[c] = pos;
+        for (uint64_t x = act; x; x &= x - 1) {
+            const int32_t v = (ch << 6) + __ffsll((unsigned long long)x) - 1;
+            rec[pos++] = GdiActiveRec{v, a.rp[v], a.rp[v + 1], a.orig[v]};
+        }
+        __syncthreads();
+        if (tid == 0) base_sh += round_total;
+        __syncthreads();
+    }
+    if (tid == 0) abeg[a.C] = base_sh;
+    __syncthreads();
+
+    int64_t dcut = 0;
+    uint32_t p = 0;
+    for (uint32_t t = a.t0; t < a.S; ++t) {
+        const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)(a.K + 1);
+        for (int32_t c = 0; c < a.C; ++c) {
+            const int32_t jb = abeg[c], je = abeg[c + 1];
+            if (jb == je) continue;
+            const PhaseView pv = make_view(M, Psh[c], a.csz[c], a.C, a.n);
+            int32_t dM = 0;
+            for (int32_t j = jb + tid; j < je; j += nth) {
+                const GdiActiveRec r = rec[j];
+                int32_t h = 0;
+                for (int32_t k = r.r0; k < r.r1; ++k) {
+                    const int2 e = a.adj[k];
+                    h += ((bits[e.x >> 5] >> (e.x & 31)) & 1u) ? e.y : -e.y;
+                }
+                const int32_t sigma = ((bits[r.v >> 5] >> (r.v & 31)) & 1u) ? 1 : -1;
+                if (decide_id(a, (uint32_t)r.orig, t, sigma, h, pv, thr_row)) {
+                    // members of a class are never neighbours: other readers of this word
+                    // only look at bits that do not change in this phase
+                    atomicXor(&bits[r.v >> 5], 1u << (r.v & 31));
+                    dM -= 2 * sigma;
+                    dcut += (int64_t)sigma * h;
+                    if (a.last_flip) a.last_flip[r.v] = (int32_t)t;
+                }
+            }
+            dM = wave_sum_i32(dM);
+            if (lane == 0 && dM != 0) atomicAdd(&acc[p % 3], dM);
+            __syncthreads();
+            const int32_t tot = acc[p % 3];
+            M += tot;
+            if (tid == 0) {
+                if (a.C > 1) Psh[c] += tot / 2;
+                acc[(p + 2) % 3] = 0;
+            }
+            ++p;
+        }
+    }
+    __syncthreads();
+    // only active nodes can have changed
+    for (int32_t j = tid; j < abeg[a.C]; j += nth) {
+        const int32_t v = rec[j].v;
+        a.spin[v] = ((bits[v >> 5] >> (v & 31)) & 1u) ? (int8_t)1 : (int8_t)-1;
+    }
+    for (int i = tid; i < a.C; i += nth) a.P[i] = Psh[i];
+    if (tid == 0) a.state[0] = M;
+    const int64_t w = wave_sum_i64(dcut);
+    if (lane == 0 && w != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)w);
+}
+
+// ------------------------------------------------------------------ batched form
+// One persistent launch over many independent instances (graph, replica): each
+// workgroup takes the next instance from an atomic queue (the host orders the
+// queue longest first), builds its initial state in LDS (Philox spins, M, per-class
+// counts, cut), runs every sweep with the same per-phase code as k_sweep_wg, and
+// writes spins (original order), M and the tracked cut. Workgroups never wait on
+// each other, so the launch needs no co-residency and always drains.
 __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_batch(GdiBatchArgs ba)
 {
     extern __shared__ int32_t dyn[];
@@ -397,6 +542,7 @@ __device__ __forceinline__ bool grid_phase_sync(const GdiSweepArgs &a, uint32_t 
 template <int L>
 __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_grid(GdiSweepArgs a)
 {
+    if (!gate_open(a)) return;
     extern __shared__ int32_t Psh[];
     __shared__ int32_t wg_acc;
     __shared__ int32_t total;
@@ -622,6 +768,7 @@ __device__ __forceinline__ bool poll_word(const uint64_t *w, uint32_t epoch, int
 __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
 {
     const GdiSweepArgs &a = h.base;
+    if (!gate_open(a)) return;
     extern __shared__ uint32_t lds[];
     uint32_t *bits = lds;                                                   // window bits
     GdiHaloEntry *tab = reinterpret_cast<GdiHaloEntry *>(lds + h.lds_words); // C entries
@@ -1020,6 +1167,23 @@ int gdi_launch_sweep_wg(const GdiSweepArgs &a, int block, int lanes, int spins_i
     GdiSweepArgs copy = a;
     void *args[] = {&copy};
     e = hipLaunchKernel(f, dim3(1), dim3(block), args, (size_t)lds, (hipStream_t)stream);
+    return status(e);
+}
+
+int gdi_active_lds_bytes(int32_t n_pad, int32_t C)
+{
+    return (n_pad / 32) * 4 + (2 * C + 1) * 4;
+}
+
+int gdi_launch_sweep_active(const GdiSweepArgs &a, GdiActiveRec *rec, void *stream)
+{
+    const void *f = (const void *)k_sweep_active;
+    const int lds = gdi_active_lds_bytes(a.n_pad, a.C);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return status(e);
+    GdiSweepArgs copy = a;
+    void *args[] = {&copy, &rec};
+    e = hipLaunchKernel(f, dim3(1), dim3(GDI_MAX_BLOCK), args, (size_t)lds, (hipStream_t)stream);
     return status(e);
 }
 

@@ -105,9 +105,10 @@ __global__ void k_mask_heuristic(const int32_t *last_flip, int32_t n_pad, int32_
     mask[w] = bits;
 }
 
-// Clears the bits of padding ids and counts the skipped node visits (bits x weight).
+// Clears the bits of padding ids, counts the skipped nodes of this block into
+// block_skips and the skipped node visits (bits x weight) into skipped.
 __global__ void k_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad, unsigned long long *skipped,
-                              uint32_t weight)
+                              uint32_t weight, unsigned long long *block_skips)
 {
     const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t bits = 0;
@@ -119,10 +120,13 @@ __global__ void k_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad
         }
         mask[w] = bits;
     }
-    unsigned long long c = (unsigned long long)__popc(bits) * weight;
+    unsigned long long c = (unsigned long long)__popc(bits);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(skipped, c);
+    if ((threadIdx.x & 63) == 0 && c) {
+        atomicAdd(skipped, c * weight);
+        atomicAdd(block_skips, c);
+    }
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t value)
@@ -457,10 +461,10 @@ int gdi_launch_mask_heuristic(const int32_t *last_flip, int32_t n_pad, int32_t t
 }
 
 int gdi_launch_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad, uint64_t *skipped, uint32_t weight,
-                           void *stream)
+                           uint64_t *block_skips, void *stream)
 {
     hipLaunchKernelGGL(k_mask_finish, dim3(nblk((n_pad + 31) / 32, 256)), dim3(256), 0, (hipStream_t)stream, mask, orig,
-                       n_pad, (unsigned long long *)skipped, weight);
+                       n_pad, (unsigned long long *)skipped, weight, (unsigned long long *)block_skips);
     return (int)hipGetLastError();
 }
 

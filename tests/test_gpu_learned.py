@@ -65,20 +65,39 @@ def test_no_proposal_equals_plain_anneal(gdi, oracle_lib, scope):
     assert r["result"]["node_visits"] == g.n * T.size
 
 
-@pytest.mark.parametrize("scope,k_full,hk", [(1, 4, 1), (1, 7, 3), (2, 5, 2), (3, 3, 1), (2, 10, 4)])
-def test_heuristic_proposal_bit_exact(gdi, L, scope, k_full, hk):
+# active_max: 0 automatic, -1 never the active-set sweep, 10**6 always, 2000 mixed
+# (early blocks with many active nodes on the full-graph kernel, late ones on the active set)
+@pytest.mark.parametrize("scope,k_full,hk,amax", [(1, 4, 1, 0), (1, 7, 3, -1), (2, 5, 2, 0), (2, 5, 2, -1),
+                                                  (3, 3, 1, 0), (3, 6, 2, 2000), (2, 10, 4, 2000),
+                                                  (2, 8, 1, 10**6)])
+def test_heuristic_proposal_bit_exact(gdi, L, scope, k_full, hk, amax):
     g = gs.rgg_graph(5000, 10.0, 51, "pm1")
     T = gs.geometric_temps(3.0, 0.05, 83)
-    print(f"[case] learned heuristic scope={scope} k={k_full} hk={hk}", flush=True)
+    print(f"[case] learned heuristic scope={scope} k={k_full} hk={hk} active_max={amax}", flush=True)
     ref = L.learned_anneal(g, T, 9, k_full=k_full, proposal="heuristic", heuristic_k=hk)
     with gdi.Annealer(g) as a:
         a.tune(scope=scope)
-        r = a.anneal_learned(T, 9, k_full, skip_mode=gdi.SKIP_HEURISTIC, heuristic_k=hk, mask_trace=True)
+        r = a.anneal_learned(T, 9, k_full, skip_mode=gdi.SKIP_HEURISTIC, heuristic_k=hk, mask_trace=True,
+                             active_max=amax)
     assert np.array_equal(r["masks"], ref["masks"])
     assert np.array_equal(r["spins"], ref["spins"]) and (r["M"], r["cut"]) == (ref["M"], ref["cut"])
     skips = skipped_visits(ref["masks"], T.size, k_full)
     assert r["result"]["node_skips"] == skips > 0
     assert r["result"]["node_visits"] == g.n * T.size - skips
+
+
+def test_active_set_sweep_on_large_graph(gdi, L):
+    """The one-workgroup active-set sweep on a graph run by the grid kernel (n = 150k)."""
+    g = gs.rgg_graph(150_000, 8.0, 56, "pm1")
+    T = gs.geometric_temps(3.0, 0.05, 60)
+    ref = L.learned_anneal(g, T, 4, k_full=6, proposal="heuristic", heuristic_k=2)
+    with gdi.Annealer(g) as a:
+        r = a.anneal_learned(T, 4, 6, skip_mode=gdi.SKIP_HEURISTIC, heuristic_k=2, mask_trace=True,
+                             active_max=60_000)
+    assert np.array_equal(r["masks"], ref["masks"])
+    assert np.array_equal(r["spins"], ref["spins"]) and (r["M"], r["cut"]) == (ref["M"], ref["cut"])
+    active = g.n - ref["masks"].sum(axis=1)
+    assert (active[:-1] <= 60_000).any() and (active[:-1] > 60_000).any()  # both kernels ran
 
 
 def test_heuristic_resume_and_odd_n(gdi, L, oracle_lib):
@@ -94,8 +113,8 @@ def test_heuristic_resume_and_odd_n(gdi, L, oracle_lib):
     assert np.array_equal(r["spins"], ref["spins"]) and r["cut"] == ref["cut"]
 
 
-@pytest.mark.parametrize("scope", [1, 2])
-def test_network_proposal_matches_oracle(gdi, L, scope):
+@pytest.mark.parametrize("scope,amax", [(1, 0), (2, 0), (2, -1)])
+def test_network_proposal_matches_oracle(gdi, L, scope, amax):
     """Masks from the BF16 network on the GPU against the oracle's kernel-precision
     decisions; with identical masks the whole trajectory is bit-exact. A mask bit may
     differ only where the oracle's logit lies within 1e-4 of the threshold (FP32
@@ -104,11 +123,12 @@ def test_network_proposal_matches_oracle(gdi, L, scope):
     g = gs.rgg_graph(3000, 8.0, 60, "pm1")
     T = gs.geometric_temps(3.0, 0.05, 120)
     w = centred_weights(L, g, 26)
-    print(f"[case] learned network scope={scope}", flush=True)
+    print(f"[case] learned network scope={scope} active_max={amax}", flush=True)
     ref = L.learned_anneal(g, T, 7, k_full=5, proposal="network", weights=w, p=0.5)
     with gdi.Annealer(g) as a:
         a.tune(scope=scope)
-        r = a.anneal_learned(T, 7, 5, skip_mode=gdi.SKIP_MLP, weights=w, skip_threshold=0.5, mask_trace=True)
+        r = a.anneal_learned(T, 7, 5, skip_mode=gdi.SKIP_MLP, weights=w, skip_threshold=0.5, mask_trace=True,
+                             active_max=amax)
     diff_rows = np.flatnonzero(np.any(r["masks"] != ref["masks"], axis=1))
     print(f"oracle min margin {min(ref['margins']):.2e}, skipped fraction {ref['masks'].mean():.3f}, "
           f"rows differing: {diff_rows.tolist()}", flush=True)
