@@ -83,9 +83,13 @@ struct gdi_graph {
     std::vector<int32_t> cls;         // class of each new id (-1 padding)
 
     // halo layout for one grid size (k_sweep_halo)
-    int32_t halo_G = 0;
+    int32_t halo_G = 0, halo_nwork = 0;
     int32_t halo_lds_words = -1;      // -1: not built; -2: does not fit LDS
+    int32_t halo_T0 = 0, halo_tail_n = 0, halo_gather_off = 0, halo_tail_off = 0;
+    int32_t halo_tail_nnz = 0, halo_trp_off = 0, halo_tent_off = 0;
     DevBuf<int2> d_adjL;
+    DevBuf<int32_t> d_tail_v, d_tail_beg, d_gat_words, d_gat_beg, d_tail_rp;
+    DevBuf<int2> d_tail_ent;
     DevBuf<GdiHaloEntry> d_tab;
     DevBuf<uint64_t> d_words, d_member, d_group;
 
@@ -116,7 +120,9 @@ struct gdi_graph {
         d_rp.release(); d_orig.release(); d_cbeg.release(); d_csz.release(); d_P.release();
         d_adj.release(); d_spin.release(); d_io.release(); d_state.release(); d_red.release();
         d_trace.release(); d_thr.release(); d_bar.release();
-        d_adjL.release(); d_tab.release(); d_words.release(); d_member.release(); d_group.release();
+        d_adjL.release(); d_tail_v.release(); d_tail_beg.release(); d_gat_words.release(); d_gat_beg.release();
+        d_tail_rp.release(); d_tail_ent.release();
+        d_tab.release(); d_words.release(); d_member.release(); d_group.release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
     }
@@ -214,7 +220,7 @@ int lanes_for_degree(double avg_deg)
 const int64_t kSpinLimit = int64_t(1) << 22;
 const int32_t kWgMaxNodes = 65536;
 
-int build_halo(gdi_graph *g, int32_t G, int lds_budget);
+int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork);
 
 int pick_launch(gdi_graph *g, Choice *ch)
 {
@@ -248,11 +254,12 @@ int pick_launch(gdi_graph *g, Choice *ch)
         if (block < 256) return fail(GDI_EINVAL, "the grid sweep needs at least 256 threads per workgroup");
         if (G < 8 || G % 8 || G > GDI_HALO_MAX_GRID)
             return fail(GDI_EINVAL, "the grid sweep needs a grid that is a multiple of 8 in [8, 512]");
-        int rc = build_halo(g, (int32_t)G, lds_max - 256);
+        int rc = build_halo(g, (int32_t)G, lds_max - 256, (int32_t)block - 128);
         if (rc) return rc;
         if (g->halo_lds_words >= 0) {
             int cap = 0;
-            int e = gdi_halo_capacity((int)block, gdi_halo_lds_bytes(g->halo_lds_words, g->C, 2 * (GDI_HALO_THR_MAX + 1)), &cap);
+            // without the threshold rows: they are staged in LDS only when they fit beside the image
+            int e = gdi_halo_capacity((int)block, gdi_halo_lds_bytes(g->halo_lds_words, g->C, 0), &cap);
             if (e) return fail(GDI_EDEVICE, std::string("occupancy query: ") + gdi_hip_error_string(e));
             if ((int)G > cap)
                 return fail(GDI_EDEVICE, "grid of " + std::to_string(G) + " workgroups cannot be co-resident (capacity " +
@@ -360,11 +367,9 @@ int upload(gdi_graph *g, const int32_t *rp, const int32_t *col, const int32_t *w
 // over the 8 XCDs, so XCD x gets the contiguous chunk range [x*G/8, (x+1)*G/8).
 inline int32_t chunk_of_block(int32_t b, int32_t G) { return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b; }
 
-// Builds the halo layout for grid size G: own chunks, windows of the packed spin
-// array per (workgroup, class), LDS offsets and the CSR with LDS bit indices.
-int build_halo(gdi_graph *g, int32_t G, int lds_budget)
+// Halo layout with the tail starting at class T0 (T0 == C: none).
+int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
 {
-    if (g->halo_G == G && g->halo_lds_words != -1) return GDI_OK;
     const int32_t C = g->C;
     std::vector<int32_t> chunk((size_t)C), blk_of_q((size_t)G);
     for (int32_t b = 0; b < G; ++b) blk_of_q[(size_t)chunk_of_block(b, G)] = b;
@@ -380,6 +385,7 @@ int build_halo(gdi_graph *g, int32_t G, int lds_budget)
         for (int32_t c = 0; c < C; ++c) {
             GdiHaloEntry &e = tab[(size_t)b * C + c];
             std::memset(&e, 0, sizeof(e));
+            if (c >= T0) continue;  // tail classes: no own chunks, no windows
             const int64_t lo = (int64_t)g->cbeg[(size_t)c] + (int64_t)q * chunk[(size_t)c];
             const int64_t hi = std::min<int64_t>((int64_t)g->cbeg[(size_t)c] + g->csz[(size_t)c], lo + chunk[(size_t)c]);
             if (lo < hi) {
@@ -395,15 +401,31 @@ int build_halo(gdi_graph *g, int32_t G, int lds_budget)
         const int32_t c = g->cls[(size_t)v];
         return blk_of_q[(size_t)((v - g->cbeg[(size_t)c]) / chunk[(size_t)c])];
     };
+    // gather lists: the packed words of classes < T0 that tail nodes read
+    std::vector<std::vector<int32_t>> gat((size_t)T0);
     for (int32_t v = 0; v < g->n_pad; ++v) {
-        if (g->cls[(size_t)v] < 0) continue;
-        const int32_t b = owner(v);
+        const int32_t cv = g->cls[(size_t)v];
+        if (cv < 0) continue;
         for (int32_t k = g->h_rp[(size_t)v]; k < g->h_rp[(size_t)v + 1]; ++k) {
             const int32_t j = g->h_adj[(size_t)k].x;
-            const size_t i = (size_t)b * C + g->cls[(size_t)j];
+            const int32_t cj = g->cls[(size_t)j];
+            if (cj >= T0) continue;  // tail neighbours live in the tail region
+            if (cv >= T0) {
+                gat[(size_t)cj].push_back(j >> 5);
+                continue;
+            }
+            const size_t i = (size_t)owner(v) * C + cj;
             wlo[i] = std::min<int32_t>(wlo[i], j >> 5);
             whi[i] = std::max<int32_t>(whi[i], (j >> 5) + 1);
         }
+    }
+    std::vector<int32_t> gat_beg((size_t)T0 + 1, 0), gat_words;
+    for (int32_t c = 0; c < T0; ++c) {
+        std::vector<int32_t> &L = gat[(size_t)c];
+        std::sort(L.begin(), L.end());
+        L.erase(std::unique(L.begin(), L.end()), L.end());
+        gat_words.insert(gat_words.end(), L.begin(), L.end());
+        gat_beg[(size_t)c + 1] = (int32_t)gat_words.size();
     }
     int32_t lds_words = 0;
     for (int32_t b = 0; b < G; ++b) {
@@ -423,19 +445,66 @@ int build_halo(gdi_graph *g, int32_t G, int lds_budget)
         }
         lds_words = std::max(lds_words, off);
     }
-    g->halo_G = G;
+    const int32_t tail_base = T0 < C ? g->cbeg[(size_t)T0] : g->n_pad;  // multiple of 64
+    int32_t tail_n = 0, tail_nnz = 0;
+    for (int32_t c = T0; c < C; ++c) {
+        tail_n += g->csz[(size_t)c];
+        for (int32_t v = g->cbeg[(size_t)c]; v < g->cbeg[(size_t)c] + g->csz[(size_t)c]; ++v)
+            tail_nnz += g->h_rp[(size_t)v + 1] - g->h_rp[(size_t)v];
+    }
+    // LDS image: windows | gather words | tail spin bits | tail row offsets | tail entries
+    const int32_t gather_off = lds_words;
+    const int32_t tail_off = gather_off + (int32_t)gat_words.size();
+    const int32_t trp_off = tail_off + (g->n_pad - tail_base) / 32;
+    const int32_t tent_off = (trp_off + (T0 < C ? tail_n + 1 : 0) + 1) & ~1;  // 8-byte aligned
+    lds_words = tent_off + 2 * tail_nnz;
     if (gdi_halo_lds_bytes(lds_words, C, 0) > lds_budget) {
         g->halo_lds_words = -2;
         return GDI_OK;
     }
-    std::vector<int2> adjL(g->h_adj.size());
+    auto tail_lb = [&](int32_t j) { return (tail_off + ((j - tail_base) >> 5)) * 32 + (j & 31); };
+    auto gather_lb = [&](int32_t j) {
+        const int32_t c = g->cls[(size_t)j];
+        const auto b0 = gat_words.begin() + gat_beg[(size_t)c], b1 = gat_words.begin() + gat_beg[(size_t)c + 1];
+        const auto it = std::lower_bound(b0, b1, j >> 5);
+        if (it == b1 || *it != (j >> 5)) return -1;  // rejected by the range check below
+        return (gather_off + (int32_t)(it - gat_words.begin())) * 32 + (j & 31);
+    };
+    std::vector<int32_t> tail_v, tail_beg((size_t)(C - T0) + 1, 0), tail_rp(1, 0);
+    std::vector<int2> tail_ent;
+    for (int32_t c = T0; c < C; ++c) {
+        for (int32_t v = g->cbeg[(size_t)c]; v < g->cbeg[(size_t)c] + g->csz[(size_t)c]; ++v) {
+            tail_v.push_back(v);
+            for (int32_t k = g->h_rp[(size_t)v]; k < g->h_rp[(size_t)v + 1]; ++k) {
+                const int32_t j = g->h_adj[(size_t)k].x;
+                const int32_t lb = g->cls[(size_t)j] >= T0 ? tail_lb(j) : gather_lb(j);
+                if (lb < 0 || lb >= trp_off * 32) return fail(GDI_EDEVICE, "internal error: tail index out of range");
+                tail_ent.push_back(make_int2(lb, g->h_adj[(size_t)k].y));
+            }
+            tail_rp.push_back((int32_t)tail_ent.size());
+        }
+        tail_beg[(size_t)(c - T0) + 1] = (int32_t)tail_v.size();
+    }
+    std::vector<int2> adjL(g->h_adj.size() + 1, make_int2(0, 0));  // last: the zero sentinel
     for (int32_t v = 0; v < g->n_pad; ++v) {
-        if (g->cls[(size_t)v] < 0) continue;
-        const int32_t b = owner(v);
+        const int32_t cv = g->cls[(size_t)v];
+        if (cv < 0) continue;
+        const int32_t b = cv < T0 ? owner(v) : -1;
         for (int32_t k = g->h_rp[(size_t)v]; k < g->h_rp[(size_t)v + 1]; ++k) {
             const int32_t j = g->h_adj[(size_t)k].x;
-            const GdiHaloEntry &e = tab[(size_t)b * C + g->cls[(size_t)j]];
-            const int32_t lb = (e.lds_off + (j >> 5) - e.win_lo) * 32 + (j & 31);
+            const int32_t cj = g->cls[(size_t)j];
+            int32_t lb;
+            if (cj >= T0) {
+                lb = tail_lb(j);
+            } else if (cv >= T0) {
+                lb = gather_lb(j);
+            } else {
+                const GdiHaloEntry &e = tab[(size_t)b * C + cj];
+                lb = (e.lds_off + (j >> 5) - e.win_lo) * 32 + (j & 31);
+            }
+            // every index must land inside this workgroup's LDS image (checked here so
+            // that a layout error surfaces as an error code, never as a device fault)
+            if (lb < 0 || lb >= lds_words * 32) return fail(GDI_EDEVICE, "internal error: halo index out of range");
             adjL[(size_t)k] = make_int2(lb, g->h_adj[(size_t)k].y);
         }
     }
@@ -447,7 +516,52 @@ int build_halo(gdi_graph *g, int32_t G, int lds_budget)
     if (!adjL.empty())
         HIP_TRY(hipMemcpy(g->d_adjL.p, adjL.data(), adjL.size() * sizeof(int2), hipMemcpyHostToDevice), "upload halo CSR");
     HIP_TRY(hipMemcpy(g->d_tab.p, tab.data(), tab.size() * sizeof(GdiHaloEntry), hipMemcpyHostToDevice), "upload halo table");
+    HIP_TRY(g->d_tail_v.reserve(std::max<size_t>(tail_v.size(), 1)), "hipMalloc halo tail");
+    HIP_TRY(g->d_tail_beg.reserve(tail_beg.size()), "hipMalloc halo tail");
+    HIP_TRY(g->d_gat_words.reserve(std::max<size_t>(gat_words.size(), 1)), "hipMalloc halo tail");
+    HIP_TRY(g->d_gat_beg.reserve(gat_beg.size()), "hipMalloc halo tail");
+    HIP_TRY(g->d_tail_rp.reserve(tail_rp.size()), "hipMalloc halo tail");
+    HIP_TRY(g->d_tail_ent.reserve(std::max<size_t>(tail_ent.size(), 1)), "hipMalloc halo tail");
+    HIP_TRY(hipMemcpy(g->d_tail_rp.p, tail_rp.data(), tail_rp.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
+    if (!tail_ent.empty())
+        HIP_TRY(hipMemcpy(g->d_tail_ent.p, tail_ent.data(), tail_ent.size() * sizeof(int2), hipMemcpyHostToDevice),
+                "upload halo tail");
+    if (!tail_v.empty())
+        HIP_TRY(hipMemcpy(g->d_tail_v.p, tail_v.data(), tail_v.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
+    HIP_TRY(hipMemcpy(g->d_tail_beg.p, tail_beg.data(), tail_beg.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
+    if (!gat_words.empty())
+        HIP_TRY(hipMemcpy(g->d_gat_words.p, gat_words.data(), gat_words.size() * 4, hipMemcpyHostToDevice),
+                "upload halo tail");
+    HIP_TRY(hipMemcpy(g->d_gat_beg.p, gat_beg.data(), gat_beg.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
     g->halo_lds_words = lds_words;
+    g->halo_T0 = T0;
+    g->halo_tail_n = (int32_t)tail_v.size();
+    g->halo_gather_off = gather_off;
+    g->halo_tail_off = tail_off;
+    g->halo_tail_nnz = (int32_t)tail_ent.size();
+    g->halo_trp_off = trp_off;
+    g->halo_tent_off = tent_off;
+    return GDI_OK;
+}
+
+// Builds the halo layout for grid size G: own chunks, windows of the packed spin
+// array per (workgroup, class), LDS offsets and the CSR with LDS bit indices.
+// Classes T0..C-1 form the redundant tail when they hold at most nwork nodes.
+int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork)
+{
+    if (g->halo_G == G && g->halo_nwork == nwork && g->halo_lds_words != -1) return GDI_OK;
+    const int32_t C = g->C;
+    int32_t T0 = C;
+    int64_t tail_n = 0;
+    while (T0 > 1 && tail_n + g->csz[(size_t)T0 - 1] <= nwork) tail_n += g->csz[(size_t)--T0];
+    for (;;) {
+        int rc = build_halo_for(g, G, lds_budget, T0);
+        if (rc) return rc;
+        if (g->halo_lds_words != -2 || T0 == C) break;
+        ++T0;  // the tail's regions do not fit: a shorter tail
+    }
+    g->halo_G = G;
+    g->halo_nwork = nwork;
     return GDI_OK;
 }
 
@@ -655,11 +769,25 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
         GdiHaloArgs ha{};
         ha.base = a;
         ha.adjL = g->d_adjL.p;
+        ha.sentinel = (int32_t)g->nnz;
         ha.tab = g->d_tab.p;
         ha.words = g->d_words.p;
         ha.member = g->d_member.p;
         ha.group = g->d_group.p;
         ha.lds_words = g->halo_lds_words;
+        ha.T0 = g->halo_T0;
+        ha.tail_n = g->halo_tail_n;
+        ha.gather_off = g->halo_gather_off;
+        ha.tail_off = g->halo_tail_off;
+        ha.tail_v = g->d_tail_v.p;
+        ha.tail_beg = g->d_tail_beg.p;
+        ha.gat_words = g->d_gat_words.p;
+        ha.gat_beg = g->d_gat_beg.p;
+        ha.tail_nnz = g->halo_tail_nnz;
+        ha.trp_off = g->halo_trp_off;
+        ha.tent_off = g->halo_tent_off;
+        ha.tail_rp = g->d_tail_rp.p;
+        ha.tail_ent = g->d_tail_ent.p;
         ha.thr_in_lds = r.thr_in_lds;
         rc = gdi_launch_fill_u64(g->d_words.p, (int64_t)g->n_pad / 32 + 1, st);
         if (!rc) rc = gdi_launch_fill_u64(g->d_member.p, 8 * 64, st);

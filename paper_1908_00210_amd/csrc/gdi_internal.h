@@ -79,13 +79,34 @@ struct GdiHaloEntry {          // one per (workgroup, class)
 
 struct GdiHaloArgs {
     GdiSweepArgs base;
-    const int2 *adjL;          // CSR with columns rewritten as LDS bit indices of the owner
+    const int2 *adjL;          // CSR with columns rewritten as LDS bit indices of the owner,
+                               // plus one zero entry {0, 0} at index sentinel
+    int32_t sentinel;          // = nnz
     const GdiHaloEntry *tab;   // grid x C entries
     uint64_t *words;           // packed spins: (epoch << 32) | 32 spin bits (bit = 1 for +1)
     uint64_t *member;          // 8 x 64 words: workgroup b posts (epoch << 32) | uint32(dM) at (b % 8) * 64 + b / 8
     uint64_t *group;           // 2 x 8 words (phase parity x group), GDI_HALO_GROUP_PAD apart
-    int32_t lds_words;         // window words per workgroup (max over workgroups)
+    int32_t lds_words;         // LDS words per workgroup: windows, then the tail's gather and tail regions
     int32_t thr_in_lds;        // 1: the current and next threshold rows are staged in LDS
+    // Redundant tail: the last classes T0..C-1 hold at most one node per worker thread
+    // in total; every workgroup runs them itself (identical results everywhere), so
+    // they take no grid-wide barrier. Tail spins live in a tail region of LDS (ids
+    // [cbeg[T0], n_pad)); the neighbours of tail nodes in classes < T0 are gathered
+    // into a gather region after their class's phase. T0 == C: no tail.
+    int32_t T0;
+    int32_t tail_n;            // tail nodes (<= worker threads)
+    int32_t gather_off;        // LDS word of the gather region
+    int32_t tail_off;          // LDS word of the tail region
+    const int32_t *tail_v;     // tail_n new ids, in class order
+    const int32_t *tail_beg;   // C - T0 + 1 offsets into tail_v per tail class
+    const int32_t *gat_words;  // packed-word ids gathered for the tail, by source class
+    const int32_t *gat_beg;    // T0 + 1 offsets into gat_words
+    // the tail's CSR, copied into LDS at trp_off (tail_n + 1 row offsets) and tent_off
+    // (tail_nnz entries {LDS bit index, weight}); thread i of the tail owns tail_v[i]
+    int32_t tail_nnz;
+    int32_t trp_off, tent_off;
+    const int32_t *tail_rp;
+    const int2 *tail_ent;
 };
 
 // Batched form: one instance (graph, replica) per queue entry.

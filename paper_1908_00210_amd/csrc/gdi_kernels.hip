@@ -727,14 +727,20 @@ __device__ __forceinline__ void load_entries(const GdiHaloArgs &h, const RowAhea
     pf.x1 = w.w1;
     pf.r0 = ra.r0;
     pf.deg = ra.r1 - ra.r0;
+    // every load is issued unconditionally (entries past the row read the zero entry
+    // at adjL[sentinel]): a register that is zeroed and then conditionally loaded
+    // makes the compiler wait for all earlier loads before zeroing it
 #pragma unroll
-    for (int k = 0; k < GDI_HALO_PF; ++k) pf.e[k] = k < pf.deg ? h.adjL[ra.r0 + k] : make_int2(0, 0);
+    for (int k = 0; k < GDI_HALO_PF; ++k) pf.e[k] = h.adjL[k < pf.deg ? ra.r0 + k : h.sentinel];
 }
 
-// Metropolis decision with the node's Philox words already drawn.
+// Metropolis decision with the node's Philox words already drawn. The threshold
+// row is read from LDS when staged there (thr_l), else from global memory (thr_g):
+// two explicit address spaces, so the lookup never becomes a generic access whose
+// wait would also wait for every outstanding global load.
 __device__ __forceinline__ bool decide_words(const GdiSweepArgs &a, int32_t sigma, int32_t h,
-                                             const PhaseView &pv, const uint32_t *thr, uint32_t x0,
-                                             uint32_t x1)
+                                             const PhaseView &pv, const uint32_t *thr_l, const uint32_t *thr_g,
+                                             bool in_lds, uint32_t x0, uint32_t x1)
 {
     int32_t m_seen;
     if (a.snapshot) {
@@ -747,7 +753,7 @@ __device__ __forceinline__ bool decide_words(const GdiSweepArgs &a, int32_t sigm
     const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
     if (dE <= 0) return true;
     if (dE > a.K) return false;
-    return x0 < thr[dE];
+    return x0 < (in_lds ? thr_l[dE] : thr_g[dE]);
 }
 
 // Bounded poll of one epoch-tagged word; returns false on timeout or abort.
@@ -765,12 +771,40 @@ __device__ __forceinline__ bool poll_word(const uint64_t *w, uint32_t epoch, int
     }
 }
 
+// Polls the tail's gather words of class c until they carry `epoch`, copying their
+// bits into the gather region. Same bounded wait as poll_window.
+__device__ __forceinline__ bool poll_gather(const GdiHaloArgs &h, int32_t c, uint32_t *bits, uint32_t epoch,
+                                            int first, int stride, int32_t *abort_sh)
+{
+    const int32_t g1 = h.gat_beg[c + 1];
+    for (int32_t i = h.gat_beg[c] + first; i < g1; i += stride) {
+        const uint64_t *src = h.words + h.gat_words[i];
+        for (int64_t tries = 0;; ++tries) {
+            const uint64_t w = ld_agent(src);
+            if ((uint32_t)(w >> 32) >= epoch) {
+                bits[h.gather_off + i] = (uint32_t)w;
+                break;
+            }
+            if (tries >= h.base.spin_limit || aborted(abort_sh)) return false;
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    return true;
+}
+
+// Node of worker thread tid in the first pass of class s, or -1.
+__device__ __forceinline__ int32_t step_node(const GdiHaloArgs &h, const GdiHaloEntry *tab, int32_t s, int tid)
+{
+    const int32_t v = tab[s].node_lo + tid;
+    return v < tab[s].node_hi ? v : -1;
+}
+
 __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
 {
     const GdiSweepArgs &a = h.base;
     if (!gate_open(a)) return;
     extern __shared__ uint32_t lds[];
-    uint32_t *bits = lds;                                                   // window bits
+    uint32_t *bits = lds;                                                   // windows, gather, tail
     GdiHaloEntry *tab = reinterpret_cast<GdiHaloEntry *>(lds + h.lds_words); // C entries
     int32_t *Psh = reinterpret_cast<int32_t *>(tab + a.C);                  // C counts of +1
     int32_t *csz_sh = Psh + a.C;                                            // C class sizes
@@ -778,6 +812,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     __shared__ int32_t wg_acc;
     __shared__ int32_t total_sh;
     __shared__ int32_t abort_sh;
+    __shared__ int32_t tacc[3];
 
     const int tid = threadIdx.x, nth = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = nth >> 6;
@@ -795,6 +830,17 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     // their window words.
     const int nwork = (nwaves - 2) * 64;
     const bool worker = tid < nwork;
+    const int32_t T0 = h.T0;
+    const bool has_tail = T0 < a.C;
+    const int32_t tail_base = has_tail ? a.cbeg[T0] : a.n_pad;  // a multiple of 64
+    // this thread's tail node, its class and original id (-1: none)
+    int32_t my_tail = -1, my_tc = -1, my_id = 0;
+    if (has_tail && worker && tid < h.tail_n) {
+        my_tail = h.tail_v[tid];
+        my_id = a.orig[my_tail];
+        for (int32_t k = 0; k < a.C - T0; ++k)
+            if (tid >= h.tail_beg[k] && tid < h.tail_beg[k + 1]) my_tc = T0 + k;
+    }
 
     for (int i = tid; i < a.C; i += nth) {
         tab[i] = h.tab[(size_t)b * a.C + i];
@@ -808,11 +854,13 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
         total_sh = 0;
         abort_sh = 0;
     }
+    if (tid < 3) tacc[tid] = 0;
     int32_t M = (int32_t)a.state[0];
     __syncthreads();
 
-    // prologue: publish own words of every class with epoch 1, then fill all windows
-    for (int32_t c = 0; c < a.C; ++c) {
+    // prologue: publish own words of every class with epoch 1, fill the tail region
+    // from the spin array, then fill all windows and the gather region
+    for (int32_t c = 0; c < T0; ++c) {
         const GdiHaloEntry e = tab[c];
         const int32_t w_lo = e.node_lo >> 5, w_hi = (e.node_hi + 31) >> 5;
         for (int32_t wd = w_lo + tid; wd < w_hi && e.node_lo < e.node_hi; wd += nth) {
@@ -825,21 +873,39 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
             st_agent(h.words + wd, (1ull << 32) | word);
         }
     }
+    for (int32_t b0 = tail_base + wave * 64; b0 < a.n_pad; b0 += nwaves * 64) {
+        const uint64_t m = __ballot(a.spin[b0 + lane] > 0);
+        if (lane == 0) {
+            bits[h.tail_off + ((b0 - tail_base) >> 5)] = (uint32_t)m;
+            bits[h.tail_off + ((b0 - tail_base) >> 5) + 1] = (uint32_t)(m >> 32);
+        }
+    }
+    // the tail's CSR (row offsets, then entries as LDS bit index and weight) stays in LDS
+    int32_t *trp = reinterpret_cast<int32_t *>(bits + h.trp_off);
+    int2 *tent = reinterpret_cast<int2 *>(bits + h.tent_off);
+    if (has_tail) {
+        for (int32_t i = tid; i <= h.tail_n; i += nth) trp[i] = h.tail_rp[i];
+        for (int32_t i = tid; i < h.tail_nnz; i += nth) tent[i] = h.tail_ent[i];
+    }
     // pipeline fill: phase 0 entries, phase 1 rows
     NodePrefetch pf;
     RowAhead ra;
     {
-        const uint32_t t1 = a.C > 1 ? a.t0 : a.t0 + 1u;
-        const int32_t c1 = a.C > 1 ? 1 : 0;
-        if (worker && a.t0 < a.S && tab[0].node_lo + tid < tab[0].node_hi) {
-            load_row(a, tab[0].node_lo + tid, ra);
+        const uint32_t t1 = T0 > 1 ? a.t0 : a.t0 + 1u;
+        const int32_t s1 = T0 > 1 ? 1 : 0;
+        const int32_t v0 = step_node(h, tab, 0, tid);
+        if (worker && a.t0 < a.S && v0 >= 0) {
+            load_row(a, v0, ra);
             load_entries(h, ra, a.t0, pf);
         }
-        if (worker && t1 < a.S && tab[c1].node_lo + tid < tab[c1].node_hi) load_row(a, tab[c1].node_lo + tid, ra);
+        const int32_t v1 = step_node(h, tab, s1, tid);
+        if (worker && t1 < a.S && v1 >= 0) load_row(a, v1, ra);
     }
     bool ok = true;
-    if (worker)
-        for (int32_t c = 0; c < a.C && ok; ++c) ok = poll_window(h, tab[c], bits, 1u, tid, nwork, abort_v);
+    if (worker) {
+        for (int32_t c = 0; c < T0 && ok; ++c) ok = poll_window(h, tab[c], bits, 1u, tid, nwork, abort_v);
+        for (int32_t c = 0; c < T0 && ok && has_tail; ++c) ok = poll_gather(h, c, bits, 1u, tid, nwork, abort_v);
+    }
     if (!ok) set_abort(abort_v);
     __syncthreads();
     if (abort_sh) {
@@ -848,10 +914,11 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     }
 
     int64_t dcut = 0, dcut_total = 0;
-    uint32_t p = 0;
+    uint32_t p = 0, kk = 0;
     for (uint32_t t = a.t0; t < a.S; ++t) {
-        const uint32_t *thr = thr_lds ? thr_sh + (t & 1u) * K1 : a.thr + (size_t)t * K1;
-        for (int32_t c = 0; c < a.C; ++c, ++p) {
+        const uint32_t *thr_l = thr_sh + (t & 1u) * K1;
+        const uint32_t *thr_g = a.thr + (size_t)t * K1;
+        for (int32_t c = 0; c < T0; ++c, ++p) {
             const GdiHaloEntry e = tab[c];
             const uint32_t epoch = p + 2u;
             int32_t dM = 0;
@@ -883,7 +950,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                         }
                         const int32_t lb = (e.lds_off + (v >> 5) - e.win_lo) * 32 + (v & 31);
                         const int32_t sigma = lds_spin(bits, lb);
-                        flip = decide_words(a, sigma, hv, pv, thr, q.x0, q.x1);
+                        flip = decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, q.x0, q.x1);
                         sigma_l = sigma;
                         if (flip) {
                             dcut += (int64_t)sigma * hv;
@@ -916,22 +983,24 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
             uint64_t *gw = h.group + (size_t)((p & 1u) * 8u) * GDI_HALO_GROUP_PAD;
             bool good = true;
             if (worker) {
-                // while the phase completes elsewhere: entries of phase p+1 (rows are
-                // already here), rows of phase p+2, next threshold row
-                const bool last_c = c + 1 == a.C;
-                const uint32_t t1 = last_c ? t + 1u : t;
-                const int32_t c1 = last_c ? 0 : c + 1;
-                const bool last_c1 = c1 + 1 == a.C;
-                const uint32_t t2 = last_c1 ? t1 + 1u : t1;
-                const int32_t c2 = last_c1 ? 0 : c1 + 1;
+                // while the phase completes elsewhere: entries of the next phase (rows are
+                // already here), rows of the phase after, next threshold row
+                const bool last_s = c + 1 == T0;
+                const uint32_t t1 = last_s ? t + 1u : t;
+                const int32_t s1 = last_s ? 0 : c + 1;
+                const bool last_s1 = s1 + 1 == T0;
+                const uint32_t t2 = last_s1 ? t1 + 1u : t1;
+                const int32_t s2 = last_s1 ? 0 : s1 + 1;
                 if (t1 < a.S) {
-                    if (last_c && thr_lds)
-                        for (int i = tid; i < K1; i += nwork) thr_sh[(t1 & 1u) * K1 + i] = a.thr[(size_t)t1 * K1 + i];
-                    if (tab[c1].node_lo + tid < tab[c1].node_hi) load_entries(h, ra, t1, pf);
+                    if (c + 1 == T0 && thr_lds && t + 1u < a.S)
+                        for (int i = tid; i < K1; i += nwork) thr_sh[((t + 1u) & 1u) * K1 + i] = a.thr[(size_t)(t + 1u) * K1 + i];
+                    if (step_node(h, tab, s1, tid) >= 0) load_entries(h, ra, t1, pf);
                 }
-                if (t2 < a.S && tab[c2].node_lo + tid < tab[c2].node_hi) load_row(a, tab[c2].node_lo + tid, ra);
+                const int32_t v2 = step_node(h, tab, s2, tid);
+                if (t2 < a.S && v2 >= 0) load_row(a, v2, ra);
                 GDI_TSTAMP(6, tid == 0);
                 good = poll_window(h, e, bits, epoch, tid, nwork, abort_v);
+                if (good && has_tail) good = poll_gather(h, c, bits, epoch, tid, nwork, abort_v);
                 GDI_TSTAMP(7, tid == 0);
             } else if (wave == nwaves - 1) {
                 // this wave has no other memory traffic, so its store leaves at once
@@ -964,6 +1033,42 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
             M += tot;
             if (tid == 0 && a.C > 1) Psh[c] += tot / 2;
         }
+        if (has_tail) {
+            // the tail, identically in every workgroup: one class after the other with
+            // workgroup barriers only; dM through a rotating triple of LDS accumulators.
+            // Its CSR is in LDS, so no global load is in flight across these barriers.
+            for (int32_t tc = T0; tc < a.C; ++tc, ++kk) {
+                int32_t dM = 0;
+                if (worker && my_tc == tc && !(a.mask && ((a.mask[my_tail >> 5] >> (my_tail & 31)) & 1u))) {
+                    const PhaseView pv = make_view(M, Psh[tc], csz_sh[tc], a.C, a.n);
+                    const int32_t v = my_tail;
+                    const Words4 xw = philox10((uint32_t)my_id, t, a.replica, 0u, a.key0, a.key1);
+                    int32_t hv = 0;
+                    for (int32_t k = trp[tid]; k < trp[tid + 1]; ++k) hv += tent[k].y * lds_spin(bits, tent[k].x);
+                    const int32_t lb = (h.tail_off + ((v - tail_base) >> 5)) * 32 + (v & 31);
+                    const int32_t sigma = lds_spin(bits, lb);
+                    if (decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, xw.w0, xw.w1)) {
+                        // members of a class are never neighbours: concurrent readers of this
+                        // word only look at bits that do not change in this class
+                        atomicXor(&bits[lb >> 5], 1u << (lb & 31));
+                        dM = -2 * sigma;
+                        if (b == 0) {
+                            dcut += (int64_t)sigma * hv;
+                            if (a.last_flip) a.last_flip[v] = (int32_t)t;
+                        }
+                    }
+                }
+                dM = wave_sum_i32(dM);
+                if (lane == 0 && dM != 0) atomicAdd(&tacc[kk % 3], dM);
+                __syncthreads();
+                const int32_t tot = tacc[kk % 3];
+                M += tot;
+                if (tid == 0) {
+                    Psh[tc] += tot / 2;
+                    tacc[(kk + 2) % 3] = 0;
+                }
+            }
+        }
         if (a.trace_m) {
             if (b == 0 && tid == 0) a.trace_m[t] = M;
             const int64_t w = wave_sum_i64(dcut);
@@ -974,8 +1079,8 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     }
     dcut_total += dcut;
     __syncthreads();
-    // epilogue: own spins back to the int8 array
-    for (int32_t c = 0; c < a.C; ++c) {
+    // epilogue: own spins back to the int8 array (the tail from workgroup 0)
+    for (int32_t c = 0; c < T0; ++c) {
         const GdiHaloEntry e = tab[c];
         for (int32_t v = e.node_lo + tid; v < e.node_hi; v += nth) {
             const int32_t lb = (e.lds_off + (v >> 5) - e.win_lo) * 32 + (v & 31);
@@ -983,6 +1088,10 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
         }
     }
     if (b == 0) {
+        for (int32_t i = tid; i < h.tail_n; i += nth) {
+            const int32_t v = h.tail_v[i];
+            a.spin[v] = (int8_t)lds_spin(bits, (h.tail_off + ((v - tail_base) >> 5)) * 32 + (v & 31));
+        }
         for (int i = tid; i < a.C; i += nth) a.P[i] = Psh[i];
         if (tid == 0) a.state[0] = M;
     }
