@@ -84,12 +84,12 @@ struct gdi_graph {
 
     // halo layout for one grid size (k_sweep_halo)
     int32_t halo_G = 0, halo_nwork = 0;
-    int32_t halo_lds_words = -1;      // -1: not built; -2: does not fit LDS
+    int32_t halo_lds_words = -1;      // -1: not built; -2: does not fit LDS; -3: weights too large
     int32_t halo_T0 = 0, halo_tail_n = 0, halo_gather_off = 0, halo_tail_off = 0;
     int32_t halo_tail_nnz = 0, halo_trp_off = 0, halo_tent_off = 0;
-    DevBuf<int2> d_adjL;
+    DevBuf<uint32_t> d_adjL;
     DevBuf<int32_t> d_tail_v, d_tail_beg, d_gat_words, d_gat_beg, d_tail_rp;
-    DevBuf<int2> d_tail_ent;
+    DevBuf<uint32_t> d_tail_ent;
     DevBuf<GdiHaloEntry> d_tab;
     DevBuf<uint64_t> d_words, d_member, d_group;
 
@@ -250,11 +250,19 @@ int pick_launch(gdi_graph *g, Choice *ch)
     if (ch->scope == GDI_SCOPE_GRID) {
         // fence-free halo sweep: one node per thread, 1024-thread workgroups, grid a multiple of 8
         const uint32_t block = t.block ? t.block : 1024u;
-        uint32_t G = t.grid ? t.grid : (uint32_t)std::min(cus, GDI_HALO_MAX_GRID) / 8u * 8u;
+        // automatic grid: about 1,500 nodes per workgroup, at most one workgroup per CU
+        // (measured on 2e5 and 1e6-node RGGs: 128 and 256 workgroups are fastest)
+        const int64_t g_cap = (int64_t)std::min(cus, GDI_HALO_MAX_GRID) / 8 * 8;
+        uint32_t G = t.grid ? t.grid : (uint32_t)std::max<int64_t>(8, std::min<int64_t>(g_cap, g->n / 1536 / 8 * 8));
         if (block < 256) return fail(GDI_EINVAL, "the grid sweep needs at least 256 threads per workgroup");
         if (G < 8 || G % 8 || G > GDI_HALO_MAX_GRID)
             return fail(GDI_EINVAL, "the grid sweep needs a grid that is a multiple of 8 in [8, 512]");
-        int rc = build_halo(g, (int32_t)G, lds_max - 256, (int32_t)block - 128);
+        const int32_t nwork = (int32_t)block - 128;  // worker threads: all but the two barrier waves
+        // the redundant tail pays for its gather polls only when few workgroups poll
+        // (measured: faster at 128 workgroups, slower at 256); tail_max > 0 forces it
+        const int32_t tail_auto = G <= 128 ? nwork : 0;
+        const int32_t tail_cap = t.tail_max < 0 ? 0 : (t.tail_max == 0 ? tail_auto : std::min(t.tail_max, nwork));
+        int rc = build_halo(g, (int32_t)G, lds_max - 256, tail_cap);
         if (rc) return rc;
         if (g->halo_lds_words >= 0) {
             int cap = 0;
@@ -270,7 +278,9 @@ int pick_launch(gdi_graph *g, Choice *ch)
             return GDI_OK;
         }
         if (t.scope == GDI_SCOPE_GRID)
-            return fail(GDI_ERANGE, "the spin windows of this graph do not fit one workgroup's LDS");
+            return fail(GDI_ERANGE, g->halo_lds_words == -3
+                                        ? "the grid scope packs weights into 11 bits: |w| must be <= 1023"
+                                        : "the spin windows of this graph do not fit one workgroup's LDS");
         ch->scope = GDI_SCOPE_GRID_FENCED;  // automatic choice falls back
     }
     int cap = 0;
@@ -367,10 +377,18 @@ int upload(gdi_graph *g, const int32_t *rp, const int32_t *col, const int32_t *w
 // over the 8 XCDs, so XCD x gets the contiguous chunk range [x*G/8, (x+1)*G/8).
 inline int32_t chunk_of_block(int32_t b, int32_t G) { return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b; }
 
+// Packed halo CSR entry: LDS bit index << 11 | the weight's low 11 bits.
+inline uint32_t pack_entry(int32_t lb, int32_t w) { return ((uint32_t)lb << 11) | ((uint32_t)w & 0x7FFu); }
+
 // Halo layout with the tail starting at class T0 (T0 == C: none).
 int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
 {
     const int32_t C = g->C;
+    for (const int2 &e : g->h_adj)
+        if (e.y < -GDI_HALO_WMAX - 1 || e.y > GDI_HALO_WMAX) {
+            g->halo_lds_words = -3;  // weights beyond the packed entries' range
+            return GDI_OK;
+        }
     std::vector<int32_t> chunk((size_t)C), blk_of_q((size_t)G);
     for (int32_t b = 0; b < G; ++b) blk_of_q[(size_t)chunk_of_block(b, G)] = b;
     for (int32_t c = 0; c < C; ++c) {
@@ -471,7 +489,7 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
         return (gather_off + (int32_t)(it - gat_words.begin())) * 32 + (j & 31);
     };
     std::vector<int32_t> tail_v, tail_beg((size_t)(C - T0) + 1, 0), tail_rp(1, 0);
-    std::vector<int2> tail_ent;
+    std::vector<uint32_t> tail_ent;
     for (int32_t c = T0; c < C; ++c) {
         for (int32_t v = g->cbeg[(size_t)c]; v < g->cbeg[(size_t)c] + g->csz[(size_t)c]; ++v) {
             tail_v.push_back(v);
@@ -479,13 +497,13 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
                 const int32_t j = g->h_adj[(size_t)k].x;
                 const int32_t lb = g->cls[(size_t)j] >= T0 ? tail_lb(j) : gather_lb(j);
                 if (lb < 0 || lb >= trp_off * 32) return fail(GDI_EDEVICE, "internal error: tail index out of range");
-                tail_ent.push_back(make_int2(lb, g->h_adj[(size_t)k].y));
+                tail_ent.push_back(pack_entry(lb, g->h_adj[(size_t)k].y));
             }
             tail_rp.push_back((int32_t)tail_ent.size());
         }
         tail_beg[(size_t)(c - T0) + 1] = (int32_t)tail_v.size();
     }
-    std::vector<int2> adjL(g->h_adj.size() + 1, make_int2(0, 0));  // last: the zero sentinel
+    std::vector<uint32_t> adjL(g->h_adj.size() + 1, 0u);  // last: the zero sentinel
     for (int32_t v = 0; v < g->n_pad; ++v) {
         const int32_t cv = g->cls[(size_t)v];
         if (cv < 0) continue;
@@ -505,7 +523,7 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
             // every index must land inside this workgroup's LDS image (checked here so
             // that a layout error surfaces as an error code, never as a device fault)
             if (lb < 0 || lb >= lds_words * 32) return fail(GDI_EDEVICE, "internal error: halo index out of range");
-            adjL[(size_t)k] = make_int2(lb, g->h_adj[(size_t)k].y);
+            adjL[(size_t)k] = pack_entry(lb, g->h_adj[(size_t)k].y);
         }
     }
     HIP_TRY(g->d_adjL.reserve(adjL.size()), "hipMalloc halo CSR");
@@ -514,7 +532,7 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
     HIP_TRY(g->d_member.reserve(8 * 64), "hipMalloc barrier");
     HIP_TRY(g->d_group.reserve(2 * 8 * GDI_HALO_GROUP_PAD), "hipMalloc barrier");
     if (!adjL.empty())
-        HIP_TRY(hipMemcpy(g->d_adjL.p, adjL.data(), adjL.size() * sizeof(int2), hipMemcpyHostToDevice), "upload halo CSR");
+        HIP_TRY(hipMemcpy(g->d_adjL.p, adjL.data(), adjL.size() * 4, hipMemcpyHostToDevice), "upload halo CSR");
     HIP_TRY(hipMemcpy(g->d_tab.p, tab.data(), tab.size() * sizeof(GdiHaloEntry), hipMemcpyHostToDevice), "upload halo table");
     HIP_TRY(g->d_tail_v.reserve(std::max<size_t>(tail_v.size(), 1)), "hipMalloc halo tail");
     HIP_TRY(g->d_tail_beg.reserve(tail_beg.size()), "hipMalloc halo tail");
@@ -524,7 +542,7 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
     HIP_TRY(g->d_tail_ent.reserve(std::max<size_t>(tail_ent.size(), 1)), "hipMalloc halo tail");
     HIP_TRY(hipMemcpy(g->d_tail_rp.p, tail_rp.data(), tail_rp.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
     if (!tail_ent.empty())
-        HIP_TRY(hipMemcpy(g->d_tail_ent.p, tail_ent.data(), tail_ent.size() * sizeof(int2), hipMemcpyHostToDevice),
+        HIP_TRY(hipMemcpy(g->d_tail_ent.p, tail_ent.data(), tail_ent.size() * 4, hipMemcpyHostToDevice),
                 "upload halo tail");
     if (!tail_v.empty())
         HIP_TRY(hipMemcpy(g->d_tail_v.p, tail_v.data(), tail_v.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
@@ -553,7 +571,9 @@ int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork)
     const int32_t C = g->C;
     int32_t T0 = C;
     int64_t tail_n = 0;
-    while (T0 > 1 && tail_n + g->csz[(size_t)T0 - 1] <= nwork) tail_n += g->csz[(size_t)--T0];
+    // at least two classes stay outside the tail: a gathered word of class c is then
+    // republished only after a grid barrier that follows every workgroup's poll of it
+    while (T0 > 2 && tail_n + g->csz[(size_t)T0 - 1] <= nwork) tail_n += g->csz[(size_t)--T0];
     for (;;) {
         int rc = build_halo_for(g, G, lds_budget, T0);
         if (rc) return rc;

@@ -68,6 +68,7 @@ struct GdiActiveRec {
 #define GDI_HALO_GROUP_PAD 16  // uint64 words between group words (128 bytes)
 #define GDI_HALO_PF 16         // CSR entries per node held in registers across a barrier
 #define GDI_HALO_THR_MAX 4096  // largest table width kept in LDS (two rows)
+#define GDI_HALO_WMAX 1023     // largest |weight| the packed entries of the halo sweep hold
 
 struct GdiHaloEntry {          // one per (workgroup, class)
     int32_t node_lo, node_hi;  // own nodes: new ids [node_lo, node_hi)
@@ -79,8 +80,9 @@ struct GdiHaloEntry {          // one per (workgroup, class)
 
 struct GdiHaloArgs {
     GdiSweepArgs base;
-    const int2 *adjL;          // CSR with columns rewritten as LDS bit indices of the owner,
-                               // plus one zero entry {0, 0} at index sentinel
+    // CSR with each entry packed into 32 bits: (LDS bit index in the owner's image << 11)
+    // | (weight & 0x7FF), weights in [-1024, 1023]; plus one zero entry at index sentinel
+    const uint32_t *adjL;
     int32_t sentinel;          // = nnz
     const GdiHaloEntry *tab;   // grid x C entries
     uint64_t *words;           // packed spins: (epoch << 32) | 32 spin bits (bit = 1 for +1)
@@ -102,11 +104,11 @@ struct GdiHaloArgs {
     const int32_t *gat_words;  // packed-word ids gathered for the tail, by source class
     const int32_t *gat_beg;    // T0 + 1 offsets into gat_words
     // the tail's CSR, copied into LDS at trp_off (tail_n + 1 row offsets) and tent_off
-    // (tail_nnz entries {LDS bit index, weight}); thread i of the tail owns tail_v[i]
+    // (tail_nnz packed entries); thread i of the tail owns tail_v[i]
     int32_t tail_nnz;
     int32_t trp_off, tent_off;
     const int32_t *tail_rp;
-    const int2 *tail_ent;
+    const uint32_t *tail_ent;
 };
 
 // Batched form: one instance (graph, replica) per queue entry.

@@ -705,8 +705,13 @@ struct RowAhead {
 struct NodePrefetch {
     int32_t r0, deg;
     uint32_t x0, x1;
-    int2 e[GDI_HALO_PF];
+    uint32_t e[GDI_HALO_PF];  // packed entries (see ent_lb / ent_w)
 };
+
+// Packed CSR entry of the halo sweep: LDS bit index in the upper 21 bits, the weight
+// as an 11-bit two's-complement number in the lower bits.
+__device__ __forceinline__ int32_t ent_lb(uint32_t e) { return (int32_t)(e >> 11); }
+__device__ __forceinline__ int32_t ent_w(uint32_t e) { return (int32_t)(e << 21) >> 21; }
 
 __device__ __forceinline__ void load_row(const GdiSweepArgs &a, int32_t v, RowAhead &ra)
 {
@@ -787,6 +792,48 @@ __device__ __forceinline__ bool poll_gather(const GdiHaloArgs &h, int32_t c, uin
             }
             if (tries >= h.base.spin_limit || aborted(abort_sh)) return false;
             __builtin_amdgcn_s_sleep(1);
+        }
+    }
+    return true;
+}
+
+// The polls after the phase of class c: the window of class c and, with a tail, the
+// gather words of class c. A thread's first window word and first gather word
+// (packed-word id gidx, loaded earlier, or -1) are loaded together, so their
+// latencies overlap; further words, if any, use the loops above.
+__device__ __forceinline__ bool poll_phase_words(const GdiHaloArgs &h, const GdiHaloEntry &e, int32_t c, int32_t gidx,
+                                                 uint32_t *bits, uint32_t epoch, int tid, int nwork, int32_t *abort_sh)
+{
+    const bool hw = tid < e.win_len, hg = gidx >= 0;
+    bool ok0 = !hw, ok1 = !hg;
+    for (int64_t tries = 0;; ++tries) {
+        const uint64_t w0 = ok0 ? 0 : ld_agent(h.words + e.win_lo + tid);
+        const uint64_t w1 = ok1 ? 0 : ld_agent(h.words + gidx);
+        if (!ok0 && (uint32_t)(w0 >> 32) >= epoch) {
+            bits[e.lds_off + tid] = (uint32_t)w0;
+            ok0 = true;
+        }
+        if (!ok1 && (uint32_t)(w1 >> 32) >= epoch) {
+            bits[h.gather_off + h.gat_beg[c] + tid] = (uint32_t)w1;
+            ok1 = true;
+        }
+        if (ok0 && ok1) break;
+        if (tries >= h.base.spin_limit || aborted(abort_sh)) return false;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    if (e.win_len > nwork && !poll_window(h, e, bits, epoch, tid + nwork, nwork, abort_sh)) return false;
+    if (hg && h.gat_beg[c + 1] - h.gat_beg[c] > nwork) {
+        for (int32_t i = h.gat_beg[c] + tid + nwork; i < h.gat_beg[c + 1]; i += nwork) {
+            const uint64_t *src = h.words + h.gat_words[i];
+            for (int64_t tries = 0;; ++tries) {
+                const uint64_t w = ld_agent(src);
+                if ((uint32_t)(w >> 32) >= epoch) {
+                    bits[h.gather_off + i] = (uint32_t)w;
+                    break;
+                }
+                if (tries >= h.base.spin_limit || aborted(abort_sh)) return false;
+                __builtin_amdgcn_s_sleep(1);
+            }
         }
     }
     return true;
@@ -882,7 +929,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     }
     // the tail's CSR (row offsets, then entries as LDS bit index and weight) stays in LDS
     int32_t *trp = reinterpret_cast<int32_t *>(bits + h.trp_off);
-    int2 *tent = reinterpret_cast<int2 *>(bits + h.tent_off);
+    uint32_t *tent = bits + h.tent_off;
     if (has_tail) {
         for (int32_t i = tid; i <= h.tail_n; i += nth) trp[i] = h.tail_rp[i];
         for (int32_t i = tid; i < h.tail_nnz; i += nth) tent[i] = h.tail_ent[i];
@@ -923,6 +970,10 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
             const uint32_t epoch = p + 2u;
             int32_t dM = 0;
             GDI_TSTAMP(0, tid == 0);
+            // this thread's first gather word of class c, loaded now so that the poll after
+            // the phase does not wait for it
+            int32_t gidx = -1;
+            if (worker && has_tail && h.gat_beg[c] + tid < h.gat_beg[c + 1]) gidx = h.gat_words[h.gat_beg[c] + tid];
             if (worker) {
                 const PhaseView pv = make_view(M, Psh[c], csz_sh[c], a.C, a.n);
                 // wave-uniform trip count so that ballots see whole waves of 64 nodes;
@@ -943,10 +994,10 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                         }
                         int32_t hv = 0;
 #pragma unroll
-                        for (int k = 0; k < GDI_HALO_PF; ++k) hv += q.e[k].y * lds_spin(bits, q.e[k].x);
+                        for (int k = 0; k < GDI_HALO_PF; ++k) hv += ent_w(q.e[k]) * lds_spin(bits, ent_lb(q.e[k]));
                         for (int32_t k = GDI_HALO_PF; k < q.deg; ++k) {
-                            const int2 en = h.adjL[q.r0 + k];
-                            hv += en.y * lds_spin(bits, en.x);
+                            const uint32_t en = h.adjL[q.r0 + k];
+                            hv += ent_w(en) * lds_spin(bits, ent_lb(en));
                         }
                         const int32_t lb = (e.lds_off + (v >> 5) - e.win_lo) * 32 + (v & 31);
                         const int32_t sigma = lds_spin(bits, lb);
@@ -999,8 +1050,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                 const int32_t v2 = step_node(h, tab, s2, tid);
                 if (t2 < a.S && v2 >= 0) load_row(a, v2, ra);
                 GDI_TSTAMP(6, tid == 0);
-                good = poll_window(h, e, bits, epoch, tid, nwork, abort_v);
-                if (good && has_tail) good = poll_gather(h, c, bits, epoch, tid, nwork, abort_v);
+                good = poll_phase_words(h, e, c, gidx, bits, epoch, tid, nwork, abort_v);
                 GDI_TSTAMP(7, tid == 0);
             } else if (wave == nwaves - 1) {
                 // this wave has no other memory traffic, so its store leaves at once
@@ -1044,7 +1094,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                     const int32_t v = my_tail;
                     const Words4 xw = philox10((uint32_t)my_id, t, a.replica, 0u, a.key0, a.key1);
                     int32_t hv = 0;
-                    for (int32_t k = trp[tid]; k < trp[tid + 1]; ++k) hv += tent[k].y * lds_spin(bits, tent[k].x);
+                    for (int32_t k = trp[tid]; k < trp[tid + 1]; ++k) hv += ent_w(tent[k]) * lds_spin(bits, ent_lb(tent[k]));
                     const int32_t lb = (h.tail_off + ((v - tail_base) >> 5)) * 32 + (v & 31);
                     const int32_t sigma = lds_spin(bits, lb);
                     if (decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, xw.w0, xw.w1)) {
@@ -1142,15 +1192,24 @@ __global__ void k_fill_u64(uint64_t *p, int64_t count)
 }
 
 // From-scratch M, doubled weighted cut, doubled crossing count and per-class +1 counts.
-__global__ void k_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad,
-                         const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P)
+// From-scratch M, doubled weighted cut, doubled crossing count and per-class +1
+// counts. Grid-stride over 64-id chunks: a chunk (one wave) never straddles a class
+// because class starts are 64-aligned, so each wave adds its +1 count to one class
+// counter; the three sums are reduced per workgroup in LDS, one atomic each.
+__global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad,
+                                                const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3,
+                                                int32_t *P)
 {
-    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ int64_t red[3][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t m = 0, cw = 0, ce = 0;
-    if (v < n_pad) {
-        const int32_t s = spin[v];
-        if (s != 0) {
-            m = s;
+    for (int32_t base = blockIdx.x * blockDim.x; base < n_pad; base += gridDim.x * blockDim.x) {
+        const int32_t v0 = base + (wave << 6);
+        const int32_t v = v0 + lane;
+        int32_t s = 0;
+        if (v < n_pad) {
+            s = spin[v];
+            m += s;
             for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
                 const int2 e = adj[k];
                 if (spin[e.x] != s) {
@@ -1158,23 +1217,30 @@ __global__ void k_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin,
                     ce += 1;
                 }
             }
-            if (s > 0) {
-                int32_t lo = 0, hi = C - 1;  // class of v: last c with cbeg[c] <= v
-                while (lo < hi) {
-                    const int32_t mid = (lo + hi + 1) >> 1;
-                    if (cbeg[mid] <= v) lo = mid; else hi = mid - 1;
-                }
-                if (v < cbeg[lo] + csz[lo]) atomicAdd(&P[lo], 1);
+        }
+        const int32_t plus = __popcll(__ballot(s > 0));
+        if (lane == 0 && plus && v0 < n_pad) {
+            int32_t lo = 0, hi = C - 1;  // class of the chunk: last c with cbeg[c] <= v0
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (cbeg[mid] <= v0) lo = mid; else hi = mid - 1;
             }
+            atomicAdd(&P[lo], plus);  // padding ids hold spin 0 and never count
         }
     }
     m = wave_sum_i64(m);
     cw = wave_sum_i64(cw);
     ce = wave_sum_i64(ce);
-    if ((threadIdx.x & 63) == 0) {
-        if (m) atomicAdd((unsigned long long *)&out3[0], (unsigned long long)m);
-        if (cw) atomicAdd((unsigned long long *)&out3[1], (unsigned long long)cw);
-        if (ce) atomicAdd((unsigned long long *)&out3[2], (unsigned long long)ce);
+    if (lane == 0) {
+        red[0][wave] = m;
+        red[1][wave] = cw;
+        red[2][wave] = ce;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        int64_t t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[threadIdx.x][w];
+        if (t) atomicAdd((unsigned long long *)&out3[threadIdx.x], (unsigned long long)t);
     }
 }
 
@@ -1255,8 +1321,9 @@ int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, in
                       const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P,
                       void *stream)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(n_pad, 256)), dim3(256), 0, (hipStream_t)stream, rp, adj,
-                       spin, n_pad, cbeg, csz, C, out3, P);
+    const unsigned grid = (unsigned)std::min<int64_t>(blocks_for(n_pad, 256), 2048);
+    hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, (hipStream_t)stream, rp, adj, spin, n_pad, cbeg, csz, C,
+                       out3, P);
     return status(hipGetLastError());
 }
 

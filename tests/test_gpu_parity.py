@@ -78,6 +78,9 @@ def test_small_graphs(gdi, oracle_lib, name, mode, scope):
     dict(scope=2, grid=64, block=512),
     dict(scope=2, grid=256, block=1024),
     dict(scope=2, grid=512, block=256),
+    dict(scope=2, grid=256, tail_max=-1),
+    dict(scope=2, grid=64, tail_max=100),
+    dict(scope=2, grid=16, block=512, tail_max=300),
     dict(scope=3, lanes_per_node=1, block=64, grid=1),
     dict(scope=3, lanes_per_node=2, block=128, grid=7),
     dict(scope=3, lanes_per_node=16, block=512, grid=64),
@@ -149,6 +152,26 @@ def test_degenerate_graphs(gdi, oracle_lib):
     for scope in (1, 2, 3):
         ref, r, _ = run_both(gdi, oracle_lib, g, T, tune=dict(scope=scope), label="star")
         assert_same(ref, r)
+
+
+def test_large_weights_take_the_fenced_grid_sweep(gdi, oracle_lib):
+    """The halo sweep packs weights into 11 bits; heavier graphs run the fenced grid sweep."""
+    g0 = gs.rgg_graph(70_000, 8.0, 22)
+    rows = np.repeat(np.arange(g0.n), np.diff(g0.row_ptr))
+    up = g0.col > rows
+    rng = np.random.default_rng(3)
+    w = rng.integers(-3000, 3001, int(up.sum()))
+    w[w == 0] = 1
+    g = gs.from_edges(g0.n, rows[up], g0.col[up], w)
+    T = gs.geometric_temps(4000.0, 50.0, 20)
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, label="heavy")
+    assert r["result"]["scope"] == gdi.SCOPE_GRID_FENCED
+    assert_same(ref, r)
+    with gdi.Annealer(g) as a:
+        a.tune(scope=2)
+        with pytest.raises(gdi.GdiError) as e:
+            a.anneal(T, 1)
+        assert e.value.code == gdi.ERANGE
 
 
 def test_single_sweep_and_empty_resume(gdi, oracle_lib):
