@@ -674,6 +674,22 @@ __device__ __forceinline__ int32_t lds_spin(const uint32_t *bits, int32_t lb)
     return (int32_t)((bits[lb >> 5] >> (lb & 31)) & 1u) * 2 - 1;
 }
 
+// Spin bits (1 = +1) of packed word wd, read from the int8 spin array: 32 spins, two
+// 16-byte loads; a byte is +1 when its low bit is set and its sign bit clear.
+__device__ __forceinline__ uint32_t pack_spins(const int8_t *spin, int32_t wd)
+{
+    const uint4 *p = reinterpret_cast<const uint4 *>(spin + (size_t)wd * 32);
+    const uint4 lo = p[0], hi = p[1];
+    const uint32_t x[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    uint32_t word = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t y = x[i] & ~(x[i] >> 7) & 0x01010101u;
+        word |= ((y | (y >> 7) | (y >> 14) | (y >> 21)) & 0xFu) << (4 * i);
+    }
+    return word;
+}
+
 // Polls the words of one window until they carry `epoch`, copying their bits to LDS.
 // Returns false when the bounded wait expires or another thread has aborted.
 __device__ __forceinline__ bool poll_window(const GdiHaloArgs &h, const GdiHaloEntry &e, uint32_t *bits,
@@ -905,21 +921,15 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     int32_t M = (int32_t)a.state[0];
     __syncthreads();
 
-    // prologue: publish own words of every class with epoch 1, fill the tail region
-    // from the spin array, then fill all windows and the gather region
+    // prologue: every window and gather word and the tail region straight from the spin
+    // array, which no workgroup writes before its epilogue, so no workgroup waits for
+    // another here (words published during the launch carry epochs >= 2)
     for (int32_t c = 0; c < T0; ++c) {
         const GdiHaloEntry e = tab[c];
-        const int32_t w_lo = e.node_lo >> 5, w_hi = (e.node_hi + 31) >> 5;
-        for (int32_t wd = w_lo + tid; wd < w_hi && e.node_lo < e.node_hi; wd += nth) {
-            uint32_t word = 0;
-            for (int k = 0; k < 32; ++k) {
-                const int32_t v = wd * 32 + k;
-                if (v >= e.node_lo && v < e.node_hi && a.spin[v] > 0) word |= 1u << k;
-            }
-            bits[e.lds_off + wd - e.win_lo] = word;
-            st_agent(h.words + wd, (1ull << 32) | word);
-        }
+        for (int32_t wd = tid; wd < e.win_len; wd += nth) bits[e.lds_off + wd] = pack_spins(a.spin, e.win_lo + wd);
     }
+    if (has_tail)
+        for (int32_t i = tid; i < h.gat_beg[T0]; i += nth) bits[h.gather_off + i] = pack_spins(a.spin, h.gat_words[i]);
     for (int32_t b0 = tail_base + wave * 64; b0 < a.n_pad; b0 += nwaves * 64) {
         const uint64_t m = __ballot(a.spin[b0 + lane] > 0);
         if (lane == 0) {
@@ -948,17 +958,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
         const int32_t v1 = step_node(h, tab, s1, tid);
         if (worker && t1 < a.S && v1 >= 0) load_row(a, v1, ra);
     }
-    bool ok = true;
-    if (worker) {
-        for (int32_t c = 0; c < T0 && ok; ++c) ok = poll_window(h, tab[c], bits, 1u, tid, nwork, abort_v);
-        for (int32_t c = 0; c < T0 && ok && has_tail; ++c) ok = poll_gather(h, c, bits, 1u, tid, nwork, abort_v);
-    }
-    if (!ok) set_abort(abort_v);
     __syncthreads();
-    if (abort_sh) {
-        if (tid == 0) __hip_atomic_store(&a.state[3], (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        return;
-    }
 
     int64_t dcut = 0, dcut_total = 0;
     uint32_t p = 0, kk = 0;
