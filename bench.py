@@ -101,12 +101,13 @@ def forms_batched(gdi, gs, torch, seed):
     return out
 
 
-def forms_learned(gdi, gs, torch, seed, k_full=8, p_skip=0.9, heuristic_k=8, replicas=8):
+def forms_learned(gdi, gs, torch, seed, k_full=8, replicas=8):
     """Learned frozen-node proposal on one GPU: collect traces from the plain annealer on
     the eight training RGGs, train the network with the library's kernels, then on the
     n=200k evaluation RGG run plain, network and heuristic anneals replica by replica and
     report the wall time each needs to reach a balanced cut within 0.5% of the best plain
-    cut over the same number of replicas."""
+    cut over the same number of replicas. The proposals apply from sweep learn_from on
+    (0: the whole schedule; S/2: the colder half)."""
     import numpy as np
 
     out = {}
@@ -135,25 +136,21 @@ def forms_learned(gdi, gs, torch, seed, k_full=8, p_skip=0.9, heuristic_k=8, rep
                        "constant_predictor_loss": float(-(ybar * np.log(ybar) + (1 - ybar) * np.log(1 - ybar)))}
     del dx, dy
     g, Te = gs.workload("rgg200k")
+    half = Te.size // 2
     runs = {}
     with gdi.Annealer(g) as a:
         a.anneal(Te[:10], seed)  # warm-up: threshold table, launch choice
-        methods = {
-            "plain": lambda r: a.anneal_learned(Te, seed, k_full, replica=r),
-            "network": lambda r: a.anneal_learned(Te, seed, k_full, replica=r, skip_mode=gdi.SKIP_MLP, weights=w,
-                                                  skip_threshold=p_skip),
-            "heuristic": lambda r: a.anneal_learned(Te, seed, k_full, replica=r, skip_mode=gdi.SKIP_HEURISTIC,
-                                                    heuristic_k=heuristic_k),
-        }
-        # the plain reference: gdi_anneal, one launch per anneal
-        plain_ms, Ms, cuts = [], [], []
-        for r in range(replicas):
-            t0 = time.perf_counter()
-            res = a.anneal(Te, seed, replica=r)
-            plain_ms.append((time.perf_counter() - t0) * 1e3)
-            Ms.append(res["M"])
-            cuts.append(res["cut"])
-        runs["plain_one_launch"] = (plain_ms, Ms, cuts, [0.0] * replicas)
+        methods = {"plain": lambda r: a.anneal(Te, seed, replica=r)}
+        for lf in (0, half):
+            for p_skip in (0.9, 0.97):
+                methods[f"network_p{p_skip}_from{lf}"] = (
+                    lambda r, lf=lf, p_skip=p_skip: a.anneal_learned(
+                        Te, seed, k_full, replica=r, skip_mode=gdi.SKIP_MLP, weights=w, skip_threshold=p_skip,
+                        learn_from=lf))
+            methods[f"heuristic_k{k_full}_from{lf}"] = (
+                lambda r, lf=lf: a.anneal_learned(Te, seed, k_full, replica=r, skip_mode=gdi.SKIP_HEURISTIC,
+                                                  heuristic_k=k_full, learn_from=lf))
+        methods[f"no_proposal_k{k_full}"] = lambda r: a.anneal_learned(Te, seed, k_full, replica=r)
         for name, fn in methods.items():
             ms, Ms, cuts, skip = [], [], [], []
             for r in range(replicas):
@@ -163,9 +160,9 @@ def forms_learned(gdi, gs, torch, seed, k_full=8, p_skip=0.9, heuristic_k=8, rep
                 Ms.append(res["M"])
                 cuts.append(res["cut"])
                 rr = res["result"]
-                skip.append(rr["node_skips"] / max(1, rr["node_skips"] + rr["node_visits"]))
+                skip.append(rr.get("node_skips", 0) / max(1, rr.get("node_skips", 0) + rr.get("node_visits", 1)))
             runs[name] = (ms, Ms, cuts, skip)
-    best_plain = best_state(runs["plain_one_launch"][1], runs["plain_one_launch"][2])
+    best_plain = best_state(runs["plain"][1], runs["plain"][2])
     target = best_plain * 1.005 if best_plain >= 0 else best_plain * 0.995
     for name, (ms, Ms, cuts, skip) in runs.items():
         reach = None
@@ -177,7 +174,7 @@ def forms_learned(gdi, gs, torch, seed, k_full=8, p_skip=0.9, heuristic_k=8, rep
                      "mean_cut": float(np.mean(cuts)), "balanced": int(sum(abs(m) <= 2 for m in Ms)),
                      "skipped_fraction": float(np.mean(skip)), "ms_to_within_0.5pct_of_plain_best": reach}
     out["eval"] = {"graph": g.name, "n": g.n, "sweeps": int(Te.size), "replicas": replicas, "k_full": k_full,
-                   "skip_threshold": p_skip, "heuristic_k": heuristic_k, "plain_best_cut": int(best_plain)}
+                   "plain_best_cut": int(best_plain), "target_cut": float(target)}
     return out
 
 

@@ -283,11 +283,14 @@ typedef struct {
     uint32_t skip_mode;        /* GDI_SKIP_* */
     float skip_threshold;      /* GDI_SKIP_MLP: probability threshold in (0, 1) */
     uint32_t heuristic_k;      /* GDI_SKIP_HEURISTIC */
-    uint8_t *mask_trace;       /* host or NULL: ceil((S - start_sweep) / k_full) x n bytes, original order:
+    uint8_t *mask_trace;       /* host or NULL: ceil((S - b0) / k_full) x n bytes with
+                                  b0 = max(start_sweep, learn_from), original order:
                                   1 = node skipped in the masked sweeps after that full sweep */
     int32_t active_max;        /* masked sweeps with at most this many active nodes run in one
                                   workgroup over the active nodes only (spins as LDS bits);
                                   0 = automatic, < 0 = never (the full-graph kernel skips nodes) */
+    uint32_t learn_from;       /* sweeps before this one run without a proposal, in one launch;
+                                  full sweeps then fall on max(start_sweep, learn_from) + m k_full */
 } gdi_learned_cfg;
 
 typedef struct {

@@ -197,9 +197,10 @@ def mlp_loss_grad(w, X, y, round_points: bool = True):
 # ---------------------------------------------------------------- the learned schedule
 def learned_anneal(g, temps, seed: int, k_full: int, proposal: str = "none", weights=None, p: float = 0.5,
                    heuristic_k: int = 1, A: int = 1, B: int = 1, replica: int = 0, mode: int = 0,
-                   start_sweep: int = 0, init=None, n_threads: int = 0) -> dict:
-    """The annealing schedule with a full sweep at start_sweep, start_sweep + k_full, ...
-    and the proposal's skip set applied to the sweeps in between.
+                   start_sweep: int = 0, init=None, n_threads: int = 0, learn_from: int = 0) -> dict:
+    """The annealing schedule: sweeps start_sweep .. b0-1 plain (b0 = max(start_sweep,
+    learn_from)), then a full sweep at b0, b0 + k_full, ... and the proposal's skip set
+    applied to the sweeps in between.
 
     Returns spins, M, cut, masks (one row per full sweep, original order; a full
     sweep with no masked sweeps after it has an all-zero row) and, for the network
@@ -211,14 +212,18 @@ def learned_anneal(g, temps, seed: int, k_full: int, proposal: str = "none", wei
     n = g.n
     lf = np.full(n, start_sweep - 1, dtype=np.int32)
     spins = None if init is None else np.asarray(init, dtype=np.int8)
-    rows = (S - start_sweep + k_full - 1) // k_full
+    b0 = min(S, max(start_sweep, learn_from))
+    rows = (S - b0 + k_full - 1) // k_full
     masks = np.zeros((rows, n), dtype=np.uint8)
     margins, logits = [], []
     kw = dict(A=A, B=B, replica=replica, mode=mode, n_threads=n_threads)
     M = None
     res = None
     thr = threshold_logit(p) if proposal == "network" else None
-    for row, b in enumerate(range(start_sweep, S, k_full)):
+    if b0 > start_sweep:
+        res = oracle_anneal(g, T[:b0], seed, start_sweep=start_sweep, init=spins, last_flip=lf, **kw)
+        spins = res["spins"]
+    for row, b in enumerate(range(b0, S, k_full)):
         res = oracle_anneal(g, T[:b + 1], seed, start_sweep=b, init=spins, last_flip=lf, **kw)
         spins, M = res["spins"], res["M"]
         if b + 1 >= S:

@@ -96,7 +96,8 @@ SKIP_NONE, SKIP_MLP, SKIP_HEURISTIC = 0, 1, 2
 
 class LearnedCfg(ctypes.Structure):
     _fields_ = [("k_full", ctypes.c_uint32), ("skip_mode", ctypes.c_uint32), ("skip_threshold", ctypes.c_float),
-                ("heuristic_k", ctypes.c_uint32), ("mask_trace", ctypes.c_void_p), ("active_max", ctypes.c_int32)]
+                ("heuristic_k", ctypes.c_uint32), ("mask_trace", ctypes.c_void_p), ("active_max", ctypes.c_int32),
+                ("learn_from", ctypes.c_uint32)]
 
 
 class LearnedResult(ctypes.Structure):
@@ -375,7 +376,7 @@ def mlp_init(seed: int) -> np.ndarray:
 def anneal_learned(h, n: int, temps, seed: int, k_full: int, skip_mode: int = SKIP_NONE, weights=None,
                    skip_threshold: float = 0.5, heuristic_k: int = 1, A: int = 1, B: int = 1, replica: int = 0,
                    mode: int = BAL_GATED, start_sweep: int = 0, init=None, mask_trace: bool = False,
-                   active_max: int = 0) -> dict:
+                   active_max: int = 0, learn_from: int = 0) -> dict:
     """gdi_anneal_learned: dict(spins, M, cut, result, [masks (blocks x n uint8)]).
 
     active_max: 0 = automatic, < 0 = never use the one-workgroup active-set sweep,
@@ -384,10 +385,11 @@ def anneal_learned(h, n: int, temps, seed: int, k_full: int, skip_mode: int = SK
     init_a = None if init is None else np.ascontiguousarray(init, dtype=np.int8)
     s, T = _schedule(T, A, B, replica, mode, start_sweep, init_a, None, None)
     w = None if weights is None else _weights(weights)
-    rows = (T.size - start_sweep + k_full - 1) // k_full if k_full > 0 else 0
+    b0 = min(T.size, max(start_sweep, learn_from))
+    rows = (T.size - b0 + k_full - 1) // k_full if k_full > 0 else 0
     masks = np.zeros((rows, n), dtype=np.uint8) if mask_trace else None
     cfg = LearnedCfg(k_full, skip_mode, skip_threshold, heuristic_k, None if masks is None else masks.ctypes.data,
-                     active_max)
+                     active_max, learn_from)
     out = np.zeros(n, dtype=np.int8)
     res = LearnedResult()
     _check(lib().gdi_anneal_learned(h, ctypes.byref(s), ctypes.c_uint64(seed), _ptr(w), ctypes.byref(cfg), _ptr(out),

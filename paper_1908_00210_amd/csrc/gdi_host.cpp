@@ -1224,10 +1224,12 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
         thr_logit = std::log(cfg->skip_threshold / (1.0f - cfg->skip_threshold));
     }
     std::vector<uint32_t> hmask;
+    const uint32_t b0 = std::min(S, std::max(t_start, cfg->learn_from));
     if (cfg->mask_trace)
-        std::memset(cfg->mask_trace, 0, (size_t)((S - t_start + k - 1) / k) * (size_t)g->n);
+        std::memset(cfg->mask_trace, 0, (size_t)((S - b0 + k - 1) / k) * (size_t)g->n);
     HIP_TRY(hipEventRecord(g->ev0, st), "hipEventRecord");
-    for (uint32_t b = t_start; b < S; b += k) {
+    if (b0 > t_start && (rc = launch_range(g, r, t_start, b0, nullptr, lf.p))) return rc;
+    for (uint32_t b = b0; b < S; b += k) {
         if ((rc = launch_range(g, r, b, b + 1, nullptr, lf.p))) return rc;
         if (b + 1 >= S) break;
         const uint32_t end = std::min<uint32_t>(b + k, S);
@@ -1249,7 +1251,7 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
             hmask.assign(words, 0u);
             if (mp) HIP_TRY(hipMemcpyAsync(hmask.data(), mask.p, words * 4, hipMemcpyDeviceToHost, st), "download mask");
             HIP_TRY(hipStreamSynchronize(st), "download mask");
-            uint8_t *row = cfg->mask_trace + (size_t)((b - t_start) / k) * (size_t)g->n;
+            uint8_t *row = cfg->mask_trace + (size_t)((b - b0) / k) * (size_t)g->n;
             for (int32_t v = 0; v < g->n_pad; ++v) {
                 const int32_t o = g->orig[(size_t)v];
                 if (o >= 0) row[o] = (uint8_t)((hmask[(size_t)v >> 5] >> (v & 31)) & 1u);

@@ -1045,7 +1045,9 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                 if (t1 < a.S) {
                     if (c + 1 == T0 && thr_lds && t + 1u < a.S)
                         for (int i = tid; i < K1; i += nwork) thr_sh[((t + 1u) & 1u) * K1 + i] = a.thr[(size_t)(t + 1u) * K1 + i];
-                    if (step_node(h, tab, s1, tid) >= 0) load_entries(h, ra, t1, pf);
+                    // nodes the proposal skips need no entries
+                    const int32_t v1 = step_node(h, tab, s1, tid);
+                    if (v1 >= 0 && !(a.mask && ((a.mask[v1 >> 5] >> (v1 & 31)) & 1u))) load_entries(h, ra, t1, pf);
                 }
                 const int32_t v2 = step_node(h, tab, s2, tid);
                 if (t2 < a.S && v2 >= 0) load_row(a, v2, ra);

@@ -156,6 +156,9 @@ def test_degenerate_proposals_reduce_to_the_plain_schedule():
                dict(k_full=6, proposal="heuristic", heuristic_k=1000)):
         r = L.learned_anneal(g, T, 12, **kw)
         assert np.array_equal(r["spins"], plain["spins"]) and r["cut"] == plain["cut"], kw
+    # a proposal that starts only after the last sweep never skips anything
+    r = L.learned_anneal(g, T, 12, k_full=3, proposal="heuristic", heuristic_k=1, learn_from=T.size)
+    assert np.array_equal(r["spins"], plain["spins"]) and r["masks"].shape == (0, g.n)
     # the same with a resumed start
     head = oracle.anneal(g, T[:10], 12)
     r = L.learned_anneal(g, T, 12, k_full=4, proposal="none", start_sweep=10, init=head["spins"])
