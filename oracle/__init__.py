@@ -25,6 +25,8 @@ SOURCE = os.path.join(_HERE, "gdi_oracle.c")
 
 MODE_GATED = 0
 MODE_SNAPSHOT = 1
+RULE_METROPOLIS = 0
+RULE_PAPER = 1
 
 
 def build(verbose: bool = False) -> str:
@@ -46,7 +48,7 @@ class _Params(ctypes.Structure):
         ("start_sweep", ctypes.c_int32),
         ("replica", ctypes.c_uint32),
         ("n_threads", ctypes.c_int32),
-        ("pad", ctypes.c_int32),
+        ("rule", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
     ]
 
@@ -142,17 +144,19 @@ def flip_delta(g, spins, A: int, B: int, i: int) -> int:
 
 def anneal(g, temps, seed: int, A: int = 1, B: int = 1, replica: int = 0, mode: int = MODE_GATED,
            start_sweep: int = 0, init=None, n_threads: int = 0, trace: bool = False,
-           phase_trace: bool = False, phase_spins: bool = False, skip=None, last_flip=None) -> dict:
+           phase_trace: bool = False, phase_spins: bool = False, skip=None, last_flip=None,
+           rule: int = RULE_METROPOLIS) -> dict:
     """Runs the oracle schedule; returns a dict with spins, M, cut, C, flips and optional traces.
 
     skip (n bools): nodes that make no decision in these sweeps; last_flip (int32
-    array of n, updated in place): sweep of each node's last flip.
+    array of n, updated in place): sweep of each node's last flip. With
+    rule=RULE_PAPER, temps holds the flip probabilities P_f(t) of the paper's rule.
     """
     T = np.ascontiguousarray(temps, dtype=np.float64)
     S = T.size
     rp, col, w = _i32(g.row_ptr), _i32(g.col), _i32(g.w)
     prm = _Params(A=A, B=B, mode=mode, n_sweeps=S, start_sweep=start_sweep, replica=replica,
-                  n_threads=n_threads, pad=0, seed=seed)
+                  n_threads=n_threads, rule=rule, seed=seed)
     spins = np.zeros(g.n, dtype=np.int8)
     init_a = None if init is None else np.ascontiguousarray(init, dtype=np.int8)
     tm = np.zeros(S, dtype=np.int64) if trace else None

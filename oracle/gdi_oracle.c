@@ -51,6 +51,12 @@
 
 #define OR_MODE_GATED 0
 #define OR_MODE_SNAPSHOT 1
+/* Acceptance rules. Metropolis: flip iff dE <= 0 or x0 < thr_t(dE). The paper's
+ * rule (Sec. V, Alg. 2 and 3): the spin takes the value minimising its local energy
+ * (flip iff dE < 0) and is then flipped with probability P_f(t), drawn as
+ * x0 < min(2^32 - 1, floor(2^32 P_f(t))); the two flips compose. */
+#define OR_RULE_METROPOLIS 0
+#define OR_RULE_PAPER 1
 
 /* ---------------------------------------------------------------- Philox4x32-10
  * Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy as 1, 2, 3"
@@ -184,7 +190,7 @@ typedef struct {
     int32_t start_sweep;   /* first sweep to run (resume) */
     uint32_t replica;
     int32_t n_threads;     /* OpenMP threads for the decision loop (<= 0: runtime default) */
-    int32_t pad;
+    int32_t rule;          /* OR_RULE_METROPOLIS, or OR_RULE_PAPER: T holds flip probabilities */
     uint64_t seed;
 } oracle_params;
 
@@ -210,8 +216,9 @@ int oracle_anneal(int32_t n, const int32_t *row_ptr, const int32_t *col, const i
 {
     if (n < 2 || p->n_sweeps < 1 || p->start_sweep < 0 || p->start_sweep > p->n_sweeps)
         return OR_EINVAL;
+    if (p->rule != OR_RULE_METROPOLIS && p->rule != OR_RULE_PAPER) return OR_EINVAL;
     for (int32_t t = 0; t < p->n_sweeps; ++t)
-        if (!(T[t] > 0.0)) return OR_EINVAL;
+        if (p->rule == OR_RULE_PAPER ? !(T[t] >= 0.0 && T[t] <= 1.0) : !(T[t] > 0.0)) return OR_EINVAL;
 
     const int64_t A = p->A, B = p->B;
     const uint32_t k0 = (uint32_t)p->seed, k1 = (uint32_t)(p->seed >> 32);
@@ -272,7 +279,10 @@ int oracle_anneal(int32_t n, const int32_t *row_ptr, const int32_t *col, const i
 
     for (int32_t t = p->start_sweep; t < p->n_sweeps; ++t) {
         int64_t width = 0;
-        for (int64_t d = 1; d <= de_max; ++d) {
+        /* the paper's rule draws one flip probability per sweep */
+        const double pf_scaled = floor(ldexp(p->rule == OR_RULE_PAPER ? T[t] : 0.0, 32));
+        const uint32_t pf_thr = pf_scaled >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)pf_scaled;
+        for (int64_t d = 1; d <= de_max && p->rule == OR_RULE_METROPOLIS; ++d) {
             uint32_t v = oracle_threshold(d, T[t]);
             if (v == 0) break;
             if (d > thr_cap) {
@@ -314,7 +324,8 @@ int oracle_anneal(int32_t n, const int32_t *row_ptr, const int32_t *col, const i
                 }
                 const int64_t dE = B * si * h + 4 * A * (1 - si * Mi);
                 int accept;
-                if (dE <= 0) accept = 1;
+                if (p->rule == OR_RULE_PAPER) accept = (dE < 0) != (x[0] < pf_thr);
+                else if (dE <= 0) accept = 1;
                 else if (dE > width) accept = 0;
                 else accept = x[0] < thr[dE];
                 flip[q] = (uint8_t)accept;

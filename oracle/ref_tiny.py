@@ -51,12 +51,19 @@ def colouring(n, adj):
     return colour
 
 
+def flip_threshold(pf: float) -> int:
+    """min(2^32 - 1, floor(2^32 P_f)) for the paper's random flips."""
+    return min(math.floor(math.ldexp(pf, 32)), MASK)
+
+
 def anneal(n, edges, temps, seed, A=1, B=1, replica=0, gated=True, init=None, start_sweep=0,
-           visit_seed=None, skip=(), last_flip=None):
+           visit_seed=None, skip=(), last_flip=None, paper_rule=False):
     """edges: list of (i, j, w) with i != j, each undirected edge once. Returns (spins, M, cut).
 
     Nodes in ``skip`` make no decision (their spins stay, they still count in the
-    magnetisation); ``last_flip`` (a list of n ints) receives each flip's sweep.
+    magnetisation); ``last_flip`` (a list of n ints) receives each flip's sweep. With
+    ``paper_rule`` temps are flip probabilities: a spin takes its energy-minimising
+    value (flips iff dE < 0) and then flips again when x0 < floor(2^32 P_f).
     """
     skip = set(skip)
     adj = [[] for _ in range(n)]
@@ -93,7 +100,10 @@ def anneal(n, edges, temps, seed, A=1, B=1, replica=0, gated=True, init=None, st
                 else:
                     seen = M0
                 dE = B * s[i] * h + 4 * A * (1 - s[i] * seen)
-                if dE <= 0 or x[0] < threshold(dE, T):
+                if paper_rule:
+                    if (dE < 0) != (x[0] < flip_threshold(T)):
+                        flips.append(i)
+                elif dE <= 0 or x[0] < threshold(dE, T):
                     flips.append(i)
             for i in flips:
                 s[i] = -s[i]
