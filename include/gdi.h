@@ -76,11 +76,19 @@ extern "C" {
 
 typedef struct gdi_graph gdi_graph;
 
-/* Annealing schedule (Alg. 3 outer loop, with Metropolis temperatures). */
+/* Acceptance rules. Metropolis: flip iff dE <= 0 or x0 < floor(2^32 exp(-dE/T_t)).
+ * Paper (Sec. V, Alg. 2/3): the spin first takes the value that minimises its local
+ * energy (flip iff dE < 0), then flips with probability P_f(t): flip iff
+ * (dE < 0) != (x0 < min(2^32 - 1, floor(2^32 P_f(t)))). */
+#define GDI_ACCEPT_METROPOLIS 0u
+#define GDI_ACCEPT_PAPER 1u
+
+/* Annealing schedule (Alg. 3 outer loop). */
 typedef struct {
     uint32_t n_sweeps;        /* S >= 1: length of temps */
     uint32_t start_sweep;     /* first sweep to run (resume); 0 = fresh start */
-    const double *temps;      /* host, S temperatures T_t > 0 (FP64); read during the call */
+    const double *temps;      /* host, S values (FP64), read during the call: temperatures T_t > 0
+                                 (Metropolis) or flip probabilities P_f(t) in [0, 1] (paper rule) */
     int32_t A;                /* balance coefficient (eq. 5) */
     int32_t B;                /* cut coefficient (eq. 6) */
     uint32_t replica;         /* Philox counter word 2 */
@@ -88,6 +96,9 @@ typedef struct {
     const int8_t *init_spins; /* host, n spins (original order) to start from, or NULL for the Philox state */
     int64_t *trace_m;         /* host, S entries or NULL: M after each sweep t >= start_sweep */
     int64_t *trace_cut;       /* host, S entries or NULL: weighted cut after each sweep t >= start_sweep */
+    uint32_t acceptance;      /* GDI_ACCEPT_METROPOLIS or GDI_ACCEPT_PAPER (the learned schedule
+                                 and trace collection take Metropolis only) */
+    uint32_t reserved;        /* 0 */
 } gdi_schedule;
 
 /* Launch tuning; zero fields mean "choose automatically". */

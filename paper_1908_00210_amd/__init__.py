@@ -16,7 +16,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "GdiError", "lib", "LIB_PATH", "BAL_GATED", "BAL_SNAPSHOT", "SCOPE_AUTO", "SCOPE_WORKGROUP",
+    "GdiError", "lib", "LIB_PATH", "BAL_GATED", "BAL_SNAPSHOT", "ACCEPT_METROPOLIS", "ACCEPT_PAPER", "SCOPE_AUTO", "SCOPE_WORKGROUP",
     "SCOPE_GRID", "SCOPE_GRID_FENCED", "Schedule", "Tuning", "Result", "GraphInfo", "create", "destroy", "anneal",
     "anneal_dev", "cut", "cut_dev", "last_result", "set_stream", "set_tuning", "get_info",
     "get_colouring", "colour_csr", "threshold_table", "philox4x32_10", "version", "Annealer",
@@ -31,6 +31,7 @@ OK, EINVAL, ERANGE, ENOMEM, EDEVICE, ESTATE, ETIMEOUT = 0, -1, -2, -3, -4, -5, -
 _NAMES = {EINVAL: "GDI_EINVAL", ERANGE: "GDI_ERANGE", ENOMEM: "GDI_ENOMEM", EDEVICE: "GDI_EDEVICE",
           ESTATE: "GDI_ESTATE", ETIMEOUT: "GDI_ETIMEOUT"}
 BAL_GATED, BAL_SNAPSHOT = 0, 1
+ACCEPT_METROPOLIS, ACCEPT_PAPER = 0, 1
 SCOPE_AUTO, SCOPE_WORKGROUP, SCOPE_GRID, SCOPE_GRID_FENCED = 0, 1, 2, 3
 
 
@@ -52,6 +53,8 @@ class Schedule(ctypes.Structure):
         ("init_spins", ctypes.c_void_p),
         ("trace_m", ctypes.c_void_p),
         ("trace_cut", ctypes.c_void_p),
+        ("acceptance", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -210,24 +213,27 @@ def set_tuning(h, scope: int = 0, block: int = 0, grid: int = 0, lanes_per_node:
     _check(lib().gdi_set_tuning(h, ctypes.byref(t)))
 
 
-def _schedule(temps, A, B, replica, mode, start_sweep, init, trace_m, trace_cut):
+def _schedule(temps, A, B, replica, mode, start_sweep, init, trace_m, trace_cut, acceptance=ACCEPT_METROPOLIS):
     T = np.ascontiguousarray(temps, dtype=np.float64)
     s = Schedule(n_sweeps=T.size, start_sweep=start_sweep, temps=T.ctypes.data, A=A, B=B,
                  replica=replica, balance_mode=mode,
                  init_spins=None if init is None else init.ctypes.data,
                  trace_m=None if trace_m is None else trace_m.ctypes.data,
-                 trace_cut=None if trace_cut is None else trace_cut.ctypes.data)
+                 trace_cut=None if trace_cut is None else trace_cut.ctypes.data,
+                 acceptance=acceptance, reserved=0)
     return s, T
 
 
 def anneal(h, n: int, temps, seed: int, A: int = 1, B: int = 1, replica: int = 0, mode: int = BAL_GATED,
-           start_sweep: int = 0, init=None, trace: bool = False) -> dict:
-    """gdi_anneal: returns dict(spins (original order), M, cut, result, [trace_m, trace_cut])."""
+           start_sweep: int = 0, init=None, trace: bool = False, acceptance: int = ACCEPT_METROPOLIS) -> dict:
+    """gdi_anneal: returns dict(spins (original order), M, cut, result, [trace_m, trace_cut]).
+
+    temps: temperatures (Metropolis) or flip probabilities P_f(t) (acceptance=ACCEPT_PAPER)."""
     T = np.ascontiguousarray(temps, dtype=np.float64)
     init_a = None if init is None else np.ascontiguousarray(init, dtype=np.int8)
     tm = np.zeros(T.size, dtype=np.int64) if trace else None
     tc = np.zeros(T.size, dtype=np.int64) if trace else None
-    s, T = _schedule(T, A, B, replica, mode, start_sweep, init_a, tm, tc)
+    s, T = _schedule(T, A, B, replica, mode, start_sweep, init_a, tm, tc, acceptance)
     out = np.zeros(n, dtype=np.int8)
     _check(lib().gdi_anneal(h, ctypes.byref(s), ctypes.c_uint64(seed), _ptr(out)))
     r = last_result(h)
@@ -238,10 +244,10 @@ def anneal(h, n: int, temps, seed: int, A: int = 1, B: int = 1, replica: int = 0
 
 
 def anneal_dev(h, temps, seed: int, d_spins_out: int, A: int = 1, B: int = 1, replica: int = 0,
-               mode: int = BAL_GATED, start_sweep: int = 0, init=None):
+               mode: int = BAL_GATED, start_sweep: int = 0, init=None, acceptance: int = ACCEPT_METROPOLIS):
     """gdi_anneal_dev: enqueues the anneal on the handle's stream; d_spins_out is a device pointer."""
     init_a = None if init is None else np.ascontiguousarray(init, dtype=np.int8)
-    s, T = _schedule(temps, A, B, replica, mode, start_sweep, init_a, None, None)
+    s, T = _schedule(temps, A, B, replica, mode, start_sweep, init_a, None, None, acceptance)
     _check(lib().gdi_anneal_dev(h, ctypes.byref(s), ctypes.c_uint64(seed), ctypes.c_void_p(d_spins_out)))
 
 
@@ -302,7 +308,7 @@ def philox4x32_10(seed: int, ctr) -> np.ndarray:
 
 
 def anneal_batch(items, temps, seed: int, A: int = 1, B: int = 1, mode: int = BAL_GATED, tune: dict | None = None,
-                 outputs: bool = True, device_outputs=None) -> dict:
+                 outputs: bool = True, device_outputs=None, acceptance: int = ACCEPT_METROPOLIS) -> dict:
     """gdi_anneal_batch over items = [(handle, n, replica), ...].
 
     Returns dict(spins=[arrays or None], M=[...], cut=[...], kernel_ms). With
@@ -324,7 +330,7 @@ def anneal_batch(items, temps, seed: int, A: int = 1, B: int = 1, mode: int = BA
         else:
             outs.append(None)
             arr[i].spins_out = None
-    s, T = _schedule(temps, A, B, 0, mode, 0, None, None, None)
+    s, T = _schedule(temps, A, B, 0, mode, 0, None, None, None, acceptance)
     t = None if tune is None else ctypes.byref(Tuning(tune.get("scope", 0), tune.get("block", 0), tune.get("grid", 0),
                                                        tune.get("lanes_per_node", 0), 0, 0))
     ms = ctypes.c_double()

@@ -103,6 +103,7 @@ struct gdi_graph {
     std::vector<double> thr_key;      // temperatures of the cached table
     int32_t thr_K = -1;
     int64_t thr_demax = -1;
+    uint32_t thr_rule = 0;
 
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -587,8 +588,36 @@ int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork)
 
 // Metropolis threshold table for a schedule: rows t < S, entries d = 0..K where K is
 // the largest d <= de_max whose threshold is non-zero at some sweep.
-int build_table(const double *temps, uint32_t S, int64_t de_max, int32_t *K_out, std::vector<uint32_t> &tab)
+// Schedule values: temperatures > 0 (Metropolis) or flip probabilities in [0, 1] (paper rule).
+int check_schedule_values(const gdi_schedule *s)
 {
+    if (s->acceptance > GDI_ACCEPT_PAPER) return fail(GDI_EINVAL, "unknown acceptance rule");
+    for (uint32_t t = 0; t < s->n_sweeps; ++t) {
+        const double v = s->temps[t];
+        if (s->acceptance == GDI_ACCEPT_PAPER ? !(v >= 0.0 && v <= 1.0) : !(v > 0.0))
+            return fail(GDI_EINVAL, s->acceptance == GDI_ACCEPT_PAPER ? "flip probabilities must lie in [0, 1]"
+                                                                     : "temperatures must be > 0");
+    }
+    return GDI_OK;
+}
+
+// Paper rule: one entry per sweep, min(2^32 - 1, floor(2^32 P_f)) (exact: P_f in [0, 1]
+// scaled by a power of two, then truncated).
+uint32_t flip_threshold_of(double pf)
+{
+    const double v = std::floor(std::ldexp(pf, 32));
+    return v >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)v;
+}
+
+int build_table(const double *temps, uint32_t S, int64_t de_max, int32_t *K_out, std::vector<uint32_t> &tab,
+                uint32_t rule)
+{
+    if (rule == GDI_ACCEPT_PAPER) {
+        tab.assign(S, 0u);
+        for (uint32_t t = 0; t < S; ++t) tab[t] = flip_threshold_of(temps[t]);
+        *K_out = 0;
+        return GDI_OK;
+    }
     int64_t K = 0;
     for (uint32_t t = 0; t < S; ++t) {
         const double T = temps[t];
@@ -617,12 +646,12 @@ int build_table(const double *temps, uint32_t S, int64_t de_max, int32_t *K_out,
 int ensure_table(gdi_graph *g, const gdi_schedule *s, int64_t de_max)
 {
     const uint32_t S = s->n_sweeps;
-    if (g->thr_K >= 0 && g->thr_demax == de_max && g->thr_key.size() == S &&
+    if (g->thr_K >= 0 && g->thr_demax == de_max && g->thr_rule == s->acceptance && g->thr_key.size() == S &&
         std::memcmp(g->thr_key.data(), s->temps, S * sizeof(double)) == 0)
         return GDI_OK;
     std::vector<uint32_t> tab;
     int32_t K = 0;
-    int rc = build_table(s->temps, S, de_max, &K, tab);
+    int rc = build_table(s->temps, S, de_max, &K, tab, s->acceptance);
     if (rc) return rc;
     HIP_TRY(g->d_thr.reserve(tab.size()), "hipMalloc thresholds");
     HIP_TRY(hipMemcpyAsync(g->d_thr.p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, g->stream),
@@ -631,6 +660,7 @@ int ensure_table(gdi_graph *g, const gdi_schedule *s, int64_t de_max)
     g->thr_key.assign(s->temps, s->temps + S);
     g->thr_K = K;
     g->thr_demax = de_max;
+    g->thr_rule = s->acceptance;
     return GDI_OK;
 }
 
@@ -677,8 +707,7 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
     if (S < 1) return fail(GDI_EINVAL, "n_sweeps must be >= 1");
     if (!s->temps) return fail(GDI_EINVAL, "NULL temps");
     if (s->start_sweep > S) return fail(GDI_EINVAL, "start_sweep > n_sweeps");
-    for (uint32_t t = 0; t < S; ++t)
-        if (!(s->temps[t] > 0.0)) return fail(GDI_EINVAL, "temperatures must be > 0");
+    if (int rc0 = check_schedule_values(s)) return rc0;
     if (s->balance_mode > GDI_BAL_SNAPSHOT) return fail(GDI_EINVAL, "unknown balance_mode");
     if (dev_out && (s->trace_m || s->trace_cut)) return fail(GDI_EINVAL, "traces need the host variant");
     const int64_t de_max = std::llabs((long long)s->B) * g->max_abs_wdeg + 4 * std::llabs((long long)s->A) * ((int64_t)g->n + 1);
@@ -746,6 +775,7 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
     a.key1 = (uint32_t)(seed >> 32);
     a.replica = s->replica;
     a.snapshot = s->balance_mode == GDI_BAL_SNAPSHOT ? 1u : 0u;
+    a.rule = s->acceptance;
     a.spin_limit = (g->have_tune && g->tune.spin_limit) ? (int64_t)g->tune.spin_limit : kSpinLimit;
     r.thr_in_lds = 0;
     if (r.ch.scope == GDI_SCOPE_GRID) {
@@ -923,8 +953,7 @@ int check_batch(const gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s
     if (s->start_sweep != 0 || s->init_spins || s->trace_m || s->trace_cut)
         return fail(GDI_EINVAL, "batched anneals start fresh and take no traces");
     if (s->balance_mode > GDI_BAL_SNAPSHOT) return fail(GDI_EINVAL, "unknown balance_mode");
-    for (uint32_t t = 0; t < s->n_sweeps; ++t)
-        if (!(s->temps[t] > 0.0)) return fail(GDI_EINVAL, "temperatures must be > 0");
+    if (int rc0 = check_schedule_values(s)) return rc0;
     for (uint32_t i = 0; i < n_inst; ++i)
         if (!inst[i].graph) return fail(GDI_EINVAL, "NULL graph in batch");
     return GDI_OK;
@@ -966,7 +995,7 @@ int run_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64
 
     std::vector<uint32_t> tab;
     int32_t K = 0;
-    if ((rc = build_table(s->temps, S, de_max, &K, tab))) return rc;
+    if ((rc = build_table(s->temps, S, de_max, &K, tab, s->acceptance))) return rc;
 
     // longest instances first
     std::vector<uint32_t> order(n_inst);
@@ -1034,6 +1063,7 @@ int run_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64
     ba.key0 = (uint32_t)seed;
     ba.key1 = (uint32_t)(seed >> 32);
     ba.snapshot = s->balance_mode == GDI_BAL_SNAPSHOT ? 1u : 0u;
+    ba.rule = s->acceptance;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&e1), "hipEventCreate");
@@ -1184,6 +1214,8 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
         return fail(GDI_EINVAL, "the network proposal needs weights and a threshold in (0, 1)");
     if (cfg->skip_mode == GDI_SKIP_HEURISTIC && cfg->heuristic_k < 1) return fail(GDI_EINVAL, "heuristic_k must be >= 1");
     if (s && (s->trace_m || s->trace_cut)) return fail(GDI_EINVAL, "the learned anneal takes no traces");
+    if (s && s->acceptance != GDI_ACCEPT_METROPOLIS)
+        return fail(GDI_EINVAL, "the learned anneal takes temperatures (Metropolis acceptance)");
     RunCtx r;
     int rc = prepare_run(g, s, seed, false, r);
     if (rc) return rc;
@@ -1296,6 +1328,8 @@ int traces_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, uint32_t eve
     if (!d_x || !d_y || !n_snapshots) return fail(GDI_EINVAL, "NULL argument");
     if (k_label < 1 || every <= k_label) return fail(GDI_EINVAL, "need every > k_label >= 1");
     if (s && (s->trace_m || s->trace_cut)) return fail(GDI_EINVAL, "no traces here");
+    if (s && s->acceptance != GDI_ACCEPT_METROPOLIS)
+        return fail(GDI_EINVAL, "trace features take temperatures (Metropolis acceptance)");
     RunCtx r;
     int rc = prepare_run(g, s, seed, false, r);
     if (rc) return rc;

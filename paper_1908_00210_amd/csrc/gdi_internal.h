@@ -43,6 +43,7 @@ struct GdiSweepArgs {
     uint32_t key0, key1;       // Philox key
     uint32_t replica;
     uint32_t snapshot;         // 1 = SNAPSHOT balance mode
+    uint32_t rule;             // 0 = Metropolis, 1 = the paper's argmin + random flip (row entry 0 = P_f threshold)
     int64_t spin_limit;        // bounded waits: polls before giving up
     const uint32_t *mask;      // n_pad/32 words, bit set = node skipped in this launch, or null
     int32_t *last_flip;        // n_pad entries: sweep of each node's last flip, or null
@@ -134,6 +135,7 @@ struct GdiBatchArgs {
     int32_t A4, B;
     uint32_t key0, key1;
     uint32_t snapshot;
+    uint32_t rule;                 // acceptance rule, as in GdiSweepArgs
 };
 
 // Learned proposal: BF16 network parameters on the device (transposed weights).

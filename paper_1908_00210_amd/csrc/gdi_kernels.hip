@@ -125,6 +125,10 @@ __device__ __forceinline__ bool decide_id(const GdiSweepArgs &a, uint32_t o, uin
         m_seen = gated ? pv.M0 : 0;
     }
     const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
+    if (a.rule) {  // the paper's rule: the argmin value, then a random flip with probability P_f
+        if (!have) x0 = philox10(o, t, a.replica, 0u, a.key0, a.key1).w0;
+        return (dE < 0) != (x0 < thr_row[0]);
+    }
     if (dE <= 0) return true;
     if (dE > a.K) return false;
     if (!have) x0 = philox10(o, t, a.replica, 0u, a.key0, a.key1).w0;
@@ -438,6 +442,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_batch(GdiBatchArgs ba)
         a.key1 = ba.key1;
         a.replica = in.replica;
         a.snapshot = ba.snapshot;
+        a.rule = ba.rule;
 
         int32_t *Psh = dyn;
         const int c_round = (in.C + 3) & ~3;
@@ -772,6 +777,7 @@ __device__ __forceinline__ bool decide_words(const GdiSweepArgs &a, int32_t sigm
         m_seen = gated ? pv.M0 : 0;
     }
     const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
+    if (a.rule) return (dE < 0) != (x0 < (in_lds ? thr_l[0] : thr_g[0]));
     if (dE <= 0) return true;
     if (dE > a.K) return false;
     return x0 < (in_lds ? thr_l[dE] : thr_g[dE]);

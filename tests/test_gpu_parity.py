@@ -27,16 +27,16 @@ def gdi():
 
 
 def run_both(gdi, oracle_lib, g, T, seed=1, mode=0, tune=None, trace=True, replica=0, A=1, B=1,
-             start_sweep=0, init=None, label=""):
-    print(f"[case] {label} n={g.n} nnz={g.nnz} S={T.size} mode={mode} tune={tune} seed={seed}",
+             start_sweep=0, init=None, label="", rule=0):
+    print(f"[case] {label} n={g.n} nnz={g.nnz} S={T.size} mode={mode} tune={tune} seed={seed} rule={rule}",
           flush=True)
     ref = oracle_lib.anneal(g, T, seed, A=A, B=B, mode=mode, trace=trace, replica=replica,
-                            start_sweep=start_sweep, init=init)
+                            start_sweep=start_sweep, init=init, rule=rule)
     with gdi.Annealer(g) as a:
         if tune:
             a.tune(**tune)
         r = a.anneal(T, seed, mode=mode, trace=trace, replica=replica, A=A, B=B,
-                     start_sweep=start_sweep, init=init)
+                     start_sweep=start_sweep, init=init, acceptance=rule)
         cw, ce, m = a.cut(r["spins"])
     return ref, r, (cw, ce, m)
 
@@ -152,6 +152,53 @@ def test_degenerate_graphs(gdi, oracle_lib):
     for scope in (1, 2, 3):
         ref, r, _ = run_both(gdi, oracle_lib, g, T, tune=dict(scope=scope), label="star")
         assert_same(ref, r)
+
+
+PAPER_PF = gs.geometric_temps(0.2, 0.001, 60)
+
+
+@pytest.mark.parametrize("scope", [1, 2, 3])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_paper_rule(gdi, oracle_lib, scope, mode):
+    """The paper's acceptance rule: argmin value, then a random flip with probability P_f."""
+    g = gs.rgg_graph(9000, 8.0, 23, "pm1")
+    ref, r, _ = run_both(gdi, oracle_lib, g, PAPER_PF, seed=4, mode=mode, tune=dict(scope=scope), rule=1,
+                         label="paper-rule")
+    assert_same(ref, r)
+
+
+def test_paper_rule_on_the_1m_graph(gdi, oracle_lib):
+    g, _ = gs.workload("rgg1m")
+    pf = gs.geometric_temps(0.2, 0.001, 200)
+    ref, r, _ = run_both(gdi, oracle_lib, g, pf, rule=1, label="paper-rule-rgg1m")
+    assert r["result"]["scope"] == gdi.SCOPE_GRID
+    assert_same(ref, r)
+
+
+def test_paper_rule_batched(gdi, oracle_lib):
+    graphs = [gs.er_graph(900, 0.03, 24), gs.rgg_graph(3000, 12.0, 25, "pm1")]
+    anns = [gdi.Annealer(g) for g in graphs]
+    items = [(anns[0].h, graphs[0].n, 0), (anns[1].h, graphs[1].n, 0), (anns[1].h, graphs[1].n, 3)]
+    out = gdi.anneal_batch(items, PAPER_PF, 8, acceptance=1)
+    for i, (g, rep) in enumerate(((graphs[0], 0), (graphs[1], 0), (graphs[1], 3))):
+        ref = oracle_lib.anneal(g, PAPER_PF, 8, replica=rep, rule=1)
+        assert np.array_equal(out["spins"][i], ref["spins"]) and out["cut"][i] == ref["cut"]
+    for a in anns:
+        a.close()
+
+
+def test_paper_rule_rejects_bad_probabilities(gdi):
+    g = gs.er_graph(100, 0.05, 26)
+    with gdi.Annealer(g) as a:
+        for bad in (np.array([0.5, 1.5]), np.array([-0.1]), np.array([np.nan])):
+            with pytest.raises(gdi.GdiError) as e:
+                a.anneal(bad, 1, acceptance=1)
+            assert e.value.code == gdi.EINVAL
+        with pytest.raises(gdi.GdiError) as e:
+            a.anneal(np.ones(3), 1, acceptance=2)
+        assert e.value.code == gdi.EINVAL
+        r = a.anneal(np.full(3, 0.5), 1, acceptance=1)
+        assert r["spins"].shape == (g.n,)
 
 
 def test_large_weights_take_the_fenced_grid_sweep(gdi, oracle_lib):
