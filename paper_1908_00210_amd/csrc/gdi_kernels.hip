@@ -734,6 +734,20 @@ struct NodePrefetch {
 __device__ __forceinline__ int32_t ent_lb(uint32_t e) { return (int32_t)(e >> 11); }
 __device__ __forceinline__ int32_t ent_w(uint32_t e) { return (int32_t)(e << 21) >> 21; }
 
+// Local field over the first GDI_HALO_PF entries of a row (zero entries past its end):
+// every LDS word is read before any is used, so the reads overlap instead of each
+// waiting for the previous one.
+__device__ __forceinline__ int32_t field_sum(const uint32_t *bits, const uint32_t (&e)[GDI_HALO_PF])
+{
+    uint32_t wv[GDI_HALO_PF];
+#pragma unroll
+    for (int k = 0; k < GDI_HALO_PF; ++k) wv[k] = bits[ent_lb(e[k]) >> 5];
+    int32_t h = 0;
+#pragma unroll
+    for (int k = 0; k < GDI_HALO_PF; ++k) h += ent_w(e[k]) * ((int32_t)((wv[k] >> (ent_lb(e[k]) & 31)) & 1u) * 2 - 1);
+    return h;
+}
+
 __device__ __forceinline__ void load_row(const GdiSweepArgs &a, int32_t v, RowAhead &ra)
 {
     ra.r0 = a.rp[v];
@@ -998,9 +1012,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                         } else {
                             q = pf;
                         }
-                        int32_t hv = 0;
-#pragma unroll
-                        for (int k = 0; k < GDI_HALO_PF; ++k) hv += ent_w(q.e[k]) * lds_spin(bits, ent_lb(q.e[k]));
+                        int32_t hv = field_sum(bits, q.e);
                         for (int32_t k = GDI_HALO_PF; k < q.deg; ++k) {
                             const uint32_t en = h.adjL[q.r0 + k];
                             hv += ent_w(en) * lds_spin(bits, ent_lb(en));
