@@ -178,6 +178,27 @@ def forms_learned(gdi, gs, torch, seed, k_full=8, replicas=8):
     return out
 
 
+def forms_standard(gdi, gs, sweeps=50):
+    """GDI vs the standard solver of Alg. 2 (every decision sums all n spins for the
+    balance term) on 2-D tori of growing size: same results, time per sweep of each."""
+    import numpy as np
+
+    out = []
+    T = gs.geometric_temps(3.0, 0.05, sweeps)
+    for L in (32, 45, 64, 90, 128, 180):
+        g = gs.torus_graph(L, 400 + L, "pm1")
+        with gdi.Annealer(g) as a:
+            a.anneal(T[:5], 1)
+            r_gdi = a.anneal(T, 1)
+            a.anneal(T[:5], 1, flags=gdi.FLAG_DENSE_BALANCE)
+            r_std = a.anneal(T, 1, flags=gdi.FLAG_DENSE_BALANCE)
+        assert np.array_equal(r_gdi["spins"], r_std["spins"])
+        out.append({"n": g.n, "sweeps": sweeps, "gdi_ms": r_gdi["result"]["sweep_ms"],
+                    "std_ms": r_std["result"]["sweep_ms"],
+                    "std_over_gdi": r_std["result"]["sweep_ms"] / r_gdi["result"]["sweep_ms"]})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -295,6 +316,7 @@ def main():
     if not args.no_forms:
         line["forms"] = forms_batched(gdi, gs, torch, seed)
         line["forms"]["learned_rgg200k"] = forms_learned(gdi, gs, torch, seed)
+        line["forms"]["gdi_vs_standard_torus"] = forms_standard(gdi, gs)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, temps, seed, min(args.cpu_sweeps, S))
     print(json.dumps(line), flush=True)

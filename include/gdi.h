@@ -98,8 +98,14 @@ typedef struct {
     int64_t *trace_cut;       /* host, S entries or NULL: weighted cut after each sweep t >= start_sweep */
     uint32_t acceptance;      /* GDI_ACCEPT_METROPOLIS or GDI_ACCEPT_PAPER (the learned schedule
                                  and trace collection take Metropolis only) */
-    uint32_t reserved;        /* 0 */
+    uint32_t flags;           /* GDI_FLAG_*; 0 for the batched and learned forms */
 } gdi_schedule;
+
+/* The standard solver of Alg. 2: every decision computes the balance term from the
+ * whole spin vector (all n spins, plus its class's over-side count) instead of the
+ * tracked magnetisation -- identical results, n reads per decision. Graphs that fit
+ * one workgroup (n_pad <= 65536) only; GDI_ERANGE otherwise. */
+#define GDI_FLAG_DENSE_BALANCE 1u
 
 /* Launch tuning; zero fields mean "choose automatically". */
 typedef struct {

@@ -16,7 +16,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "GdiError", "lib", "LIB_PATH", "BAL_GATED", "BAL_SNAPSHOT", "ACCEPT_METROPOLIS", "ACCEPT_PAPER", "SCOPE_AUTO", "SCOPE_WORKGROUP",
+    "GdiError", "lib", "LIB_PATH", "BAL_GATED", "BAL_SNAPSHOT", "ACCEPT_METROPOLIS", "ACCEPT_PAPER", "FLAG_DENSE_BALANCE", "SCOPE_AUTO", "SCOPE_WORKGROUP",
     "SCOPE_GRID", "SCOPE_GRID_FENCED", "Schedule", "Tuning", "Result", "GraphInfo", "create", "destroy", "anneal",
     "anneal_dev", "cut", "cut_dev", "last_result", "set_stream", "set_tuning", "get_info",
     "get_colouring", "colour_csr", "threshold_table", "philox4x32_10", "version", "Annealer",
@@ -32,6 +32,7 @@ _NAMES = {EINVAL: "GDI_EINVAL", ERANGE: "GDI_ERANGE", ENOMEM: "GDI_ENOMEM", EDEV
           ESTATE: "GDI_ESTATE", ETIMEOUT: "GDI_ETIMEOUT"}
 BAL_GATED, BAL_SNAPSHOT = 0, 1
 ACCEPT_METROPOLIS, ACCEPT_PAPER = 0, 1
+FLAG_DENSE_BALANCE = 1
 SCOPE_AUTO, SCOPE_WORKGROUP, SCOPE_GRID, SCOPE_GRID_FENCED = 0, 1, 2, 3
 
 
@@ -54,7 +55,7 @@ class Schedule(ctypes.Structure):
         ("trace_m", ctypes.c_void_p),
         ("trace_cut", ctypes.c_void_p),
         ("acceptance", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
     ]
 
 
@@ -213,19 +214,21 @@ def set_tuning(h, scope: int = 0, block: int = 0, grid: int = 0, lanes_per_node:
     _check(lib().gdi_set_tuning(h, ctypes.byref(t)))
 
 
-def _schedule(temps, A, B, replica, mode, start_sweep, init, trace_m, trace_cut, acceptance=ACCEPT_METROPOLIS):
+def _schedule(temps, A, B, replica, mode, start_sweep, init, trace_m, trace_cut, acceptance=ACCEPT_METROPOLIS,
+              flags=0):
     T = np.ascontiguousarray(temps, dtype=np.float64)
     s = Schedule(n_sweeps=T.size, start_sweep=start_sweep, temps=T.ctypes.data, A=A, B=B,
                  replica=replica, balance_mode=mode,
                  init_spins=None if init is None else init.ctypes.data,
                  trace_m=None if trace_m is None else trace_m.ctypes.data,
                  trace_cut=None if trace_cut is None else trace_cut.ctypes.data,
-                 acceptance=acceptance, reserved=0)
+                 acceptance=acceptance, flags=flags)
     return s, T
 
 
 def anneal(h, n: int, temps, seed: int, A: int = 1, B: int = 1, replica: int = 0, mode: int = BAL_GATED,
-           start_sweep: int = 0, init=None, trace: bool = False, acceptance: int = ACCEPT_METROPOLIS) -> dict:
+           start_sweep: int = 0, init=None, trace: bool = False, acceptance: int = ACCEPT_METROPOLIS,
+           flags: int = 0) -> dict:
     """gdi_anneal: returns dict(spins (original order), M, cut, result, [trace_m, trace_cut]).
 
     temps: temperatures (Metropolis) or flip probabilities P_f(t) (acceptance=ACCEPT_PAPER)."""
@@ -233,7 +236,7 @@ def anneal(h, n: int, temps, seed: int, A: int = 1, B: int = 1, replica: int = 0
     init_a = None if init is None else np.ascontiguousarray(init, dtype=np.int8)
     tm = np.zeros(T.size, dtype=np.int64) if trace else None
     tc = np.zeros(T.size, dtype=np.int64) if trace else None
-    s, T = _schedule(T, A, B, replica, mode, start_sweep, init_a, tm, tc, acceptance)
+    s, T = _schedule(T, A, B, replica, mode, start_sweep, init_a, tm, tc, acceptance, flags)
     out = np.zeros(n, dtype=np.int8)
     _check(lib().gdi_anneal(h, ctypes.byref(s), ctypes.c_uint64(seed), _ptr(out)))
     r = last_result(h)
@@ -244,10 +247,11 @@ def anneal(h, n: int, temps, seed: int, A: int = 1, B: int = 1, replica: int = 0
 
 
 def anneal_dev(h, temps, seed: int, d_spins_out: int, A: int = 1, B: int = 1, replica: int = 0,
-               mode: int = BAL_GATED, start_sweep: int = 0, init=None, acceptance: int = ACCEPT_METROPOLIS):
+               mode: int = BAL_GATED, start_sweep: int = 0, init=None, acceptance: int = ACCEPT_METROPOLIS,
+               flags: int = 0):
     """gdi_anneal_dev: enqueues the anneal on the handle's stream; d_spins_out is a device pointer."""
     init_a = None if init is None else np.ascontiguousarray(init, dtype=np.int8)
-    s, T = _schedule(temps, A, B, replica, mode, start_sweep, init_a, None, None, acceptance)
+    s, T = _schedule(temps, A, B, replica, mode, start_sweep, init_a, None, None, acceptance, flags)
     _check(lib().gdi_anneal_dev(h, ctypes.byref(s), ctypes.c_uint64(seed), ctypes.c_void_p(d_spins_out)))
 
 

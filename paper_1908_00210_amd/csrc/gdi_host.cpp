@@ -693,6 +693,7 @@ struct RunCtx {
     GdiSweepArgs a;
     int thr_in_lds;
     uint64_t bar_words;
+    bool dense;        // the standard solver (GDI_FLAG_DENSE_BALANCE)
 };
 
 // Validates the schedule, builds the threshold table, writes the initial state
@@ -709,6 +710,7 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
     if (s->start_sweep > S) return fail(GDI_EINVAL, "start_sweep > n_sweeps");
     if (int rc0 = check_schedule_values(s)) return rc0;
     if (s->balance_mode > GDI_BAL_SNAPSHOT) return fail(GDI_EINVAL, "unknown balance_mode");
+    if (s->flags & ~GDI_FLAG_DENSE_BALANCE) return fail(GDI_EINVAL, "unknown schedule flags");
     if (dev_out && (s->trace_m || s->trace_cut)) return fail(GDI_EINVAL, "traces need the host variant");
     const int64_t de_max = std::llabs((long long)s->B) * g->max_abs_wdeg + 4 * std::llabs((long long)s->A) * ((int64_t)g->n + 1);
     if (de_max >= (int64_t(1) << 31))
@@ -716,6 +718,15 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
     const bool trace = s->trace_m || s->trace_cut;
 
     if ((rc = pick_launch(g, &r.ch))) return rc;
+    r.dense = (s->flags & GDI_FLAG_DENSE_BALANCE) != 0;
+    if (r.dense) {
+        int dev = 0, lds_max = 0;
+        HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+        HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
+        if (r.ch.scope != GDI_SCOPE_WORKGROUP || gdi_dense_lds_bytes(g->n_pad, g->C) + 64 > lds_max)
+            return fail(GDI_ERANGE, "the standard solver runs graphs that fit one workgroup (workgroup scope, "
+                                    "two spin copies in LDS)");
+    }
     if ((rc = ensure_table(g, s, de_max))) return rc;
     const uint64_t phases = (uint64_t)(S - s->start_sweep) * (uint64_t)g->C;
     r.bar_words = 0;
@@ -813,7 +824,9 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
     a.active_max = active_max;
     a.gate_small = 0;
     int rc = 0;
-    if (r.ch.scope == GDI_SCOPE_WORKGROUP) {
+    if (r.dense) {
+        rc = gdi_launch_sweep_dense(a, (int)r.ch.block, (int)r.ch.lanes, st);
+    } else if (r.ch.scope == GDI_SCOPE_WORKGROUP) {
         rc = gdi_launch_sweep_wg(a, (int)r.ch.block, (int)r.ch.lanes, r.ch.spins_lds ? 1 : 0, st);
     } else if (r.ch.scope == GDI_SCOPE_GRID) {
         GdiHaloArgs ha{};
@@ -954,6 +967,7 @@ int check_batch(const gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s
         return fail(GDI_EINVAL, "batched anneals start fresh and take no traces");
     if (s->balance_mode > GDI_BAL_SNAPSHOT) return fail(GDI_EINVAL, "unknown balance_mode");
     if (int rc0 = check_schedule_values(s)) return rc0;
+    if (s->flags) return fail(GDI_EINVAL, "the batched form takes no schedule flags");
     for (uint32_t i = 0; i < n_inst; ++i)
         if (!inst[i].graph) return fail(GDI_EINVAL, "NULL graph in batch");
     return GDI_OK;
@@ -1214,8 +1228,8 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
         return fail(GDI_EINVAL, "the network proposal needs weights and a threshold in (0, 1)");
     if (cfg->skip_mode == GDI_SKIP_HEURISTIC && cfg->heuristic_k < 1) return fail(GDI_EINVAL, "heuristic_k must be >= 1");
     if (s && (s->trace_m || s->trace_cut)) return fail(GDI_EINVAL, "the learned anneal takes no traces");
-    if (s && s->acceptance != GDI_ACCEPT_METROPOLIS)
-        return fail(GDI_EINVAL, "the learned anneal takes temperatures (Metropolis acceptance)");
+    if (s && (s->acceptance != GDI_ACCEPT_METROPOLIS || s->flags))
+        return fail(GDI_EINVAL, "the learned anneal takes temperatures (Metropolis acceptance) and no flags");
     RunCtx r;
     int rc = prepare_run(g, s, seed, false, r);
     if (rc) return rc;
@@ -1328,8 +1342,8 @@ int traces_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, uint32_t eve
     if (!d_x || !d_y || !n_snapshots) return fail(GDI_EINVAL, "NULL argument");
     if (k_label < 1 || every <= k_label) return fail(GDI_EINVAL, "need every > k_label >= 1");
     if (s && (s->trace_m || s->trace_cut)) return fail(GDI_EINVAL, "no traces here");
-    if (s && s->acceptance != GDI_ACCEPT_METROPOLIS)
-        return fail(GDI_EINVAL, "trace features take temperatures (Metropolis acceptance)");
+    if (s && (s->acceptance != GDI_ACCEPT_METROPOLIS || s->flags))
+        return fail(GDI_EINVAL, "trace features take temperatures (Metropolis acceptance) and no flags");
     RunCtx r;
     int rc = prepare_run(g, s, seed, false, r);
     if (rc) return rc;

@@ -1264,6 +1264,98 @@ __global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *a
     }
 }
 
+// ------------------------------------------------------------------ standard solver
+// The standard annealer of Alg. 2: every node computes the balance term from the
+// whole spin vector -- the sum of all n spins and the over-side count of its class --
+// instead of reading the tracked magnetisation. The scans read an LDS snapshot of the
+// phase-start spins, so the decisions equal those of the tracked sweep bit for bit;
+// only the cost differs (n reads per decision, n^2 per sweep). One workgroup, spins
+// and snapshot in LDS; the L lanes of a node split its scans.
+template <int L>
+__device__ __forceinline__ int32_t subgroup_sum(int32_t v)
+{
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
+    return v;
+}
+
+template <int L>
+__global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_dense(GdiSweepArgs a)
+{
+    extern __shared__ int32_t dyn[];
+    __shared__ int32_t acc[3];
+    const int c_round = (a.C + 3) & ~3;
+    int32_t *Psh = dyn;
+    int8_t *sp = reinterpret_cast<int8_t *>(dyn + c_round);
+    int8_t *snap = sp + a.n_pad;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int sub = tid / L, lane = tid % L, nsub = nth / L;
+    for (int i = tid; i < a.C; i += nth) Psh[i] = a.P[i];
+    for (int i = tid; i < a.n_pad; i += nth) sp[i] = a.spin[i];
+    if (tid < 3) acc[tid] = 0;
+    int32_t M = (int32_t)a.state[0];
+    __syncthreads();
+
+    int64_t dcut = 0, dcut_total = 0;
+    uint32_t p = 0;
+    for (uint32_t t = a.t0; t < a.S; ++t) {
+        const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)(a.K + 1);
+        for (int32_t c = 0; c < a.C; ++c, ++p) {
+            const int32_t beg = a.cbeg[c];
+            const int32_t size = a.csz[c];
+            for (int i = tid; i < a.n_pad; i += nth) snap[i] = sp[i];
+            __syncthreads();
+            int32_t dM = 0;
+            for (int32_t j = sub; j < size; j += nsub) {
+                const int32_t v = beg + j;
+                int32_t m = 0;
+                for (int32_t i = lane; i < a.n_pad; i += L) m += snap[i];
+                m = subgroup_sum<L>(m);
+                const int32_t sg = (m > 0) - (m < 0);
+                int32_t o = 0;
+                if (sg != 0)
+                    for (int32_t i = lane; i < size; i += L) o += snap[beg + i] == sg;
+                o = subgroup_sum<L>(o);
+                PhaseView pv;
+                pv.M0 = m;
+                pv.s = sg;
+                pv.D = (m < 0 ? -m : m) >> 1;
+                pv.O = (uint32_t)o;
+                int32_t h, sigma;
+                const bool flip = node_decide<L>(a, sp, v, lane, t, pv, thr_row, &h, &sigma);
+                if (flip && lane == 0) {
+                    sp[v] = (int8_t)(-sigma);
+                    dM -= 2 * sigma;
+                    dcut += (int64_t)sigma * h;
+                }
+            }
+            dM = wave_sum_i32(dM);
+            if ((tid & 63) == 0 && dM != 0) atomicAdd(&acc[p % 3], dM);
+            __syncthreads();
+            const int32_t tot = acc[p % 3];
+            M += tot;
+            if (tid == 0) {
+                if (a.C > 1) Psh[c] += tot / 2;
+                acc[(p + 2) % 3] = 0;
+            }
+        }
+        if (a.trace_m) {
+            if (tid == 0) a.trace_m[t] = M;
+            const int64_t w = wave_sum_i64(dcut);
+            if ((tid & 63) == 0 && w != 0) atomicAdd((unsigned long long *)&a.trace_dcut[t], (unsigned long long)w);
+            dcut_total += dcut;
+            dcut = 0;
+        }
+    }
+    dcut_total += dcut;
+    __syncthreads();
+    for (int i = tid; i < a.n_pad; i += nth) a.spin[i] = sp[i];
+    for (int i = tid; i < a.C; i += nth) a.P[i] = Psh[i];
+    if (tid == 0) a.state[0] = M;
+    const int64_t w = wave_sum_i64(dcut_total);
+    if ((tid & 63) == 0 && w != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)w);
+}
+
 inline int status(hipError_t e) { return (int)e; }
 
 template <int L>
@@ -1345,6 +1437,30 @@ int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, in
     hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, (hipStream_t)stream, rp, adj, spin, n_pad, cbeg, csz, C,
                        out3, P);
     return status(hipGetLastError());
+}
+
+int gdi_dense_lds_bytes(int32_t n_pad, int32_t C) { return ((C + 3) & ~3) * 4 + 2 * n_pad; }
+
+int gdi_launch_sweep_dense(const GdiSweepArgs &a, int block, int lanes, void *stream)
+{
+    const void *f = nullptr;
+    switch (lanes) {
+    case 1: f = (const void *)k_sweep_dense<1>; break;
+    case 2: f = (const void *)k_sweep_dense<2>; break;
+    case 4: f = (const void *)k_sweep_dense<4>; break;
+    case 8: f = (const void *)k_sweep_dense<8>; break;
+    case 16: f = (const void *)k_sweep_dense<16>; break;
+    case 32: f = (const void *)k_sweep_dense<32>; break;
+    case 64: f = (const void *)k_sweep_dense<64>; break;
+    default: return (int)hipErrorInvalidValue;
+    }
+    const int lds = gdi_dense_lds_bytes(a.n_pad, a.C);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return status(e);
+    GdiSweepArgs copy = a;
+    void *args[] = {&copy};
+    e = hipLaunchKernel(f, dim3(1), dim3(block), args, (size_t)lds, (hipStream_t)stream);
+    return status(e);
 }
 
 int gdi_wg_lds_bytes(int32_t n_pad, int32_t C, int spins_in_lds)

@@ -201,6 +201,30 @@ def test_paper_rule_rejects_bad_probabilities(gdi):
         assert r["spins"].shape == (g.n,)
 
 
+@pytest.mark.parametrize("mode,rule", [(0, 0), (1, 0), (0, 1)])
+def test_standard_solver_dense_balance(gdi, oracle_lib, mode, rule):
+    """Alg. 2's dense balance term (every decision sums all n spins) gives the tracked
+    sweep's results bit for bit."""
+    g = gs.rgg_graph(6000, 8.0, 27, "pm1")
+    T = PAPER_PF[:30] if rule else gs.geometric_temps(3.0, 0.05, 30)
+    print(f"[case] dense balance mode={mode} rule={rule}", flush=True)
+    ref = oracle_lib.anneal(g, T, 2, mode=mode, rule=rule, trace=True)
+    with gdi.Annealer(g) as a:
+        r = a.anneal(T, 2, mode=mode, acceptance=rule, flags=gdi.FLAG_DENSE_BALANCE, trace=True)
+    assert_same(ref, r)
+
+
+def test_standard_solver_needs_one_workgroup(gdi):
+    g = gs.rgg_graph(70_000, 8.0, 28)
+    with gdi.Annealer(g) as a:
+        with pytest.raises(gdi.GdiError) as e:
+            a.anneal(np.ones(2), 1, flags=gdi.FLAG_DENSE_BALANCE)
+        assert e.value.code == gdi.ERANGE
+        with pytest.raises(gdi.GdiError) as e:
+            a.anneal(np.ones(2), 1, flags=8)
+        assert e.value.code == gdi.EINVAL
+
+
 def test_large_weights_take_the_fenced_grid_sweep(gdi, oracle_lib):
     """The halo sweep packs weights into 11 bits; heavier graphs run the fenced grid sweep."""
     g0 = gs.rgg_graph(70_000, 8.0, 22)
