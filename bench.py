@@ -199,6 +199,28 @@ def forms_standard(gdi, gs, sweeps=50):
     return out
 
 
+def forms_racy(gdi, gs, seed, runs=3):
+    """Price of determinism on the 1M-node RGG: the deterministic colour-phase sweep
+    against Alg. 3's asynchronous racy sweep (one launch per sweep, no phases)."""
+    import numpy as np
+
+    g, T = gs.workload("rgg1m")
+    out = {}
+    with gdi.Annealer(g) as a:
+        for name, flags in (("deterministic", 0), ("racy", gdi.FLAG_RACY)):
+            a.anneal(T[:10], seed, flags=flags)
+            ms, cuts, Ms = [], [], []
+            for r in range(runs):
+                t0 = time.perf_counter()
+                res = a.anneal(T, seed, replica=r, flags=flags)
+                ms.append((time.perf_counter() - t0) * 1e3)
+                cuts.append(res["cut"])
+                Ms.append(res["M"])
+            out[name] = {"mean_ms": float(np.mean(ms)), "cuts": [int(c) for c in cuts], "M": [int(m) for m in Ms]}
+    out["racy_speedup"] = out["deterministic"]["mean_ms"] / out["racy"]["mean_ms"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +339,7 @@ def main():
         line["forms"] = forms_batched(gdi, gs, torch, seed)
         line["forms"]["learned_rgg200k"] = forms_learned(gdi, gs, torch, seed)
         line["forms"]["gdi_vs_standard_torus"] = forms_standard(gdi, gs)
+        line["forms"]["determinism_rgg1m"] = forms_racy(gdi, gs, seed)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, temps, seed, min(args.cpu_sweeps, S))
     print(json.dumps(line), flush=True)

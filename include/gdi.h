@@ -107,6 +107,12 @@ typedef struct {
  * one workgroup (n_pad <= 65536) only; GDI_ERANGE otherwise. */
 #define GDI_FLAG_DENSE_BALANCE 1u
 
+/* Alg. 3 as printed, asynchronous and racy: all nodes of a sweep decide in one launch
+ * against whatever neighbour spins and magnetisation they read, without colour phases
+ * or a gate; results are NOT reproducible (for pricing determinism). The returned M
+ * and cut are recounted from the final spins. No traces. */
+#define GDI_FLAG_RACY 2u
+
 /* Launch tuning; zero fields mean "choose automatically". */
 typedef struct {
     uint32_t scope;           /* GDI_SCOPE_* */

@@ -16,7 +16,7 @@ import os
 import numpy as np
 
 __all__ = [
-    "GdiError", "lib", "LIB_PATH", "BAL_GATED", "BAL_SNAPSHOT", "ACCEPT_METROPOLIS", "ACCEPT_PAPER", "FLAG_DENSE_BALANCE", "SCOPE_AUTO", "SCOPE_WORKGROUP",
+    "GdiError", "lib", "LIB_PATH", "BAL_GATED", "BAL_SNAPSHOT", "ACCEPT_METROPOLIS", "ACCEPT_PAPER", "FLAG_DENSE_BALANCE", "FLAG_RACY", "SCOPE_AUTO", "SCOPE_WORKGROUP",
     "SCOPE_GRID", "SCOPE_GRID_FENCED", "Schedule", "Tuning", "Result", "GraphInfo", "create", "destroy", "anneal",
     "anneal_dev", "cut", "cut_dev", "last_result", "set_stream", "set_tuning", "get_info",
     "get_colouring", "colour_csr", "threshold_table", "philox4x32_10", "version", "Annealer",
@@ -33,6 +33,7 @@ _NAMES = {EINVAL: "GDI_EINVAL", ERANGE: "GDI_ERANGE", ENOMEM: "GDI_ENOMEM", EDEV
 BAL_GATED, BAL_SNAPSHOT = 0, 1
 ACCEPT_METROPOLIS, ACCEPT_PAPER = 0, 1
 FLAG_DENSE_BALANCE = 1
+FLAG_RACY = 2
 SCOPE_AUTO, SCOPE_WORKGROUP, SCOPE_GRID, SCOPE_GRID_FENCED = 0, 1, 2, 3
 
 

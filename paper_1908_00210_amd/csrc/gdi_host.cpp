@@ -694,6 +694,7 @@ struct RunCtx {
     int thr_in_lds;
     uint64_t bar_words;
     bool dense;        // the standard solver (GDI_FLAG_DENSE_BALANCE)
+    bool racy;         // the asynchronous sweep (GDI_FLAG_RACY)
 };
 
 // Validates the schedule, builds the threshold table, writes the initial state
@@ -710,7 +711,11 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
     if (s->start_sweep > S) return fail(GDI_EINVAL, "start_sweep > n_sweeps");
     if (int rc0 = check_schedule_values(s)) return rc0;
     if (s->balance_mode > GDI_BAL_SNAPSHOT) return fail(GDI_EINVAL, "unknown balance_mode");
-    if (s->flags & ~GDI_FLAG_DENSE_BALANCE) return fail(GDI_EINVAL, "unknown schedule flags");
+    if (s->flags & ~(GDI_FLAG_DENSE_BALANCE | GDI_FLAG_RACY)) return fail(GDI_EINVAL, "unknown schedule flags");
+    if ((s->flags & GDI_FLAG_DENSE_BALANCE) && (s->flags & GDI_FLAG_RACY))
+        return fail(GDI_EINVAL, "the dense-balance and asynchronous flags exclude each other");
+    if ((s->flags & GDI_FLAG_RACY) && (s->trace_m || s->trace_cut))
+        return fail(GDI_EINVAL, "the asynchronous sweep takes no traces");
     if (dev_out && (s->trace_m || s->trace_cut)) return fail(GDI_EINVAL, "traces need the host variant");
     const int64_t de_max = std::llabs((long long)s->B) * g->max_abs_wdeg + 4 * std::llabs((long long)s->A) * ((int64_t)g->n + 1);
     if (de_max >= (int64_t(1) << 31))
@@ -719,6 +724,7 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
 
     if ((rc = pick_launch(g, &r.ch))) return rc;
     r.dense = (s->flags & GDI_FLAG_DENSE_BALANCE) != 0;
+    r.racy = (s->flags & GDI_FLAG_RACY) != 0;
     if (r.dense) {
         int dev = 0, lds_max = 0;
         HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
@@ -824,7 +830,19 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
     a.active_max = active_max;
     a.gate_small = 0;
     int rc = 0;
-    if (r.dense) {
+    if (r.racy) {
+        for (uint32_t t = t_from; t < t_to && !rc; ++t) rc = gdi_launch_sweep_racy(a, t, st);
+        // the tracked values are racy: recount M, the cut and the class counts from the spins
+        if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_red.p), 4, st);
+        if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_P.p), (g->C + 2) / 2, st);
+        if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->d_cbeg.p, g->d_csz.p, g->C,
+                                        g->d_red.p, g->d_P.p, st);
+        if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_state.p + 1), 1, st);
+        if (!rc) {
+            hipError_t e = hipMemcpyAsync(g->d_state.p, g->d_red.p, 8, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return hip_fail(e, "state copy");
+        }
+    } else if (r.dense) {
         rc = gdi_launch_sweep_dense(a, (int)r.ch.block, (int)r.ch.lanes, st);
     } else if (r.ch.scope == GDI_SCOPE_WORKGROUP) {
         rc = gdi_launch_sweep_wg(a, (int)r.ch.block, (int)r.ch.lanes, r.ch.spins_lds ? 1 : 0, st);

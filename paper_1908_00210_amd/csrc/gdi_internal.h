@@ -160,6 +160,7 @@ int gdi_launch_gather_in(const int32_t *orig, const int8_t *in_orig, int32_t n_p
 int gdi_active_lds_bytes(int32_t n_pad, int32_t C);
 int gdi_launch_sweep_active(const GdiSweepArgs &a, GdiActiveRec *rec, void *stream);
 int gdi_dense_lds_bytes(int32_t n_pad, int32_t C);
+int gdi_launch_sweep_racy(const GdiSweepArgs &a, uint32_t t, void *stream);
 int gdi_launch_sweep_dense(const GdiSweepArgs &a, int block, int lanes, void *stream);
 int gdi_launch_sweep_wg(const GdiSweepArgs &a, int block, int lanes, int spins_in_lds, void *stream);
 int gdi_launch_sweep_grid(const GdiSweepArgs &a, int grid, int block, int lanes, void *stream);

@@ -1356,6 +1356,54 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_dense(GdiSweepArgs a)
     if ((tid & 63) == 0 && w != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)w);
 }
 
+// ------------------------------------------------------------------ asynchronous sweep
+// Alg. 3 as printed, racy by design: every node of the graph decides in the same
+// launch against the neighbour spins and the magnetisation as it finds them (other
+// nodes may or may not have flipped yet) and publishes its flip at once. One launch
+// per sweep; results are not reproducible. The balance term takes the magnetisation
+// read by its workgroup (there are no colour phases, hence no gate); each workgroup
+// adds its flips' change of M with one atomic.
+__global__ void __launch_bounds__(1024) k_sweep_racy(GdiSweepArgs a, uint32_t t)
+{
+    __shared__ int32_t m_sh, dm_sh;
+    // the magnetisation as this workgroup finds it (one load; racy anyway), and one
+    // atomic per workgroup for its flips: same-address atomics serialise in memory
+    if (threadIdx.x == 0) {
+        m_sh = (int32_t)__hip_atomic_load(&a.state[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        dm_sh = 0;
+    }
+    __syncthreads();
+    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t dM = 0;
+    if (v < a.n_pad) {
+        const int32_t o = a.orig[v];
+        if (o >= 0) {
+            int32_t h = 0;
+            for (int32_t k = a.rp[v]; k < a.rp[v + 1]; ++k) {
+                const int2 e = a.adj[k];
+                // relaxed and cached: whatever value this CU's caches hold, as on the paper's GPU
+                h += e.y * (int32_t)__hip_atomic_load(&a.spin[e.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            const int32_t sigma = a.spin[v];
+            const int32_t M = m_sh;
+            const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * M);
+            const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)(a.K + 1);
+            const uint32_t x0 = philox10((uint32_t)o, t, a.replica, 0u, a.key0, a.key1).w0;
+            bool flip;
+            if (a.rule) flip = (dE < 0) != (x0 < thr_row[0]);
+            else flip = dE <= 0 || (dE <= a.K && x0 < thr_row[dE]);
+            if (flip) {
+                __hip_atomic_store(&a.spin[v], (int8_t)(-sigma), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                dM = -2 * sigma;
+            }
+        }
+    }
+    dM = wave_sum_i32(dM);
+    if ((threadIdx.x & 63) == 0 && dM != 0) atomicAdd(&dm_sh, dM);
+    __syncthreads();
+    if (threadIdx.x == 0 && dm_sh != 0) atomicAdd((unsigned long long *)&a.state[0], (unsigned long long)(int64_t)dm_sh);
+}
+
 inline int status(hipError_t e) { return (int)e; }
 
 template <int L>
@@ -1440,6 +1488,12 @@ int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, in
 }
 
 int gdi_dense_lds_bytes(int32_t n_pad, int32_t C) { return ((C + 3) & ~3) * 4 + 2 * n_pad; }
+
+int gdi_launch_sweep_racy(const GdiSweepArgs &a, uint32_t t, void *stream)
+{
+    hipLaunchKernelGGL(k_sweep_racy, dim3(blocks_for(a.n_pad, 1024)), dim3(1024), 0, (hipStream_t)stream, a, t);
+    return status(hipGetLastError());
+}
 
 int gdi_launch_sweep_dense(const GdiSweepArgs &a, int block, int lanes, void *stream)
 {

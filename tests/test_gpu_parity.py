@@ -225,6 +225,25 @@ def test_standard_solver_needs_one_workgroup(gdi):
         assert e.value.code == gdi.EINVAL
 
 
+def test_asynchronous_sweep_reports_its_own_state(gdi):
+    """The racy sweep of Alg. 3 as printed is not reproducible; what must hold is that
+    the returned M and cut are those of the returned spins. (Its quality is measured by
+    the benchmark: with every node of a sweep updating at once, neighbours flip
+    together and the cut stays near random.)"""
+    g = gs.rgg_graph(100_000, 8.0, 29)
+    T = gs.geometric_temps(3.0, 0.05, 300)
+    with gdi.Annealer(g) as a:
+        det = a.anneal(T, 3)
+        rac = a.anneal(T, 3, flags=gdi.FLAG_RACY)
+        cw, ce, m = a.cut(rac["spins"])
+        with pytest.raises(gdi.GdiError) as e:
+            a.anneal(T, 3, flags=gdi.FLAG_RACY, trace=True)
+        assert e.value.code == gdi.EINVAL
+    print(f"deterministic cut {det['cut']} M {det['M']}; racy cut {rac['cut']} M {rac['M']}", flush=True)
+    assert (cw, m) == (rac["cut"], rac["M"])
+    assert 0 <= rac["cut"] <= g.nnz // 2 and abs(rac["M"]) <= g.n
+
+
 def test_large_weights_take_the_fenced_grid_sweep(gdi, oracle_lib):
     """The halo sweep packs weights into 11 bits; heavier graphs run the fenced grid sweep."""
     g0 = gs.rgg_graph(70_000, 8.0, 22)
