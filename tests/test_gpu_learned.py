@@ -298,3 +298,34 @@ def test_trained_network_gain(gdi):
     assert res["network"][1] > 0.5 and res["age"][1] > 0.5
     assert net <= 1.03 * plain
     assert age >= 1.15 * plain
+
+
+def test_full_size_learned_schedules(gdi, L):
+    """The evaluation graph of the learned form (RGG n = 200k, mean degree 8), in the
+    bench's launch configuration: the age-based proposal over the whole 2000-sweep
+    schedule from sweep 1000 on, bit-exact; the network proposal (random weights, centred)
+    over 200 sweeps, with the near-tie rule of the network parity test."""
+    g, T = gs.workload("rgg200k")
+    print("[case] rgg200k heuristic learn_from=1000", flush=True)
+    ref = L.learned_anneal(g, T, 1, k_full=8, proposal="heuristic", heuristic_k=8, learn_from=1000)
+    with gdi.Annealer(g) as a:
+        r = a.anneal_learned(T, 1, 8, skip_mode=gdi.SKIP_HEURISTIC, heuristic_k=8, learn_from=1000, mask_trace=True)
+    assert np.array_equal(r["masks"], ref["masks"])
+    assert np.array_equal(r["spins"], ref["spins"]) and (r["M"], r["cut"]) == (ref["M"], ref["cut"])
+
+    T2 = gs.geometric_temps(3.0, 0.05, 200)
+    w = centred_weights(L, g, 31)
+    print("[case] rgg200k network 200 sweeps", flush=True)
+    ref = L.learned_anneal(g, T2, 1, k_full=8, proposal="network", weights=w, p=0.5, learn_from=100)
+    with gdi.Annealer(g) as a:
+        r = a.anneal_learned(T2, 1, 8, skip_mode=gdi.SKIP_MLP, weights=w, skip_threshold=0.5, learn_from=100,
+                             mask_trace=True)
+    diff_rows = np.flatnonzero(np.any(r["masks"] != ref["masks"], axis=1))
+    print(f"skipped fraction {ref['masks'].mean():.3f}, rows differing: {diff_rows.tolist()}", flush=True)
+    if diff_rows.size == 0:
+        assert np.array_equal(r["spins"], ref["spins"]) and (r["M"], r["cut"]) == (ref["M"], ref["cut"])
+    else:
+        row = int(diff_rows[0])
+        nodes = np.flatnonzero(r["masks"][row] != ref["masks"][row])
+        near = np.abs(ref["logits"][row][nodes].astype(np.float64) - np.float64(ref["threshold"]))
+        assert near.max() < 1e-4, "a mask bit differs at a node far from the threshold"
