@@ -504,7 +504,9 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
         }
         tail_beg[(size_t)(c - T0) + 1] = (int32_t)tail_v.size();
     }
-    std::vector<uint32_t> adjL(g->h_adj.size() + 1, 0u);  // last: the zero sentinel
+    // after the last row: GDI_HALO_PF zero entries; the sweep reads GDI_HALO_PF entries
+    // from any row start, so these keep it in bounds
+    std::vector<uint32_t> adjL(g->h_adj.size() + GDI_HALO_PF, 0u);
     for (int32_t v = 0; v < g->n_pad; ++v) {
         const int32_t cv = g->cls[(size_t)v];
         if (cv < 0) continue;
@@ -850,7 +852,6 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
         GdiHaloArgs ha{};
         ha.base = a;
         ha.adjL = g->d_adjL.p;
-        ha.sentinel = (int32_t)g->nnz;
         ha.tab = g->d_tab.p;
         ha.words = g->d_words.p;
         ha.member = g->d_member.p;

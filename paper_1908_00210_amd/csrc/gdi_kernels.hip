@@ -734,18 +734,70 @@ struct NodePrefetch {
 __device__ __forceinline__ int32_t ent_lb(uint32_t e) { return (int32_t)(e >> 11); }
 __device__ __forceinline__ int32_t ent_w(uint32_t e) { return (int32_t)(e << 21) >> 21; }
 
-// Local field over the first GDI_HALO_PF entries of a row (zero entries past its end):
-// every LDS word is read before any is used, so the reads overlap instead of each
-// waiting for the previous one.
-__device__ __forceinline__ int32_t field_sum(const uint32_t *bits, const uint32_t (&e)[GDI_HALO_PF])
+// Local field over the first `cnt` of GDI_HALO_PF loaded entries (the rest belong to
+// later rows and count as the zero entry: bit 0, weight 0). Every LDS word is read
+// before any is used, so the reads overlap instead of each waiting for the previous one.
+__device__ __forceinline__ int32_t field_sum(const uint32_t *bits, const uint32_t (&e)[GDI_HALO_PF], int32_t cnt)
 {
-    uint32_t wv[GDI_HALO_PF];
+    uint32_t ek[GDI_HALO_PF], wv[GDI_HALO_PF];
 #pragma unroll
-    for (int k = 0; k < GDI_HALO_PF; ++k) wv[k] = bits[ent_lb(e[k]) >> 5];
+    for (int k = 0; k < GDI_HALO_PF; ++k) ek[k] = k < cnt ? e[k] : 0u;
+#pragma unroll
+    for (int k = 0; k < GDI_HALO_PF; ++k) wv[k] = bits[ent_lb(ek[k]) >> 5];
     int32_t h = 0;
 #pragma unroll
-    for (int k = 0; k < GDI_HALO_PF; ++k) h += ent_w(e[k]) * ((int32_t)((wv[k] >> (ent_lb(e[k]) & 31)) & 1u) * 2 - 1);
+    for (int k = 0; k < GDI_HALO_PF; ++k) h += ent_w(ek[k]) * ((int32_t)((wv[k] >> (ent_lb(ek[k]) & 31)) & 1u) * 2 - 1);
     return h;
+}
+
+// GDI_HALO_PF consecutive packed entries from index k0, as 16-byte loads. Rows start at
+// any entry, so the loads are only dword-aligned; the packed CSR carries GDI_HALO_PF zero
+// entries after its last row, so the loads stay inside it for every k0 <= nnz.
+typedef uint32_t gdi_u32x4 __attribute__((ext_vector_type(4)));
+typedef gdi_u32x4 gdi_u32x4_a4 __attribute__((aligned(4)));
+__device__ __forceinline__ void load_run(const uint32_t *adjL, int32_t k0, uint32_t (&e)[GDI_HALO_PF])
+{
+    const gdi_u32x4_a4 *src = reinterpret_cast<const gdi_u32x4_a4 *>(adjL + k0);
+#pragma unroll
+    for (int q = 0; q < GDI_HALO_PF / 4; ++q) {
+        const gdi_u32x4 v = src[q];
+        e[4 * q] = v.x;
+        e[4 * q + 1] = v.y;
+        e[4 * q + 2] = v.z;
+        e[4 * q + 3] = v.w;
+    }
+}
+
+// Local field of a row whose first GDI_HALO_PF entries are in registers. Entries past
+// them are loaded GDI_HALO_PF at a time, every load of a batch issued before any is
+// used, so a batch costs one memory round trip rather than one per entry.
+__device__ __forceinline__ int32_t row_field(const GdiHaloArgs &h, const uint32_t *bits, const NodePrefetch &q)
+{
+    int32_t hv = field_sum(bits, q.e, q.deg);
+    for (int32_t k0 = GDI_HALO_PF; k0 < q.deg; k0 += GDI_HALO_PF) {
+        uint32_t ex[GDI_HALO_PF];
+        load_run(h.adjL, q.r0 + k0, ex);
+        hv += field_sum(bits, ex, q.deg - k0);
+    }
+    return hv;
+}
+
+// Local field of a tail node from the tail's CSR in LDS, entries [k0, k1): eight
+// entries are read before their spin words, and those before any is used, so the
+// LDS latencies overlap. Past k1 the zero entry (bit 0, weight 0) adds nothing.
+__device__ __forceinline__ int32_t tail_field(const uint32_t *bits, const uint32_t *tent, int32_t k0, int32_t k1)
+{
+    int32_t hv = 0;
+    for (int32_t k = k0; k < k1; k += 8) {
+        uint32_t ee[8], wv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ee[j] = k + j < k1 ? tent[k + j] : 0u;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) wv[j] = bits[ent_lb(ee[j]) >> 5];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) hv += ent_w(ee[j]) * ((int32_t)((wv[j] >> (ent_lb(ee[j]) & 31)) & 1u) * 2 - 1);
+    }
+    return hv;
 }
 
 __device__ __forceinline__ void load_row(const GdiSweepArgs &a, int32_t v, RowAhead &ra)
@@ -767,11 +819,10 @@ __device__ __forceinline__ void load_entries(const GdiHaloArgs &h, const RowAhea
     pf.x1 = w.w1;
     pf.r0 = ra.r0;
     pf.deg = ra.r1 - ra.r0;
-    // every load is issued unconditionally (entries past the row read the zero entry
-    // at adjL[sentinel]): a register that is zeroed and then conditionally loaded
+    // every load is issued unconditionally, whatever the degree (field_sum drops the
+    // entries past the row): a register that is zeroed and then conditionally loaded
     // makes the compiler wait for all earlier loads before zeroing it
-#pragma unroll
-    for (int k = 0; k < GDI_HALO_PF; ++k) pf.e[k] = h.adjL[k < pf.deg ? ra.r0 + k : h.sentinel];
+    load_run(h.adjL, ra.r0, pf.e);
 }
 
 // Metropolis decision with the node's Philox words already drawn. The threshold
@@ -896,6 +947,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     __shared__ int32_t total_sh;
     __shared__ int32_t abort_sh;
     __shared__ int32_t tacc[3];
+    __shared__ uint32_t wdone;  // worker waves whose window polls are done (running count)
 
     const int tid = threadIdx.x, nth = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = nth >> 6;
@@ -938,6 +990,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
         abort_sh = 0;
     }
     if (tid < 3) tacc[tid] = 0;
+    if (tid == 0) wdone = 0;
     int32_t M = (int32_t)a.state[0];
     __syncthreads();
 
@@ -982,6 +1035,15 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
 
     int64_t dcut = 0, dcut_total = 0;
     uint32_t p = 0, kk = 0;
+    // local field of this thread's first-pass node of the coming phase, summed before
+    // the phase's M is known (h_ready) or not
+    int32_t h_pre = 0;
+    bool h_ready = false;
+    uint32_t wtarget = 0;
+    // this thread's tail node in the current sweep: Philox words and, for the first tail
+    // class, the local field, drawn while the last grid phase's dM travels
+    uint32_t tx0 = 0, tx1 = 0;
+    int32_t th_pre = 0;
     for (uint32_t t = a.t0; t < a.S; ++t) {
         const uint32_t *thr_l = thr_sh + (t & 1u) * K1;
         const uint32_t *thr_g = a.thr + (size_t)t * K1;
@@ -1012,11 +1074,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                         } else {
                             q = pf;
                         }
-                        int32_t hv = field_sum(bits, q.e);
-                        for (int32_t k = GDI_HALO_PF; k < q.deg; ++k) {
-                            const uint32_t en = h.adjL[q.r0 + k];
-                            hv += ent_w(en) * lds_spin(bits, ent_lb(en));
-                        }
+                        const int32_t hv = base == e.node_lo && h_ready ? h_pre : row_field(h, bits, q);
                         const int32_t lb = (e.lds_off + (v >> 5) - e.win_lo) * 32 + (v & 31);
                         const int32_t sigma = lds_spin(bits, lb);
                         flip = decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, q.x0, q.x1);
@@ -1060,18 +1118,48 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                 const bool last_s1 = s1 + 1 == T0;
                 const uint32_t t2 = last_s1 ? t1 + 1u : t1;
                 const int32_t s2 = last_s1 ? 0 : s1 + 1;
+                // nodes the proposal skips need no entries
+                const int32_t v1 = step_node(h, tab, s1, tid);
+                const bool want1 = t1 < a.S && v1 >= 0 && !(a.mask && ((a.mask[v1 >> 5] >> (v1 & 31)) & 1u));
                 if (t1 < a.S) {
                     if (c + 1 == T0 && thr_lds && t + 1u < a.S)
                         for (int i = tid; i < K1; i += nwork) thr_sh[((t + 1u) & 1u) * K1 + i] = a.thr[(size_t)(t + 1u) * K1 + i];
-                    // nodes the proposal skips need no entries
-                    const int32_t v1 = step_node(h, tab, s1, tid);
-                    if (v1 >= 0 && !(a.mask && ((a.mask[v1 >> 5] >> (v1 & 31)) & 1u))) load_entries(h, ra, t1, pf);
+                    if (want1) load_entries(h, ra, t1, pf);
                 }
                 const int32_t v2 = step_node(h, tab, s2, tid);
                 if (t2 < a.S && v2 >= 0) load_row(a, v2, ra);
                 GDI_TSTAMP(6, tid == 0);
                 good = poll_phase_words(h, e, c, gidx, bits, epoch, tid, nwork, abort_v);
                 GDI_TSTAMP(7, tid == 0);
+                // Once every worker wave has polled, the windows hold every spin the next
+                // phase reads, so the next phase's local fields are summed now, while this
+                // phase's dM is still travelling; only the decisions wait for the new M.
+                // Before the tail, the same holds for the first tail class. Each worker
+                // wave counts itself in whether or not its polls succeeded, so this wait ends.
+                h_ready = false;
+                const bool pre_next = t1 < a.S && !(has_tail && last_s);
+                const bool pre_tail = has_tail && last_s;
+                if (pre_next || pre_tail) {
+                    if (pre_tail && my_tail >= 0) {
+                        const Words4 xw = philox10((uint32_t)my_id, t, a.replica, 0u, a.key0, a.key1);
+                        tx0 = xw.w0;
+                        tx1 = xw.w1;
+                    }
+                    if (lane == 0) __hip_atomic_fetch_add(&wdone, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    wtarget += (uint32_t)(nwork >> 6);
+                    for (int64_t tries = 0;
+                         (int32_t)(__hip_atomic_load(&wdone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) - wtarget) < 0;
+                         ++tries) {
+                        if (tries >= a.spin_limit || aborted(abort_v)) {
+                            good = false;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    if (good && pre_next && want1) h_pre = row_field(h, bits, pf);
+                    if (good && pre_tail && my_tc == T0) th_pre = tail_field(bits, tent, trp[tid], trp[tid + 1]);
+                    h_ready = pre_next;
+                }
             } else if (wave == nwaves - 1) {
                 // this wave has no other memory traffic, so its store leaves at once
                 if (lane == 0) {
@@ -1112,12 +1200,10 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                 if (worker && my_tc == tc && !(a.mask && ((a.mask[my_tail >> 5] >> (my_tail & 31)) & 1u))) {
                     const PhaseView pv = make_view(M, Psh[tc], csz_sh[tc], a.C, a.n);
                     const int32_t v = my_tail;
-                    const Words4 xw = philox10((uint32_t)my_id, t, a.replica, 0u, a.key0, a.key1);
-                    int32_t hv = 0;
-                    for (int32_t k = trp[tid]; k < trp[tid + 1]; ++k) hv += ent_w(tent[k]) * lds_spin(bits, ent_lb(tent[k]));
+                    const int32_t hv = tc == T0 ? th_pre : tail_field(bits, tent, trp[tid], trp[tid + 1]);
                     const int32_t lb = (h.tail_off + ((v - tail_base) >> 5)) * 32 + (v & 31);
                     const int32_t sigma = lds_spin(bits, lb);
-                    if (decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, xw.w0, xw.w1)) {
+                    if (decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, tx0, tx1)) {
                         // members of a class are never neighbours: concurrent readers of this
                         // word only look at bits that do not change in this class
                         atomicXor(&bits[lb >> 5], 1u << (lb & 31));
