@@ -90,6 +90,8 @@ struct gdi_graph {
     DevBuf<uint32_t> d_adjL;
     DevBuf<int32_t> d_tail_v, d_tail_beg, d_gat_words, d_gat_beg, d_tail_rp;
     DevBuf<uint32_t> d_tail_ent;
+    int32_t halo_ovf_off = 0, halo_ovf_len = 0;
+    DevBuf<uint32_t> d_ovf;
     DevBuf<GdiHaloEntry> d_tab;
     DevBuf<uint64_t> d_words, d_member, d_group;
 
@@ -122,7 +124,7 @@ struct gdi_graph {
         d_adj.release(); d_spin.release(); d_io.release(); d_state.release(); d_red.release();
         d_trace.release(); d_thr.release(); d_bar.release();
         d_adjL.release(); d_tail_v.release(); d_tail_beg.release(); d_gat_words.release(); d_gat_beg.release();
-        d_tail_rp.release(); d_tail_ent.release();
+        d_tail_rp.release(); d_tail_ent.release(); d_ovf.release();
         d_tab.release(); d_words.release(); d_member.release(); d_group.release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -529,6 +531,38 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
             adjL[(size_t)k] = pack_entry(lb, g->h_adj[(size_t)k].y);
         }
     }
+    // Rows longer than GDI_HALO_PF keep their entries from GDI_HALO_PF - 1 on in an
+    // overflow region at the end of the owner workgroup's LDS image, and the row's entry
+    // GDI_HALO_PF - 1 then holds the LDS word where they start, so that no row needs a
+    // second trip to memory. Only when every workgroup's region fits beside its image;
+    // otherwise the sweep reads those entries from the packed CSR.
+    std::vector<std::vector<uint32_t>> ovf((size_t)G);
+    std::vector<std::pair<size_t, int32_t>> links;  // (entry index, position in the owner's region)
+    for (int32_t v = 0; v < g->n_pad; ++v) {
+        const int32_t cv = g->cls[(size_t)v];
+        const int32_t r0 = g->h_rp[(size_t)v], r1 = g->h_rp[(size_t)v + 1];
+        if (cv < 0 || cv >= T0 || r1 - r0 <= GDI_HALO_PF) continue;
+        std::vector<uint32_t> &L = ovf[(size_t)owner(v)];
+        links.emplace_back((size_t)r0 + GDI_HALO_PF - 1, (int32_t)L.size());
+        L.insert(L.end(), adjL.begin() + r0 + GDI_HALO_PF - 1, adjL.begin() + r1);
+    }
+    int64_t ovf_max = 0;
+    for (const auto &L : ovf) ovf_max = std::max<int64_t>(ovf_max, (int64_t)L.size());
+    int32_t ovf_len = 0;
+    const int32_t ovf_off = lds_words;
+    if (ovf_max > 0 && ovf_max < INT32_MAX / 8 &&
+        gdi_halo_lds_bytes(lds_words + (int32_t)ovf_max, C, 0) <= lds_budget) {
+        ovf_len = (int32_t)ovf_max;
+        lds_words += ovf_len;
+        for (const auto &l : links) adjL[l.first] = (uint32_t)(ovf_off + l.second);
+    }
+    std::vector<uint32_t> ovf_flat((size_t)G * (size_t)ovf_len, 0u);
+    for (int32_t b = 0; b < G && ovf_len > 0; ++b)
+        std::copy(ovf[(size_t)b].begin(), ovf[(size_t)b].end(), ovf_flat.begin() + (size_t)b * ovf_len);
+    HIP_TRY(g->d_ovf.reserve(std::max<size_t>(ovf_flat.size(), 1)), "hipMalloc halo overflow");
+    if (!ovf_flat.empty())
+        HIP_TRY(hipMemcpy(g->d_ovf.p, ovf_flat.data(), ovf_flat.size() * 4, hipMemcpyHostToDevice),
+                "upload halo overflow");
     HIP_TRY(g->d_adjL.reserve(adjL.size()), "hipMalloc halo CSR");
     HIP_TRY(g->d_tab.reserve(tab.size()), "hipMalloc halo table");
     HIP_TRY(g->d_words.reserve((size_t)g->n_pad / 32 + 1), "hipMalloc packed spins");
@@ -562,6 +596,8 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
     g->halo_tail_nnz = (int32_t)tail_ent.size();
     g->halo_trp_off = trp_off;
     g->halo_tent_off = tent_off;
+    g->halo_ovf_off = ovf_off;
+    g->halo_ovf_len = ovf_len;
     return GDI_OK;
 }
 
@@ -870,6 +906,9 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
         ha.tent_off = g->halo_tent_off;
         ha.tail_rp = g->d_tail_rp.p;
         ha.tail_ent = g->d_tail_ent.p;
+        ha.ovf_off = g->halo_ovf_off;
+        ha.ovf_len = g->halo_ovf_len;
+        ha.ovf = g->d_ovf.p;
         ha.thr_in_lds = r.thr_in_lds;
         rc = gdi_launch_fill_u64(g->d_words.p, (int64_t)g->n_pad / 32 + 1, st);
         if (!rc) rc = gdi_launch_fill_u64(g->d_member.p, 8 * 64, st);

@@ -110,6 +110,12 @@ struct GdiHaloArgs {
     int32_t trp_off, tent_off;
     const int32_t *tail_rp;
     const uint32_t *tail_ent;
+    // Rows longer than GDI_HALO_PF (when ovf_len > 0): their entries from GDI_HALO_PF - 1
+    // on sit in an overflow region of the owner workgroup's LDS image (ovf_len words at
+    // ovf_off, copied from ovf + b * ovf_len at launch), and the row's entry GDI_HALO_PF - 1
+    // holds the LDS word where they start. With ovf_len == 0 they are read from adjL.
+    int32_t ovf_off, ovf_len;
+    const uint32_t *ovf;
 };
 
 // Batched form: one instance (graph, replica) per queue entry.

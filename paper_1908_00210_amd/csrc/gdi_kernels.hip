@@ -768,34 +768,41 @@ __device__ __forceinline__ void load_run(const uint32_t *adjL, int32_t k0, uint3
     }
 }
 
-// Local field of a row whose first GDI_HALO_PF entries are in registers. Entries past
-// them are loaded GDI_HALO_PF at a time, every load of a batch issued before any is
-// used, so a batch costs one memory round trip rather than one per entry.
-__device__ __forceinline__ int32_t row_field(const GdiHaloArgs &h, const uint32_t *bits, const NodePrefetch &q)
-{
-    int32_t hv = field_sum(bits, q.e, q.deg);
-    for (int32_t k0 = GDI_HALO_PF; k0 < q.deg; k0 += GDI_HALO_PF) {
-        uint32_t ex[GDI_HALO_PF];
-        load_run(h.adjL, q.r0 + k0, ex);
-        hv += field_sum(bits, ex, q.deg - k0);
-    }
-    return hv;
-}
-
-// Local field of a tail node from the tail's CSR in LDS, entries [k0, k1): eight
-// entries are read before their spin words, and those before any is used, so the
-// LDS latencies overlap. Past k1 the zero entry (bit 0, weight 0) adds nothing.
-__device__ __forceinline__ int32_t tail_field(const uint32_t *bits, const uint32_t *tent, int32_t k0, int32_t k1)
+// Local field over packed entries src[k0, k1) held in LDS (the tail's CSR, or a long
+// row's overflow entries): eight entries are read before their spin words, and those
+// before any is used, so the LDS latencies overlap. Past k1 the zero entry (bit 0,
+// weight 0) adds nothing.
+__device__ __forceinline__ int32_t lds_field(const uint32_t *bits, const uint32_t *src, int32_t k0, int32_t k1)
 {
     int32_t hv = 0;
     for (int32_t k = k0; k < k1; k += 8) {
         uint32_t ee[8], wv[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) ee[j] = k + j < k1 ? tent[k + j] : 0u;
+        for (int j = 0; j < 8; ++j) ee[j] = k + j < k1 ? src[k + j] : 0u;
 #pragma unroll
         for (int j = 0; j < 8; ++j) wv[j] = bits[ent_lb(ee[j]) >> 5];
 #pragma unroll
         for (int j = 0; j < 8; ++j) hv += ent_w(ee[j]) * ((int32_t)((wv[j] >> (ent_lb(ee[j]) & 31)) & 1u) * 2 - 1);
+    }
+    return hv;
+}
+
+// Local field of a row whose first GDI_HALO_PF entries are in registers. A longer row
+// continues in the LDS overflow region at the word its entry GDI_HALO_PF - 1 names;
+// without that region, the entries past GDI_HALO_PF are loaded GDI_HALO_PF at a time,
+// every load of a batch issued before any is used (one memory round trip per batch).
+__device__ __forceinline__ int32_t row_field(const GdiHaloArgs &h, const uint32_t *bits, const NodePrefetch &q)
+{
+    const bool linked = h.ovf_len > 0 && q.deg > GDI_HALO_PF;
+    int32_t hv = field_sum(bits, q.e, linked ? GDI_HALO_PF - 1 : q.deg);
+    if (linked) {
+        const int32_t k0 = (int32_t)q.e[GDI_HALO_PF - 1];
+        return hv + lds_field(bits, bits, k0, k0 + q.deg - (GDI_HALO_PF - 1));
+    }
+    for (int32_t k0 = GDI_HALO_PF; k0 < q.deg; k0 += GDI_HALO_PF) {
+        uint32_t ex[GDI_HALO_PF];
+        load_run(h.adjL, q.r0 + k0, ex);
+        hv += field_sum(bits, ex, q.deg - k0);
     }
     return hv;
 }
@@ -1017,6 +1024,8 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
         for (int32_t i = tid; i <= h.tail_n; i += nth) trp[i] = h.tail_rp[i];
         for (int32_t i = tid; i < h.tail_nnz; i += nth) tent[i] = h.tail_ent[i];
     }
+    // overflow entries of this workgroup's long rows
+    for (int32_t i = tid; i < h.ovf_len; i += nth) bits[h.ovf_off + i] = h.ovf[(size_t)b * h.ovf_len + i];
     // pipeline fill: phase 0 entries, phase 1 rows
     NodePrefetch pf;
     RowAhead ra;
@@ -1157,7 +1166,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                         __builtin_amdgcn_s_sleep(1);
                     }
                     if (good && pre_next && want1) h_pre = row_field(h, bits, pf);
-                    if (good && pre_tail && my_tc == T0) th_pre = tail_field(bits, tent, trp[tid], trp[tid + 1]);
+                    if (good && pre_tail && my_tc == T0) th_pre = lds_field(bits, tent, trp[tid], trp[tid + 1]);
                     h_ready = pre_next;
                 }
             } else if (wave == nwaves - 1) {
@@ -1200,7 +1209,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                 if (worker && my_tc == tc && !(a.mask && ((a.mask[my_tail >> 5] >> (my_tail & 31)) & 1u))) {
                     const PhaseView pv = make_view(M, Psh[tc], csz_sh[tc], a.C, a.n);
                     const int32_t v = my_tail;
-                    const int32_t hv = tc == T0 ? th_pre : tail_field(bits, tent, trp[tid], trp[tid + 1]);
+                    const int32_t hv = tc == T0 ? th_pre : lds_field(bits, tent, trp[tid], trp[tid + 1]);
                     const int32_t lb = (h.tail_off + ((v - tail_base) >> 5)) * 32 + (v & 31);
                     const int32_t sigma = lds_spin(bits, lb);
                     if (decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, tx0, tx1)) {

@@ -152,6 +152,12 @@ def test_degenerate_graphs(gdi, oracle_lib):
     for scope in (1, 2, 3):
         ref, r, _ = run_both(gdi, oracle_lib, g, T, tune=dict(scope=scope), label="star")
         assert_same(ref, r)
+    # a hub row too long for the grid sweep's LDS overflow region (50,000 entries): the
+    # sweep reads the entries past the first 16 from memory instead
+    a = np.zeros(50000, np.int64); b = np.arange(1, 50001)
+    g = gs.from_edges(50001, a, b, np.ones(50000, np.int64))
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, tune=dict(scope=2), label="big star")
+    assert_same(ref, r)
 
 
 PAPER_PF = gs.geometric_temps(0.2, 0.001, 60)
