@@ -125,6 +125,10 @@ typedef struct {
                                  capped at one per worker thread) */
     uint64_t spin_limit;      /* polls before a device-side barrier wait gives up with
                                  GDI_ETIMEOUT (0 = default, about a second) */
+    int32_t leaders;          /* GDI_SCOPE_GRID: > 0 = the 8 workgroups that collect the
+                                 phase sums of their XCD (blocks 0..7) hold no nodes, so
+                                 that no node work queues ahead of their polls; < 0 =
+                                 they hold nodes like every workgroup; 0 = automatic */
 } gdi_tuning;
 
 /* Outcome of the last anneal on a handle. */

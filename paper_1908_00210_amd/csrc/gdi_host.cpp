@@ -83,14 +83,14 @@ struct gdi_graph {
     std::vector<int32_t> cls;         // class of each new id (-1 padding)
 
     // halo layout for one grid size (k_sweep_halo)
-    int32_t halo_G = 0, halo_nwork = 0;
+    int32_t halo_G = 0, halo_nwork = 0, halo_lead = 0;
     int32_t halo_lds_words = -1;      // -1: not built; -2: does not fit LDS; -3: weights too large
     int32_t halo_T0 = 0, halo_tail_n = 0, halo_gather_off = 0, halo_tail_off = 0;
     int32_t halo_tail_nnz = 0, halo_trp_off = 0, halo_tent_off = 0;
     DevBuf<uint32_t> d_adjL;
     DevBuf<int32_t> d_tail_v, d_tail_beg, d_gat_words, d_gat_beg, d_tail_rp;
     DevBuf<uint32_t> d_tail_ent;
-    int32_t halo_ovf_off = 0, halo_ovf_len = 0;
+    int32_t halo_ovf_off = 0, halo_ovf_len = 0, halo_unit_w = 0;
     DevBuf<uint32_t> d_ovf;
     DevBuf<GdiHaloEntry> d_tab;
     DevBuf<uint64_t> d_words, d_member, d_group;
@@ -223,7 +223,7 @@ int lanes_for_degree(double avg_deg)
 const int64_t kSpinLimit = int64_t(1) << 22;
 const int32_t kWgMaxNodes = 65536;
 
-int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork);
+int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork, int32_t lead);
 
 int pick_launch(gdi_graph *g, Choice *ch)
 {
@@ -265,7 +265,10 @@ int pick_launch(gdi_graph *g, Choice *ch)
         // (measured: faster at 128 workgroups, slower at 256); tail_max > 0 forces it
         const int32_t tail_auto = G <= 128 ? nwork : 0;
         const int32_t tail_cap = t.tail_max < 0 ? 0 : (t.tail_max == 0 ? tail_auto : std::min(t.tail_max, nwork));
-        int rc = build_halo(g, (int32_t)G, lds_max - 256, tail_cap);
+        // dedicated group leaders: blocks 0..7 hold no nodes (automatic: never)
+        const int32_t lead = t.leaders > 0 ? 8 : 0;
+        if (lead && G < 16) return fail(GDI_EINVAL, "dedicated leaders need a grid of at least 16 workgroups");
+        int rc = build_halo(g, (int32_t)G, lds_max - 256, tail_cap, lead);
         if (rc) return rc;
         if (g->halo_lds_words >= 0) {
             int cap = 0;
@@ -377,36 +380,51 @@ int upload(gdi_graph *g, const int32_t *rp, const int32_t *col, const int32_t *w
 }
 
 // Workgroup b handles chunk q(b) of every class; consecutive block ids are spread
-// over the 8 XCDs, so XCD x gets the contiguous chunk range [x*G/8, (x+1)*G/8).
-inline int32_t chunk_of_block(int32_t b, int32_t G) { return (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b; }
+// over the 8 XCDs, so XCD x gets a contiguous chunk range. With `lead` dedicated
+// group leaders (8, blocks 0..7, one per XCD) those hold no chunk (-1) and the other
+// G - lead blocks share the chunks.
+inline int32_t chunk_of_block(int32_t b, int32_t G, int32_t lead)
+{
+    if (b < lead) return -1;
+    const int32_t Gw = G - lead, bw = b - lead;  // bw % 8 == b % 8
+    return (Gw % 8 == 0) ? (bw % 8) * (Gw / 8) + bw / 8 : bw;
+}
 
-// Packed halo CSR entry: LDS bit index << 11 | the weight's low 11 bits.
-inline uint32_t pack_entry(int32_t lb, int32_t w) { return ((uint32_t)lb << 11) | ((uint32_t)w & 0x7FFu); }
+// Packed halo CSR entry from an LDS bit index lb: (lb / 32) << 16 | the weight's low 11
+// bits << 5 | lb % 32.
+inline uint32_t pack_entry(int32_t lb, int32_t w)
+{
+    return ((uint32_t)(lb >> 5) << 16) | (((uint32_t)w & 0x7FFu) << 5) | ((uint32_t)lb & 31u);
+}
 
 // Halo layout with the tail starting at class T0 (T0 == C: none).
-int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
+int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0, int32_t lead)
 {
     const int32_t C = g->C;
-    for (const int2 &e : g->h_adj)
+    g->halo_unit_w = 1;
+    for (const int2 &e : g->h_adj) {
         if (e.y < -GDI_HALO_WMAX - 1 || e.y > GDI_HALO_WMAX) {
             g->halo_lds_words = -3;  // weights beyond the packed entries' range
             return GDI_OK;
         }
-    std::vector<int32_t> chunk((size_t)C), blk_of_q((size_t)G);
-    for (int32_t b = 0; b < G; ++b) blk_of_q[(size_t)chunk_of_block(b, G)] = b;
+        if (e.y != 1) g->halo_unit_w = 0;
+    }
+    const int32_t Gw = G - lead;  // blocks holding nodes
+    std::vector<int32_t> chunk((size_t)C), blk_of_q((size_t)Gw);
+    for (int32_t b = lead; b < G; ++b) blk_of_q[(size_t)chunk_of_block(b, G, lead)] = b;
     for (int32_t c = 0; c < C; ++c) {
-        const int64_t per = ((int64_t)g->csz[(size_t)c] + G - 1) / G;
+        const int64_t per = ((int64_t)g->csz[(size_t)c] + Gw - 1) / Gw;
         chunk[(size_t)c] = (int32_t)std::max<int64_t>(GDI_CLASS_ALIGN, (per + GDI_CLASS_ALIGN - 1) / GDI_CLASS_ALIGN * GDI_CLASS_ALIGN);
     }
     const size_t GC = (size_t)G * (size_t)C;
     std::vector<GdiHaloEntry> tab(GC);
     std::vector<int32_t> wlo(GC, INT32_MAX), whi(GC, -1);
     for (int32_t b = 0; b < G; ++b) {
-        const int32_t q = chunk_of_block(b, G);
+        const int32_t q = chunk_of_block(b, G, lead);
         for (int32_t c = 0; c < C; ++c) {
             GdiHaloEntry &e = tab[(size_t)b * C + c];
             std::memset(&e, 0, sizeof(e));
-            if (c >= T0) continue;  // tail classes: no own chunks, no windows
+            if (c >= T0 || q < 0) continue;  // tail classes and dedicated leaders: no own chunks
             const int64_t lo = (int64_t)g->cbeg[(size_t)c] + (int64_t)q * chunk[(size_t)c];
             const int64_t hi = std::min<int64_t>((int64_t)g->cbeg[(size_t)c] + g->csz[(size_t)c], lo + chunk[(size_t)c]);
             if (lo < hi) {
@@ -479,7 +497,8 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
     const int32_t trp_off = tail_off + (g->n_pad - tail_base) / 32;
     const int32_t tent_off = (trp_off + (T0 < C ? tail_n + 1 : 0) + 1) & ~1;  // 8-byte aligned
     lds_words = tent_off + 2 * tail_nnz;
-    if (gdi_halo_lds_bytes(lds_words, C, 0) > lds_budget) {
+    // (packed entries hold LDS word indices in 16 bits)
+    if (gdi_halo_lds_bytes(lds_words, C, 0) > lds_budget || lds_words > 65536) {
         g->halo_lds_words = -2;
         return GDI_OK;
     }
@@ -604,9 +623,9 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0)
 // Builds the halo layout for grid size G: own chunks, windows of the packed spin
 // array per (workgroup, class), LDS offsets and the CSR with LDS bit indices.
 // Classes T0..C-1 form the redundant tail when they hold at most nwork nodes.
-int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork)
+int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork, int32_t lead)
 {
-    if (g->halo_G == G && g->halo_nwork == nwork && g->halo_lds_words != -1) return GDI_OK;
+    if (g->halo_G == G && g->halo_nwork == nwork && g->halo_lead == lead && g->halo_lds_words != -1) return GDI_OK;
     const int32_t C = g->C;
     int32_t T0 = C;
     int64_t tail_n = 0;
@@ -614,13 +633,14 @@ int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork)
     // republished only after a grid barrier that follows every workgroup's poll of it
     while (T0 > 2 && tail_n + g->csz[(size_t)T0 - 1] <= nwork) tail_n += g->csz[(size_t)--T0];
     for (;;) {
-        int rc = build_halo_for(g, G, lds_budget, T0);
+        int rc = build_halo_for(g, G, lds_budget, T0, lead);
         if (rc) return rc;
         if (g->halo_lds_words != -2 || T0 == C) break;
         ++T0;  // the tail's regions do not fit: a shorter tail
     }
     g->halo_G = G;
     g->halo_nwork = nwork;
+    g->halo_lead = lead;
     return GDI_OK;
 }
 
@@ -888,6 +908,7 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
         GdiHaloArgs ha{};
         ha.base = a;
         ha.adjL = g->d_adjL.p;
+        ha.unit_w = g->halo_unit_w;
         ha.tab = g->d_tab.p;
         ha.words = g->d_words.p;
         ha.member = g->d_member.p;

@@ -81,10 +81,11 @@ struct GdiHaloEntry {          // one per (workgroup, class)
 
 struct GdiHaloArgs {
     GdiSweepArgs base;
-    // CSR with each entry packed into 32 bits: (LDS bit index in the owner's image << 11)
-    // | (weight & 0x7FF), weights in [-1024, 1023]; followed by GDI_HALO_PF zero entries
-    // (bit 0, weight 0), so that GDI_HALO_PF entries can be read from any row start
+    // CSR with each entry packed into 32 bits: (LDS word in the owner's image << 16) |
+    // ((weight & 0x7FF) << 5) | bit in that word, weights in [-1024, 1023]; followed by
+    // GDI_HALO_PF zero entries, so that GDI_HALO_PF entries can be read from any row start
     const uint32_t *adjL;
+    int32_t unit_w;            // 1: every weight is 1
     const GdiHaloEntry *tab;   // grid x C entries
     uint64_t *words;           // packed spins: (epoch << 32) | 32 spin bits (bit = 1 for +1)
     uint64_t *member;          // 8 x 64 words: workgroup b posts (epoch << 32) | uint32(dM) at (b % 8) * 64 + b / 8

@@ -726,28 +726,43 @@ struct RowAhead {
 struct NodePrefetch {
     int32_t r0, deg;
     uint32_t x0, x1;
-    uint32_t e[GDI_HALO_PF];  // packed entries (see ent_lb / ent_w)
+    uint32_t e[GDI_HALO_PF];  // packed entries (see ent_word / ent_bit / ent_w)
 };
 
-// Packed CSR entry of the halo sweep: LDS bit index in the upper 21 bits, the weight
-// as an 11-bit two's-complement number in the lower bits.
-__device__ __forceinline__ int32_t ent_lb(uint32_t e) { return (int32_t)(e >> 11); }
-__device__ __forceinline__ int32_t ent_w(uint32_t e) { return (int32_t)(e << 21) >> 21; }
+// Packed CSR entry of the halo sweep: the LDS word holding the neighbour's spin bit in
+// bits 16..31, the weight as an 11-bit two's-complement number in bits 5..15, and the
+// bit's position in that word in bits 0..4 (so a bit-field extract can take the entry
+// itself as its offset operand).
+__device__ __forceinline__ int32_t ent_word(uint32_t e) { return (int32_t)(e >> 16); }
+__device__ __forceinline__ uint32_t ent_bit(uint32_t word, uint32_t e) { return (word >> (e & 31u)) & 1u; }
+__device__ __forceinline__ int32_t ent_w(uint32_t e) { return (int32_t)(e << 16) >> 21; }
 
-// Local field over the first `cnt` of GDI_HALO_PF loaded entries (the rest belong to
-// later rows and count as the zero entry: bit 0, weight 0). Every LDS word is read
-// before any is used, so the reads overlap instead of each waiting for the previous one.
-__device__ __forceinline__ int32_t field_sum(const uint32_t *bits, const uint32_t (&e)[GDI_HALO_PF], int32_t cnt)
+// Local field over the first `cnt` of GDI_HALO_PF loaded entries; the rest belong to
+// later rows (or are the zero padding) and count for nothing. Every entry names a word
+// inside every workgroup's LDS image, so all GDI_HALO_PF words are read, each before any
+// is used (the reads overlap). With h = 2 * sum(w over +1 neighbours) - sum(w): for unit
+// weights the first sum is a population count over a mask of neighbour bits.
+__device__ __forceinline__ int32_t field_sum(const uint32_t *bits, const uint32_t (&e)[GDI_HALO_PF], int32_t cnt,
+                                             bool unit)
 {
-    uint32_t ek[GDI_HALO_PF], wv[GDI_HALO_PF];
+    const int32_t c = cnt < GDI_HALO_PF ? cnt : GDI_HALO_PF;
+    uint32_t wv[GDI_HALO_PF];
 #pragma unroll
-    for (int k = 0; k < GDI_HALO_PF; ++k) ek[k] = k < cnt ? e[k] : 0u;
+    for (int k = 0; k < GDI_HALO_PF; ++k) wv[k] = bits[ent_word(e[k])];
+    if (unit) {
+        uint32_t m = 0;
 #pragma unroll
-    for (int k = 0; k < GDI_HALO_PF; ++k) wv[k] = bits[ent_lb(ek[k]) >> 5];
-    int32_t h = 0;
+        for (int k = 0; k < GDI_HALO_PF; ++k) m |= ent_bit(wv[k], e[k]) << k;
+        return 2 * __popc(m & ((1u << c) - 1u)) - c;
+    }
+    int32_t s = 0, W = 0;
 #pragma unroll
-    for (int k = 0; k < GDI_HALO_PF; ++k) h += ent_w(ek[k]) * ((int32_t)((wv[k] >> (ent_lb(ek[k]) & 31)) & 1u) * 2 - 1);
-    return h;
+    for (int k = 0; k < GDI_HALO_PF; ++k) {
+        const int32_t w = k < c ? ent_w(e[k]) : 0;
+        s += (int32_t)ent_bit(wv[k], e[k]) * w;
+        W += w;
+    }
+    return 2 * s - W;
 }
 
 // GDI_HALO_PF consecutive packed entries from index k0, as 16-byte loads. Rows start at
@@ -780,9 +795,9 @@ __device__ __forceinline__ int32_t lds_field(const uint32_t *bits, const uint32_
 #pragma unroll
         for (int j = 0; j < 8; ++j) ee[j] = k + j < k1 ? src[k + j] : 0u;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) wv[j] = bits[ent_lb(ee[j]) >> 5];
+        for (int j = 0; j < 8; ++j) wv[j] = bits[ent_word(ee[j])];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) hv += ent_w(ee[j]) * ((int32_t)((wv[j] >> (ent_lb(ee[j]) & 31)) & 1u) * 2 - 1);
+        for (int j = 0; j < 8; ++j) hv += ent_w(ee[j]) * ((int32_t)ent_bit(wv[j], ee[j]) * 2 - 1);
     }
     return hv;
 }
@@ -791,10 +806,11 @@ __device__ __forceinline__ int32_t lds_field(const uint32_t *bits, const uint32_
 // continues in the LDS overflow region at the word its entry GDI_HALO_PF - 1 names;
 // without that region, the entries past GDI_HALO_PF are loaded GDI_HALO_PF at a time,
 // every load of a batch issued before any is used (one memory round trip per batch).
+template <bool UNIT>
 __device__ __forceinline__ int32_t row_field(const GdiHaloArgs &h, const uint32_t *bits, const NodePrefetch &q)
 {
     const bool linked = h.ovf_len > 0 && q.deg > GDI_HALO_PF;
-    int32_t hv = field_sum(bits, q.e, linked ? GDI_HALO_PF - 1 : q.deg);
+    int32_t hv = field_sum(bits, q.e, linked ? GDI_HALO_PF - 1 : q.deg, UNIT);
     if (linked) {
         const int32_t k0 = (int32_t)q.e[GDI_HALO_PF - 1];
         return hv + lds_field(bits, bits, k0, k0 + q.deg - (GDI_HALO_PF - 1));
@@ -802,7 +818,7 @@ __device__ __forceinline__ int32_t row_field(const GdiHaloArgs &h, const uint32_
     for (int32_t k0 = GDI_HALO_PF; k0 < q.deg; k0 += GDI_HALO_PF) {
         uint32_t ex[GDI_HALO_PF];
         load_run(h.adjL, q.r0 + k0, ex);
-        hv += field_sum(bits, ex, q.deg - k0);
+        hv += field_sum(bits, ex, q.deg - k0, UNIT);
     }
     return hv;
 }
@@ -940,6 +956,8 @@ __device__ __forceinline__ int32_t step_node(const GdiHaloArgs &h, const GdiHalo
     return v < tab[s].node_hi ? v : -1;
 }
 
+// UNIT: every weight is 1 (the local fields reduce to population counts)
+template <bool UNIT>
 __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
 {
     const GdiSweepArgs &a = h.base;
@@ -1083,7 +1101,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                         } else {
                             q = pf;
                         }
-                        const int32_t hv = base == e.node_lo && h_ready ? h_pre : row_field(h, bits, q);
+                        const int32_t hv = base == e.node_lo && h_ready ? h_pre : row_field<UNIT>(h, bits, q);
                         const int32_t lb = (e.lds_off + (v >> 5) - e.win_lo) * 32 + (v & 31);
                         const int32_t sigma = lds_spin(bits, lb);
                         flip = decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, q.x0, q.x1);
@@ -1165,7 +1183,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                         }
                         __builtin_amdgcn_s_sleep(1);
                     }
-                    if (good && pre_next && want1) h_pre = row_field(h, bits, pf);
+                    if (good && pre_next && want1) h_pre = row_field<UNIT>(h, bits, pf);
                     if (good && pre_tail && my_tc == T0) th_pre = lds_field(bits, tent, trp[tid], trp[tid + 1]);
                     h_ready = pre_next;
                 }
@@ -1681,20 +1699,25 @@ int gdi_halo_lds_bytes(int32_t lds_words, int32_t C, int32_t thr_words)
 
 int gdi_halo_capacity(int block, int lds_bytes, int *max_grid)
 {
-    const void *f = (const void *)k_sweep_halo;
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
-    int dev = 0, cus = 0, per_cu = 0;
-    if (e == hipSuccess) e = hipGetDevice(&dev);
+    // the smaller capacity of the two instantiations (unit and general weights)
+    const void *fs[2] = {(const void *)k_sweep_halo<false>, (const void *)k_sweep_halo<true>};
+    int dev = 0, cus = 0, best = INT32_MAX;
+    hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, block, lds_bytes);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) {
+        int per_cu = 0;
+        e = hipFuncSetAttribute(fs[i], hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fs[i], block, lds_bytes);
+        best = std::min(best, per_cu);
+    }
     if (e != hipSuccess) return status(e);
-    *max_grid = cus * per_cu;
+    *max_grid = cus * best;
     return 0;
 }
 
 int gdi_launch_sweep_halo(const GdiHaloArgs &h, int grid, int block, void *stream)
 {
-    const void *f = (const void *)k_sweep_halo;
+    const void *f = h.unit_w ? (const void *)k_sweep_halo<true> : (const void *)k_sweep_halo<false>;
     const int lds = gdi_halo_lds_bytes(h.lds_words, h.base.C, h.thr_in_lds ? 2 * (h.base.K + 1) : 0);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return status(e);
