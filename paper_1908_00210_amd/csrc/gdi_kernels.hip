@@ -834,24 +834,36 @@ __device__ __forceinline__ void load_entries(const GdiHaloArgs &h, const RowAhea
                                              NodePrefetch &pf)
 {
     const GdiSweepArgs &a = h.base;
-    // draw the Philox words first: they only need the id loaded a phase ago, whereas
-    // waiting for it after issuing the CSR loads would wait for those loads as well
-    // (vector memory counters complete in order)
-    const Words4 w = philox10((uint32_t)ra.id, t, a.replica, 0u, a.key0, a.key1);
-    pf.x0 = w.w0;
-    pf.x1 = w.w1;
+    // The CSR loads go out first and the Philox words are drawn while they are in
+    // flight. The id (loaded a phase ago) is pinned in a register before the loads are
+    // issued, so the Philox rounds never wait on them (vector memory counters complete
+    // in order, and a wait for a value loaded earlier would count the new loads too).
+    uint32_t id = (uint32_t)ra.id;
+    asm volatile("" : "+v"(id));
     pf.r0 = ra.r0;
     pf.deg = ra.r1 - ra.r0;
     // every load is issued unconditionally, whatever the degree (field_sum drops the
     // entries past the row): a register that is zeroed and then conditionally loaded
     // makes the compiler wait for all earlier loads before zeroing it
     load_run(h.adjL, ra.r0, pf.e);
+    const Words4 w = philox10(id, t, a.replica, 0u, a.key0, a.key1);
+    pf.x0 = w.w0;
+    pf.x1 = w.w1;
+}
+
+// Threshold i of the current row, from LDS when staged there, else from global
+// memory. The LDS read goes through an LDS-qualified pointer: a choice between two
+// generic pointers would become one flat load, whose wait also waits for every
+// outstanding global load of the wave.
+typedef __attribute__((address_space(3))) const uint32_t gdi_lds_cu32;
+__device__ __forceinline__ uint32_t thr_at(const uint32_t *thr_l, const uint32_t *thr_g, bool in_lds, int32_t i)
+{
+    if (in_lds) return ((gdi_lds_cu32 *)thr_l)[i];
+    return thr_g[i];
 }
 
 // Metropolis decision with the node's Philox words already drawn. The threshold
-// row is read from LDS when staged there (thr_l), else from global memory (thr_g):
-// two explicit address spaces, so the lookup never becomes a generic access whose
-// wait would also wait for every outstanding global load.
+// row is read from LDS when staged there (thr_l), else from global memory (thr_g).
 __device__ __forceinline__ bool decide_words(const GdiSweepArgs &a, int32_t sigma, int32_t h,
                                              const PhaseView &pv, const uint32_t *thr_l, const uint32_t *thr_g,
                                              bool in_lds, uint32_t x0, uint32_t x1)
@@ -865,10 +877,10 @@ __device__ __forceinline__ bool decide_words(const GdiSweepArgs &a, int32_t sigm
         m_seen = gated ? pv.M0 : 0;
     }
     const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
-    if (a.rule) return (dE < 0) != (x0 < (in_lds ? thr_l[0] : thr_g[0]));
+    if (a.rule) return (dE < 0) != (x0 < thr_at(thr_l, thr_g, in_lds, 0));
     if (dE <= 0) return true;
     if (dE > a.K) return false;
-    return x0 < (in_lds ? thr_l[dE] : thr_g[dE]);
+    return x0 < thr_at(thr_l, thr_g, in_lds, dE);
 }
 
 // Bounded poll of one epoch-tagged word; returns false on timeout or abort.
