@@ -260,10 +260,12 @@ int pick_launch(gdi_graph *g, Choice *ch)
         if (block < 256) return fail(GDI_EINVAL, "the grid sweep needs at least 256 threads per workgroup");
         if (G < 8 || G % 8 || G > GDI_HALO_MAX_GRID)
             return fail(GDI_EINVAL, "the grid sweep needs a grid that is a multiple of 8 in [8, 512]");
-        const int32_t nwork = (int32_t)block - 128;  // worker threads: all but the two barrier waves
-        // the redundant tail pays for its gather polls only when few workgroups poll
-        // (measured: faster at 128 workgroups, slower at 256); tail_max > 0 forces it
-        const int32_t tail_auto = G <= 128 ? nwork : 0;
+        const int32_t nwork = (int32_t)block - 64;  // worker threads: all but the barrier wave
+        // the redundant tail is off unless asked for (tail_max > 0): since the grid
+        // phases sum their fields while the phase sum travels, its gather polls and the
+        // lost overlap before the first class cost about what its saved barriers gain
+        // (measured on 2e5- and 1e6-node RGGs at 128 and 256 workgroups)
+        const int32_t tail_auto = 0;
         const int32_t tail_cap = t.tail_max < 0 ? 0 : (t.tail_max == 0 ? tail_auto : std::min(t.tail_max, nwork));
         // dedicated group leaders: blocks 0..7 hold no nodes (automatic: never)
         const int32_t lead = t.leaders > 0 ? 8 : 0;

@@ -996,11 +996,11 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     const int32_t K1 = a.K + 1;
     const bool thr_lds = h.thr_in_lds != 0;
     int32_t *abort_v = &abort_sh;
-    // roles: the last wave reads the group words, the wave before it collects the
-    // member words (leader workgroups only); both start polling as soon as a phase's
-    // nodes are done. All other waves ("workers") update nodes, prefetch and poll
-    // their window words.
-    const int nwork = (nwaves - 2) * 64;
+    // roles: the last wave is the barrier wave: as soon as a phase's nodes are done it
+    // posts the workgroup's dM, collects its group's member words when this workgroup
+    // leads the group, then reads the group words. All other waves ("workers") update
+    // nodes, prefetch and poll their window words.
+    const int nwork = (nwaves - 1) * 64;
     const bool worker = tid < nwork;
     const int32_t T0 = h.T0;
     const bool has_tail = T0 < a.C;
@@ -1199,25 +1199,29 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                     if (good && pre_tail && my_tc == T0) th_pre = lds_field(bits, tent, trp[tid], trp[tid + 1]);
                     h_ready = pre_next;
                 }
-            } else if (wave == nwaves - 1) {
-                // this wave has no other memory traffic, so its store leaves at once
+            } else {
+                // the barrier wave has no other memory traffic, so its store leaves at once
+                const int32_t mine = wg_acc;
                 if (lane == 0) {
-                    st_agent(h.member + x * 64u + b / ngroups, ((uint64_t)epoch << 32) | (uint32_t)wg_acc);
+                    st_agent(h.member + x * 64u + b / ngroups, ((uint64_t)epoch << 32) | (uint32_t)mine);
                     wg_acc = 0;
                 }
+                if (leader) {
+                    // the leader's own member word is its group's first (b / ngroups == 0)
+                    int32_t part = lane == 0 ? mine : 0;
+                    if (lane > 0 && (uint32_t)lane < gsz)
+                        good = poll_word(h.member + x * 64u + (uint32_t)lane, epoch, a.spin_limit, abort_v, &part);
+                    if (!good) set_abort(abort_v);
+                    part = wave_sum_i32(part);
+                    if (lane == 0) st_agent(gw + (size_t)x * GDI_HALO_GROUP_PAD, ((uint64_t)epoch << 32) | (uint32_t)part);
+                    GDI_TSTAMP(4, lane == 0);
+                }
                 int32_t part = 0;
-                if ((uint32_t)lane < ngroups)
+                if (good && (uint32_t)lane < ngroups)
                     good = poll_word(gw + (size_t)lane * GDI_HALO_GROUP_PAD, epoch, a.spin_limit, abort_v, &part);
                 part = wave_sum_i32(part);
                 if (lane == 0) total_sh = part;
                 GDI_TSTAMP(5, lane == 0);
-            } else if (leader) {
-                int32_t part = 0;
-                if ((uint32_t)lane < gsz)
-                    good = poll_word(h.member + x * 64u + (uint32_t)lane, epoch, a.spin_limit, abort_v, &part);
-                part = wave_sum_i32(part);
-                if (lane == 0) st_agent(gw + (size_t)x * GDI_HALO_GROUP_PAD, ((uint64_t)epoch << 32) | (uint32_t)part);
-                GDI_TSTAMP(4, lane == 0);
             }
             if (!good) set_abort(abort_v);
             __syncthreads();

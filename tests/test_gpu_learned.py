@@ -86,6 +86,20 @@ def test_heuristic_proposal_bit_exact(gdi, L, scope, k_full, hk, amax):
     assert r["result"]["node_visits"] == g.n * T.size - skips
 
 
+def test_heuristic_proposal_with_redundant_tail(gdi, L):
+    """Skipped nodes inside the grid sweep's redundant tail (every workgroup runs the
+    last classes itself)."""
+    g = gs.rgg_graph(5000, 10.0, 51, "pm1")
+    T = gs.geometric_temps(3.0, 0.05, 83)
+    print("[case] learned heuristic with redundant tail", flush=True)
+    ref = L.learned_anneal(g, T, 9, k_full=5, proposal="heuristic", heuristic_k=2)
+    with gdi.Annealer(g) as a:
+        a.tune(scope=2, tail_max=960)
+        r = a.anneal_learned(T, 9, 5, skip_mode=gdi.SKIP_HEURISTIC, heuristic_k=2, mask_trace=True, active_max=-1)
+    assert np.array_equal(r["masks"], ref["masks"])
+    assert np.array_equal(r["spins"], ref["spins"]) and (r["M"], r["cut"]) == (ref["M"], ref["cut"])
+
+
 @pytest.mark.parametrize("scope,learn_from,amax", [(1, 30, 0), (2, 41, 0), (2, 41, -1), (3, 83, 0)])
 def test_learn_from_bit_exact(gdi, L, scope, learn_from, amax):
     """Plain sweeps up to learn_from in one launch, then the proposal's blocks."""

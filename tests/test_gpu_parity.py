@@ -163,6 +163,18 @@ def test_degenerate_graphs(gdi, oracle_lib):
 PAPER_PF = gs.geometric_temps(0.2, 0.001, 60)
 
 
+@pytest.mark.parametrize("name", list(SMALL))
+@pytest.mark.parametrize("rule", [0, 1])
+def test_redundant_tail(gdi, oracle_lib, name, rule):
+    """The grid sweep's redundant tail (the last classes, run by every workgroup with
+    workgroup barriers only) follows the oracle's trajectory under both rules."""
+    g = SMALL[name]()
+    T = gs.geometric_temps(2.5, 0.05, 40) if rule == 0 else PAPER_PF[:40]
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, seed=13, tune=dict(scope=2, tail_max=960), label=f"tail {name}",
+                         rule=rule)
+    assert_same(ref, r)
+
+
 @pytest.mark.parametrize("scope", [1, 2, 3])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_paper_rule(gdi, oracle_lib, scope, mode):
