@@ -329,8 +329,8 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": {gdi.SCOPE_GRID: "k_sweep_halo", gdi.SCOPE_GRID_FENCED: "k_sweep_grid"}.get(res.scope, "k_sweep_wg"),
-            "entry_layout": ("packed 32-bit CSR entries (21-bit LDS index, 11-bit weight); achieved counts the "
-                             "algorithmic 8 bytes per entry, traffic the bytes the counters saw")
+            "entry_layout": ("packed 32-bit CSR entries (16-bit LDS word, 11-bit weight, 5-bit bit position); "
+                             "achieved counts the algorithmic 8 bytes per entry, traffic the bytes the counters saw")
             if res.scope == gdi.SCOPE_GRID else "int32 column + int32 weight per entry",
             "kernel_ms": kern_s * 1e3, "bytes_per_launch": bytes_launch,
         },
