@@ -261,11 +261,11 @@ int pick_launch(gdi_graph *g, Choice *ch)
         if (G < 8 || G % 8 || G > GDI_HALO_MAX_GRID)
             return fail(GDI_EINVAL, "the grid sweep needs a grid that is a multiple of 8 in [8, 512]");
         const int32_t nwork = (int32_t)block - 64;  // worker threads: all but the barrier wave
-        // the redundant tail is off unless asked for (tail_max > 0): since the grid
-        // phases sum their fields while the phase sum travels, its gather polls and the
-        // lost overlap before the first class cost about what its saved barriers gain
-        // (measured on 2e5- and 1e6-node RGGs at 128 and 256 workgroups)
-        const int32_t tail_auto = 0;
+        // the redundant tail (its gather words read a phase late) saves its classes'
+        // grid barriers but every workgroup reads every gather word: on by default up to
+        // 128 workgroups (measured: 5-9 % faster on a 2e5-node RGG at 128 workgroups,
+        // 3 % slower on a 1e6-node RGG at 256); tail_max > 0 forces it
+        const int32_t tail_auto = G <= 128 ? nwork : 0;
         const int32_t tail_cap = t.tail_max < 0 ? 0 : (t.tail_max == 0 ? tail_auto : std::min(t.tail_max, nwork));
         // dedicated group leaders: blocks 0..7 hold no nodes (automatic: never)
         const int32_t lead = t.leaders > 0 ? 8 : 0;
@@ -631,9 +631,11 @@ int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork, int32_t l
     const int32_t C = g->C;
     int32_t T0 = C;
     int64_t tail_n = 0;
-    // at least two classes stay outside the tail: a gathered word of class c is then
-    // republished only after a grid barrier that follows every workgroup's poll of it
-    while (T0 > 2 && tail_n + g->csz[(size_t)T0 - 1] <= nwork) tail_n += g->csz[(size_t)--T0];
+    // at least three classes stay outside the tail: the gathered words of class c are
+    // read in the phase of class c + 1 (those of the last grid class before the tail),
+    // and are then republished only after a grid barrier that follows every
+    // workgroup's read of them
+    while (T0 > 3 && tail_n + g->csz[(size_t)T0 - 1] <= nwork) tail_n += g->csz[(size_t)--T0];
     for (;;) {
         int rc = build_halo_for(g, G, lds_budget, T0, lead);
         if (rc) return rc;

@@ -918,12 +918,15 @@ __device__ __forceinline__ bool poll_gather(const GdiHaloArgs &h, int32_t c, uin
     return true;
 }
 
-// The polls after the phase of class c: the window of class c and, with a tail, the
-// gather words of class c. A thread's first window word and first gather word
-// (packed-word id gidx, loaded earlier, or -1) are loaded together, so their
+// The polls after the phase of class c: the window of class c (words carrying `epoch`)
+// and, with a tail, the gather words of class cg = c - 1 (carrying `epoch_g`, published
+// a phase earlier, so they are there by now and no workgroup waits here for the
+// slowest owner anywhere in the grid). A thread's first window word and first gather
+// word (packed-word id gidx, loaded earlier, or -1) are loaded together, so their
 // latencies overlap; further words, if any, use the loops above.
-__device__ __forceinline__ bool poll_phase_words(const GdiHaloArgs &h, const GdiHaloEntry &e, int32_t c, int32_t gidx,
-                                                 uint32_t *bits, uint32_t epoch, int tid, int nwork, int32_t *abort_sh)
+__device__ __forceinline__ bool poll_phase_words(const GdiHaloArgs &h, const GdiHaloEntry &e, int32_t cg, int32_t gidx,
+                                                 uint32_t *bits, uint32_t epoch, uint32_t epoch_g, int tid, int nwork,
+                                                 int32_t *abort_sh)
 {
     const bool hw = tid < e.win_len, hg = gidx >= 0;
     bool ok0 = !hw, ok1 = !hg;
@@ -934,8 +937,8 @@ __device__ __forceinline__ bool poll_phase_words(const GdiHaloArgs &h, const Gdi
             bits[e.lds_off + tid] = (uint32_t)w0;
             ok0 = true;
         }
-        if (!ok1 && (uint32_t)(w1 >> 32) >= epoch) {
-            bits[h.gather_off + h.gat_beg[c] + tid] = (uint32_t)w1;
+        if (!ok1 && (uint32_t)(w1 >> 32) >= epoch_g) {
+            bits[h.gather_off + h.gat_beg[cg] + tid] = (uint32_t)w1;
             ok1 = true;
         }
         if (ok0 && ok1) break;
@@ -943,12 +946,12 @@ __device__ __forceinline__ bool poll_phase_words(const GdiHaloArgs &h, const Gdi
         __builtin_amdgcn_s_sleep(1);
     }
     if (e.win_len > nwork && !poll_window(h, e, bits, epoch, tid + nwork, nwork, abort_sh)) return false;
-    if (hg && h.gat_beg[c + 1] - h.gat_beg[c] > nwork) {
-        for (int32_t i = h.gat_beg[c] + tid + nwork; i < h.gat_beg[c + 1]; i += nwork) {
+    if (hg && h.gat_beg[cg + 1] - h.gat_beg[cg] > nwork) {
+        for (int32_t i = h.gat_beg[cg] + tid + nwork; i < h.gat_beg[cg + 1]; i += nwork) {
             const uint64_t *src = h.words + h.gat_words[i];
             for (int64_t tries = 0;; ++tries) {
                 const uint64_t w = ld_agent(src);
-                if ((uint32_t)(w >> 32) >= epoch) {
+                if ((uint32_t)(w >> 32) >= epoch_g) {
                     bits[h.gather_off + i] = (uint32_t)w;
                     break;
                 }
@@ -1078,10 +1081,9 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     int32_t h_pre = 0;
     bool h_ready = false;
     uint32_t wtarget = 0;
-    // this thread's tail node in the current sweep: Philox words and, for the first tail
-    // class, the local field, drawn while the last grid phase's dM travels
+    // this thread's tail node in the current sweep: Philox words, drawn while the last
+    // grid phase's dM travels
     uint32_t tx0 = 0, tx1 = 0;
-    int32_t th_pre = 0;
     for (uint32_t t = a.t0; t < a.S; ++t) {
         const uint32_t *thr_l = thr_sh + (t & 1u) * K1;
         const uint32_t *thr_g = a.thr + (size_t)t * K1;
@@ -1092,8 +1094,10 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
             GDI_TSTAMP(0, tid == 0);
             // this thread's first gather word of class c, loaded now so that the poll after
             // the phase does not wait for it
+            const int32_t cg = c - 1;  // gather words are read one phase late
             int32_t gidx = -1;
-            if (worker && has_tail && h.gat_beg[c] + tid < h.gat_beg[c + 1]) gidx = h.gat_words[h.gat_beg[c] + tid];
+            if (worker && has_tail && cg >= 0 && h.gat_beg[cg] + tid < h.gat_beg[cg + 1])
+                gidx = h.gat_words[h.gat_beg[cg] + tid];
             if (worker) {
                 const PhaseView pv = make_view(M, Psh[c], csz_sh[c], a.C, a.n);
                 // wave-uniform trip count so that ballots see whole waves of 64 nodes;
@@ -1167,22 +1171,21 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                 const int32_t v2 = step_node(h, tab, s2, tid);
                 if (t2 < a.S && v2 >= 0) load_row(a, v2, ra);
                 GDI_TSTAMP(6, tid == 0);
-                good = poll_phase_words(h, e, c, gidx, bits, epoch, tid, nwork, abort_v);
+                good = poll_phase_words(h, e, cg, gidx, bits, epoch, epoch - 1u, tid, nwork, abort_v);
                 GDI_TSTAMP(7, tid == 0);
                 // Once every worker wave has polled, the windows hold every spin the next
                 // phase reads, so the next phase's local fields are summed now, while this
                 // phase's dM is still travelling; only the decisions wait for the new M.
-                // Before the tail, the same holds for the first tail class. Each worker
-                // wave counts itself in whether or not its polls succeeded, so this wait ends.
+                // Each worker wave counts itself in whether or not its polls succeeded, so
+                // this wait ends. Before the tail, the tail nodes' Philox words are drawn.
                 h_ready = false;
                 const bool pre_next = t1 < a.S && !(has_tail && last_s);
-                const bool pre_tail = has_tail && last_s;
-                if (pre_next || pre_tail) {
-                    if (pre_tail && my_tail >= 0) {
-                        const Words4 xw = philox10((uint32_t)my_id, t, a.replica, 0u, a.key0, a.key1);
-                        tx0 = xw.w0;
-                        tx1 = xw.w1;
-                    }
+                if (has_tail && last_s && my_tail >= 0) {
+                    const Words4 xw = philox10((uint32_t)my_id, t, a.replica, 0u, a.key0, a.key1);
+                    tx0 = xw.w0;
+                    tx1 = xw.w1;
+                }
+                if (pre_next) {
                     if (lane == 0) __hip_atomic_fetch_add(&wdone, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                     wtarget += (uint32_t)(nwork >> 6);
                     for (int64_t tries = 0;
@@ -1194,9 +1197,8 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                         }
                         __builtin_amdgcn_s_sleep(1);
                     }
-                    if (good && pre_next && want1) h_pre = row_field<UNIT>(h, bits, pf);
-                    if (good && pre_tail && my_tc == T0) th_pre = lds_field(bits, tent, trp[tid], trp[tid + 1]);
-                    h_ready = pre_next;
+                    if (good && want1) h_pre = row_field<UNIT>(h, bits, pf);
+                    h_ready = true;
                 }
             } else {
                 // the barrier wave has no other memory traffic, so its store leaves at once
@@ -1234,6 +1236,14 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
             if (tid == 0 && a.C > 1) Psh[c] += tot / 2;
         }
         if (has_tail) {
+            // the last grid class's gather words (its phase was p - 1): published before
+            // that phase's barrier, so they are all there now
+            if (worker && !poll_gather(h, T0 - 1, bits, p + 1u, tid, nwork, abort_v)) set_abort(abort_v);
+            __syncthreads();
+            if (abort_sh) {
+                if (tid == 0) __hip_atomic_store(&a.state[3], (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return;
+            }
             // the tail, identically in every workgroup: one class after the other with
             // workgroup barriers only; dM through a rotating triple of LDS accumulators.
             // Its CSR is in LDS, so no global load is in flight across these barriers.
@@ -1242,7 +1252,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                 if (worker && my_tc == tc && !(a.mask && ((a.mask[my_tail >> 5] >> (my_tail & 31)) & 1u))) {
                     const PhaseView pv = make_view(M, Psh[tc], csz_sh[tc], a.C, a.n);
                     const int32_t v = my_tail;
-                    const int32_t hv = tc == T0 ? th_pre : lds_field(bits, tent, trp[tid], trp[tid + 1]);
+                    const int32_t hv = lds_field(bits, tent, trp[tid], trp[tid + 1]);
                     const int32_t lb = (h.tail_off + ((v - tail_base) >> 5)) * 32 + (v & 31);
                     const int32_t sigma = lds_spin(bits, lb);
                     if (decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, tx0, tx1)) {
