@@ -66,11 +66,18 @@ __device__ __forceinline__ Words4 philox10(uint32_t x0, uint32_t x1, uint32_t x2
     return {x0, x1, x2, x3};
 }
 
+// Wave-wide sum with DPP lane moves (no LDS round trips): within quads, then mirrored
+// half-rows and rows, then rows 1 and 3 add the last lane of rows 0 and 2, rows 2 and 3
+// that of row 1; lane 63 ends with the total. All 64 lanes must be active.
 __device__ __forceinline__ int32_t wave_sum_i32(int32_t v)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);  // row_half_mirror
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);  // row_mirror
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
