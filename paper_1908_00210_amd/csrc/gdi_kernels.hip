@@ -80,6 +80,21 @@ __device__ __forceinline__ int32_t wave_sum_i32(int32_t v)
     return __builtin_amdgcn_readlane(v, 63);
 }
 
+// Sum over each aligned group of L lanes, left in every lane of the group: DPP moves
+// within quads, half-rows and rows (every lane they read belongs to the same group),
+// then lane shuffles for groups of 32 and 64.
+template <int L>
+__device__ __forceinline__ int32_t group_sum(int32_t v)
+{
+    if (L >= 2) v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+    if (L >= 4) v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+    if (L >= 8) v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);  // row_half_mirror
+    if (L >= 16) v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false); // row_mirror
+    if (L >= 32) v += __shfl_xor(v, 16, 64);
+    if (L >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
 {
 #pragma unroll
@@ -173,10 +188,7 @@ __device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t 
         const int2 e = a.adj[k];
         h += e.y * (int32_t)sp[e.x];
     }
-    if (L > 1) {
-#pragma unroll
-        for (int off = L / 2; off > 0; off >>= 1) h += __shfl_xor(h, off, L);
-    }
+    if (L > 1) h = group_sum<L>(h);
     const int32_t sigma = sp[v];
     *h_out = h;
     *sigma_out = sigma;
@@ -1419,9 +1431,7 @@ __global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *a
 template <int L>
 __device__ __forceinline__ int32_t subgroup_sum(int32_t v)
 {
-#pragma unroll
-    for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, L);
-    return v;
+    return L > 1 ? group_sum<L>(v) : v;
 }
 
 template <int L>
