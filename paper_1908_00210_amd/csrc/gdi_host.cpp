@@ -245,8 +245,10 @@ int pick_launch(gdi_graph *g, Choice *ch)
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
     if (ch->scope == GDI_SCOPE_WORKGROUP) {
-        ch->spins_lds = gdi_wg_lds_bytes(g->n_pad, g->C, 1) + 64 <= lds_max;
-        if (gdi_wg_lds_bytes(g->n_pad, g->C, 0) + 64 > lds_max)
+        // beside the dynamic part: the kernel's own LDS words and two threshold rows
+        const int fixed = 64 + 2 * GDI_WG_THR_MAX * 4;
+        ch->spins_lds = gdi_wg_lds_bytes(g->n_pad, g->C, 1) + fixed <= lds_max;
+        if (gdi_wg_lds_bytes(g->n_pad, g->C, 0) + fixed > lds_max)
             return fail(GDI_ERANGE, "too many colour classes for one workgroup's LDS");
         return GDI_OK;
     }
@@ -1079,7 +1081,7 @@ int run_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
-    if (lds > lds_max) return fail(GDI_ERANGE, "an instance does not fit one workgroup's LDS");
+    if (lds + 64 + 2 * GDI_WG_THR_MAX * 4 > lds_max) return fail(GDI_ERANGE, "an instance does not fit one workgroup's LDS");
     const uint32_t block = tn.block ? tn.block : 256u;
     if (block < 64 || block > GDI_MAX_BLOCK || block % 64) return fail(GDI_EINVAL, "block must be a multiple of 64 in [64, 1024]");
     if (tn.lanes_per_node && (tn.lanes_per_node > 64 || (tn.lanes_per_node & (tn.lanes_per_node - 1))))

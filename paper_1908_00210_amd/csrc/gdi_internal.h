@@ -15,6 +15,7 @@
 
 #define GDI_CLASS_ALIGN 64
 #define GDI_MAX_BLOCK 1024
+#define GDI_WG_THR_MAX 256     // largest table width the workgroup sweep keeps in LDS (two rows)
 #define GDI_BAR_GROUPS 8       // workgroups are grouped by blockIdx % 8 for the two-level barrier
 #define GDI_BAR_PAD 16         // uint64 words between group counters (128 bytes)
 

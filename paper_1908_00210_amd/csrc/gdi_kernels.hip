@@ -123,11 +123,24 @@ __device__ __forceinline__ PhaseView make_view(int32_t M0, int32_t P_c, int32_t 
     return v;
 }
 
+// Threshold i of the current row, from LDS when staged there, else from global
+// memory. The LDS read goes through an LDS-qualified pointer: a choice between two
+// generic pointers would become one flat load, whose wait also waits for every
+// outstanding global load of the wave.
+typedef __attribute__((address_space(3))) const uint32_t gdi_lds_cu32;
+__device__ __forceinline__ uint32_t thr_at(const uint32_t *thr_l, const uint32_t *thr_g, bool in_lds, int32_t i)
+{
+    if (in_lds) return ((gdi_lds_cu32 *)thr_l)[i];
+    return thr_g[i];
+}
+
 // Metropolis decision of one node (original id o) given its local field h and spin
 // sigma (eq. 5 / eq. 6 flip cost with the gated balance term). Philox words are
-// drawn only when the gate or the threshold lookup needs them.
+// drawn only when the gate or the threshold lookup needs them. The threshold row is
+// thr_l in LDS when staged there (non-null), else thr_row in global memory.
 __device__ __forceinline__ bool decide_id(const GdiSweepArgs &a, uint32_t o, uint32_t t, int32_t sigma,
-                                          int32_t h, const PhaseView &pv, const uint32_t *thr_row)
+                                          int32_t h, const PhaseView &pv, const uint32_t *thr_row,
+                                          const uint32_t *thr_l = nullptr)
 {
     const bool need_gate = !a.snapshot && pv.D > 0 && sigma == pv.s;
     uint32_t x0 = 0, x1 = 0;
@@ -148,18 +161,12 @@ __device__ __forceinline__ bool decide_id(const GdiSweepArgs &a, uint32_t o, uin
     const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
     if (a.rule) {  // the paper's rule: the argmin value, then a random flip with probability P_f
         if (!have) x0 = philox10(o, t, a.replica, 0u, a.key0, a.key1).w0;
-        return (dE < 0) != (x0 < thr_row[0]);
+        return (dE < 0) != (x0 < thr_at(thr_l, thr_row, thr_l != nullptr, 0));
     }
     if (dE <= 0) return true;
     if (dE > a.K) return false;
     if (!have) x0 = philox10(o, t, a.replica, 0u, a.key0, a.key1).w0;
-    return x0 < thr_row[dE];
-}
-
-__device__ __forceinline__ bool decide(const GdiSweepArgs &a, int32_t v, uint32_t t, int32_t sigma,
-                                       int32_t h, const PhaseView &pv, const uint32_t *thr_row)
-{
-    return decide_id(a, (uint32_t)a.orig[v], t, sigma, h, pv, thr_row);
+    return x0 < thr_at(thr_l, thr_row, thr_l != nullptr, dE);
 }
 
 // Launch gate of the masked sweeps: the active-set kernel and the full-graph
@@ -175,14 +182,15 @@ __device__ __forceinline__ bool gate_open(const GdiSweepArgs &a)
 // One node of the current class: L lanes share its CSR row. All L lanes return
 // the same decision; lane 0 of the subgroup performs the write.
 // sp is an LDS or a global int8 pointer.
+// Row bounds r0, r1 come from the caller (loaded ahead by the workgroup sweep); the
+// original id is loaded before the row so that its latency overlaps the row's.
 template <int L>
-__device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t *sp, int32_t v,
-                                            int lane, uint32_t t, const PhaseView &pv,
-                                            const uint32_t *thr_row, int32_t *h_out,
+__device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t *sp, int32_t v, int32_t r0,
+                                            int32_t r1, int lane, uint32_t t, const PhaseView &pv,
+                                            const uint32_t *thr_row, const uint32_t *thr_l, int32_t *h_out,
                                             int32_t *sigma_out)
 {
-    const int32_t r0 = a.rp[v];
-    const int32_t r1 = a.rp[v + 1];
+    const uint32_t o = (uint32_t)a.orig[v];
     int32_t h = 0;
     for (int32_t k = r0 + lane; k < r1; k += L) {
         const int2 e = a.adj[k];
@@ -192,7 +200,7 @@ __device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t 
     const int32_t sigma = sp[v];
     *h_out = h;
     *sigma_out = sigma;
-    return decide(a, v, t, sigma, h, pv, thr_row);
+    return decide_id(a, o, t, sigma, h, pv, thr_row, thr_l);
 }
 
 // ------------------------------------------------------------------ workgroup scope
@@ -209,18 +217,38 @@ __device__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp, int32_t *Psh, i
     const int sub = tid / L, lane = tid % L, nsub = nth / L;
     int64_t dcut = 0;
     uint32_t p = 0;
+    // the current and the next threshold row in LDS when they fit (staged during the
+    // last phase of each sweep, whose barrier publishes them)
+    __shared__ uint32_t thr_s[2 * GDI_WG_THR_MAX];
+    const int32_t K1 = a.K + 1;
+    const bool thr_lds = K1 <= GDI_WG_THR_MAX;
+    if (thr_lds && a.t0 < a.S)
+        for (int i = tid; i < K1; i += nth) thr_s[(a.t0 & 1u) * GDI_WG_THR_MAX + i] = a.thr[(size_t)a.t0 * K1 + i];
+    __syncthreads();
     for (uint32_t t = a.t0; t < a.S; ++t) {
-        const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)(a.K + 1);
+        const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)K1;
+        const uint32_t *thr_l = thr_lds ? thr_s + (t & 1u) * GDI_WG_THR_MAX : nullptr;
         for (int32_t c = 0; c < a.C; ++c, ++p) {
             const int32_t beg = a.cbeg[c];
             const int32_t size = a.csz[c];
             const PhaseView pv = make_view(M, Psh[c], size, a.C, a.n);
             int32_t dM = 0;
+            // each subgroup loads the next node's row bounds while it works on this one
+            int32_t nr0 = 0, nr1 = 0;
+            if (sub < size) {
+                nr0 = a.rp[beg + sub];
+                nr1 = a.rp[beg + sub + 1];
+            }
             for (int32_t j = sub; j < size; j += nsub) {
                 const int32_t v = beg + j;
+                const int32_t r0 = nr0, r1 = nr1;
+                if (j + nsub < size) {
+                    nr0 = a.rp[v + nsub];
+                    nr1 = a.rp[v + nsub + 1];
+                }
                 if (a.mask && ((a.mask[v >> 5] >> (v & 31)) & 1u)) continue;  // skipped node
                 int32_t h, sigma;
-                const bool flip = node_decide<L>(a, sp, v, lane, t, pv, thr_row, &h, &sigma);
+                const bool flip = node_decide<L>(a, sp, v, r0, r1, lane, t, pv, thr_row, thr_l, &h, &sigma);
                 if (flip && lane == 0) {
                     sp[v] = (int8_t)(-sigma);
                     dM -= 2 * sigma;
@@ -228,6 +256,9 @@ __device__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp, int32_t *Psh, i
                     if (a.last_flip) a.last_flip[v] = (int32_t)t;
                 }
             }
+            if (c + 1 == a.C && thr_lds && t + 1u < a.S)
+                for (int i = tid; i < K1; i += nth)
+                    thr_s[((t + 1u) & 1u) * GDI_WG_THR_MAX + i] = a.thr[(size_t)(t + 1u) * K1 + i];
             dM = wave_sum_i32(dM);
             if ((tid & 63) == 0 && dM != 0) atomicAdd(&acc[p % 3], dM);
             __syncthreads();
@@ -607,7 +638,8 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_grid(GdiSweepArgs a)
                 const int32_t v = beg + j;
                 if (a.mask && ((a.mask[v >> 5] >> (v & 31)) & 1u)) continue;  // skipped node
                 int32_t h, sigma;
-                const bool flip = node_decide<L>(a, a.spin, v, lane, t, pv, thr_row, &h, &sigma);
+                const bool flip = node_decide<L>(a, a.spin, v, a.rp[v], a.rp[v + 1], lane, t, pv, thr_row, nullptr, &h,
+                                                 &sigma);
                 if (flip && lane == 0) {
                     a.spin[v] = (int8_t)(-sigma);
                     dM -= 2 * sigma;
@@ -867,17 +899,6 @@ __device__ __forceinline__ void load_entries(const GdiHaloArgs &h, const RowAhea
     const Words4 w = philox10(id, t, a.replica, 0u, a.key0, a.key1);
     pf.x0 = w.w0;
     pf.x1 = w.w1;
-}
-
-// Threshold i of the current row, from LDS when staged there, else from global
-// memory. The LDS read goes through an LDS-qualified pointer: a choice between two
-// generic pointers would become one flat load, whose wait also waits for every
-// outstanding global load of the wave.
-typedef __attribute__((address_space(3))) const uint32_t gdi_lds_cu32;
-__device__ __forceinline__ uint32_t thr_at(const uint32_t *thr_l, const uint32_t *thr_g, bool in_lds, int32_t i)
-{
-    if (in_lds) return ((gdi_lds_cu32 *)thr_l)[i];
-    return thr_g[i];
 }
 
 // Metropolis decision with the node's Philox words already drawn. The threshold
@@ -1477,7 +1498,8 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_dense(GdiSweepArgs a)
                 pv.D = (m < 0 ? -m : m) >> 1;
                 pv.O = (uint32_t)o;
                 int32_t h, sigma;
-                const bool flip = node_decide<L>(a, sp, v, lane, t, pv, thr_row, &h, &sigma);
+                const bool flip = node_decide<L>(a, sp, v, a.rp[v], a.rp[v + 1], lane, t, pv, thr_row, nullptr, &h,
+                                                 &sigma);
                 if (flip && lane == 0) {
                     sp[v] = (int8_t)(-sigma);
                     dM -= 2 * sigma;
