@@ -192,17 +192,17 @@ __device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t 
 {
     const uint32_t o = (uint32_t)a.orig[v];
     int32_t h = 0;
-    // four entries per lane and round: all loads of a round are issued before any is
+    // eight entries per lane and round: all loads of a round are issued before any is
     // used (indices past the row are clamped to its last entry and count for nothing)
-    for (int32_t k = r0 + lane; k < r1; k += 4 * L) {
-        int2 e[4];
+    for (int32_t k = r0 + lane; k < r1; k += 8 * L) {
+        int2 e[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) e[u] = a.adj[k + u * L < r1 ? k + u * L : r1 - 1];
-        int32_t s4[4];
+        for (int u = 0; u < 8; ++u) e[u] = a.adj[k + u * L < r1 ? k + u * L : r1 - 1];
+        int32_t s8[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) s4[u] = sp[e[u].x];
+        for (int u = 0; u < 8; ++u) s8[u] = sp[e[u].x];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) h += k + u * L < r1 ? e[u].y * s4[u] : 0;
+        for (int u = 0; u < 8; ++u) h += k + u * L < r1 ? e[u].y * s8[u] : 0;
     }
     if (L > 1) h = group_sum<L>(h);
     const int32_t sigma = sp[v];
