@@ -416,12 +416,22 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_active(GdiSweepArgs a, 
             if (jb == je) continue;
             const PhaseView pv = make_view(M, Psh[c], a.csz[c], a.C, a.n);
             int32_t dM = 0;
+            // each thread loads its next record while it works on this one, and a row's
+            // entries eight at a time, all loads of a round issued before any is used
+            // (indices past the row are clamped to its last entry and count for nothing)
+            GdiActiveRec rn{};
+            if (jb + tid < je) rn = rec[jb + tid];
             for (int32_t j = jb + tid; j < je; j += nth) {
-                const GdiActiveRec r = rec[j];
+                const GdiActiveRec r = rn;
+                if (j + nth < je) rn = rec[j + nth];
                 int32_t h = 0;
-                for (int32_t k = r.r0; k < r.r1; ++k) {
-                    const int2 e = a.adj[k];
-                    h += ((bits[e.x >> 5] >> (e.x & 31)) & 1u) ? e.y : -e.y;
+                for (int32_t k0 = r.r0; k0 < r.r1; k0 += 8) {
+                    int2 e[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) e[u] = a.adj[k0 + u < r.r1 ? k0 + u : r.r1 - 1];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        if (k0 + u < r.r1) h += ((bits[e[u].x >> 5] >> (e[u].x & 31)) & 1u) ? e[u].y : -e[u].y;
                 }
                 const int32_t sigma = ((bits[r.v >> 5] >> (r.v & 31)) & 1u) ? 1 : -1;
                 if (decide_id(a, (uint32_t)r.orig, t, sigma, h, pv, thr_row)) {
