@@ -1143,7 +1143,7 @@ int run_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64
         b.lanes = tn.lanes_per_node ? (int32_t)tn.lanes_per_node
                                     : lanes_for_degree(g->n ? (double)g->nnz / g->n : 0.0);
         b.replica = inst[i].replica;
-        b.pad = 0;
+        b.wide = g->n && (double)g->nnz / g->n >= 4.0 * b.lanes ? 1u : 0u;
     }
     hipStream_t st = inst[0].graph->stream;
     HIP_TRY(hipMemcpyAsync(d_inst.p, h_inst.data(), h_inst.size() * sizeof(GdiBatchInstance), hipMemcpyHostToDevice, st),

@@ -130,7 +130,8 @@ struct GdiBatchInstance {
     int8_t *out;               // n spins in original order (device) or null
     int64_t *result;           // [0] final M, [1] tracked weighted cut
     int32_t n, n_pad, C, lanes;
-    uint32_t replica, pad;
+    uint32_t replica;
+    uint32_t wide;             // 1: long rows for `lanes` (eight entries per lane and round)
 };
 
 struct GdiBatchArgs {

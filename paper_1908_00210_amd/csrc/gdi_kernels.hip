@@ -183,8 +183,10 @@ __device__ __forceinline__ bool gate_open(const GdiSweepArgs &a)
 // the same decision; lane 0 of the subgroup performs the write.
 // sp is an LDS or a global int8 pointer.
 // Row bounds r0, r1 come from the caller (loaded ahead by the workgroup sweep); the
-// original id is loaded before the row so that its latency overlaps the row's.
-template <int L>
+// original id is loaded before the row so that its latency overlaps the row's. U
+// entries per lane and round: 8 for rows long against L, else 4 (skipped loads still
+// cost their branch).
+template <int L, int U = 4>
 __device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t *sp, int32_t v, int32_t r0,
                                             int32_t r1, int lane, uint32_t t, const PhaseView &pv,
                                             const uint32_t *thr_row, const uint32_t *thr_l, int32_t *h_out,
@@ -192,17 +194,17 @@ __device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t 
 {
     const uint32_t o = (uint32_t)a.orig[v];
     int32_t h = 0;
-    // eight entries per lane and round: all loads of a round are issued before any is
-    // used (indices past the row are clamped to its last entry and count for nothing)
-    for (int32_t k = r0 + lane; k < r1; k += 8 * L) {
-        int2 e[8];
+    // up to U entries per lane and round, all loads of a round issued before any is
+    // used; an entry past the row is not loaded and counts as (node 0, weight 0)
+    for (int32_t k = r0 + lane; k < r1; k += U * L) {
+        int2 e[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) e[u] = a.adj[k + u * L < r1 ? k + u * L : r1 - 1];
-        int32_t s8[8];
+        for (int u = 0; u < U; ++u) e[u] = k + u * L < r1 ? a.adj[k + u * L] : make_int2(0, 0);
+        int32_t sv[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s8[u] = sp[e[u].x];
+        for (int u = 0; u < U; ++u) sv[u] = sp[e[u].x];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) h += k + u * L < r1 ? e[u].y * s8[u] : 0;
+        for (int u = 0; u < U; ++u) h += e[u].y * sv[u];
     }
     if (L > 1) h = group_sum<L>(h);
     const int32_t sigma = sp[v];
@@ -216,7 +218,7 @@ __device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t 
 // s_barrier, dM is summed in an LDS triple buffer (one barrier per phase).
 // sp points to the instance's spins (LDS, or global for large instances),
 // Psh to its per-class +1 counts in LDS, acc to three zeroed LDS words.
-template <int L>
+template <int L, int U = 4>
 __device__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp, int32_t *Psh, int32_t *acc, int32_t &M,
                               int64_t &dcut_total)
 {
@@ -256,7 +258,7 @@ __device__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp, int32_t *Psh, i
                 }
                 if (a.mask && ((a.mask[v >> 5] >> (v & 31)) & 1u)) continue;  // skipped node
                 int32_t h, sigma;
-                const bool flip = node_decide<L>(a, sp, v, r0, r1, lane, t, pv, thr_row, thr_l, &h, &sigma);
+                const bool flip = node_decide<L, U>(a, sp, v, r0, r1, lane, t, pv, thr_row, thr_l, &h, &sigma);
                 if (flip && lane == 0) {
                     sp[v] = (int8_t)(-sigma);
                     dM -= 2 * sigma;
@@ -548,14 +550,26 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_batch(GdiBatchArgs ba)
         const int64_t cut0 = red[1] / 2;
 
         int64_t dcut_total = 0;
-        switch (in.lanes) {
-        case 1: wg_run_sweeps<1>(a, sp, Psh, acc, M, dcut_total); break;
-        case 2: wg_run_sweeps<2>(a, sp, Psh, acc, M, dcut_total); break;
-        case 4: wg_run_sweeps<4>(a, sp, Psh, acc, M, dcut_total); break;
-        case 8: wg_run_sweeps<8>(a, sp, Psh, acc, M, dcut_total); break;
-        case 16: wg_run_sweeps<16>(a, sp, Psh, acc, M, dcut_total); break;
-        case 32: wg_run_sweeps<32>(a, sp, Psh, acc, M, dcut_total); break;
-        default: wg_run_sweeps<64>(a, sp, Psh, acc, M, dcut_total); break;
+        if (in.wide) {
+            switch (in.lanes) {
+            case 1: wg_run_sweeps<1, 8>(a, sp, Psh, acc, M, dcut_total); break;
+            case 2: wg_run_sweeps<2, 8>(a, sp, Psh, acc, M, dcut_total); break;
+            case 4: wg_run_sweeps<4, 8>(a, sp, Psh, acc, M, dcut_total); break;
+            case 8: wg_run_sweeps<8, 8>(a, sp, Psh, acc, M, dcut_total); break;
+            case 16: wg_run_sweeps<16, 8>(a, sp, Psh, acc, M, dcut_total); break;
+            case 32: wg_run_sweeps<32, 8>(a, sp, Psh, acc, M, dcut_total); break;
+            default: wg_run_sweeps<64, 8>(a, sp, Psh, acc, M, dcut_total); break;
+            }
+        } else {
+            switch (in.lanes) {
+            case 1: wg_run_sweeps<1>(a, sp, Psh, acc, M, dcut_total); break;
+            case 2: wg_run_sweeps<2>(a, sp, Psh, acc, M, dcut_total); break;
+            case 4: wg_run_sweeps<4>(a, sp, Psh, acc, M, dcut_total); break;
+            case 8: wg_run_sweeps<8>(a, sp, Psh, acc, M, dcut_total); break;
+            case 16: wg_run_sweeps<16>(a, sp, Psh, acc, M, dcut_total); break;
+            case 32: wg_run_sweeps<32>(a, sp, Psh, acc, M, dcut_total); break;
+            default: wg_run_sweeps<64>(a, sp, Psh, acc, M, dcut_total); break;
+            }
         }
         __syncthreads();
         if (in.out)
