@@ -1431,6 +1431,16 @@ __global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *a
                                                 int32_t *P)
 {
     __shared__ int64_t red[3][4];
+    // with few classes, class starts and this block's +1 counts live in LDS (one global
+    // atomic per class and block instead of one per 64-id chunk)
+    __shared__ int32_t cb_sh[256], pc_sh[256];
+    const bool local = C <= 256;
+    if (local)
+        for (int i = threadIdx.x; i < C; i += blockDim.x) {
+            cb_sh[i] = cbeg[i];
+            pc_sh[i] = 0;
+        }
+    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int64_t m = 0, cw = 0, ce = 0;
     for (int32_t base = blockIdx.x * blockDim.x; base < n_pad; base += gridDim.x * blockDim.x) {
@@ -1440,12 +1450,22 @@ __global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *a
         if (v < n_pad) {
             s = spin[v];
             m += s;
-            for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
-                const int2 e = adj[k];
-                if (spin[e.x] != s) {
-                    cw += e.y;
-                    ce += 1;
-                }
+            // eight entries per round, every load of a round issued before any is used;
+            // entries past the row are not loaded and count for nothing
+            const int32_t r0 = rp[v], r1 = rp[v + 1];
+            for (int32_t k = r0; k < r1; k += 8) {
+                int2 e[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) e[u] = k + u < r1 ? adj[k + u] : make_int2(v, 0);
+                int8_t sj[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) sj[u] = spin[e[u].x];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (k + u < r1 && sj[u] != s) {
+                        cw += e[u].y;
+                        ce += 1;
+                    }
             }
         }
         const int32_t plus = __popcll(__ballot(s > 0));
@@ -1453,9 +1473,11 @@ __global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *a
             int32_t lo = 0, hi = C - 1;  // class of the chunk: last c with cbeg[c] <= v0
             while (lo < hi) {
                 const int32_t mid = (lo + hi + 1) >> 1;
-                if (cbeg[mid] <= v0) lo = mid; else hi = mid - 1;
+                if ((local ? cb_sh[mid] : cbeg[mid]) <= v0) lo = mid; else hi = mid - 1;
             }
-            atomicAdd(&P[lo], plus);  // padding ids hold spin 0 and never count
+            // padding ids hold spin 0 and never count
+            if (local) atomicAdd(&pc_sh[lo], plus);
+            else atomicAdd(&P[lo], plus);
         }
     }
     m = wave_sum_i64(m);
@@ -1472,6 +1494,9 @@ __global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *a
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[threadIdx.x][w];
         if (t) atomicAdd((unsigned long long *)&out3[threadIdx.x], (unsigned long long)t);
     }
+    if (local)
+        for (int i = threadIdx.x; i < C; i += blockDim.x)
+            if (pc_sh[i]) atomicAdd(&P[i], pc_sh[i]);
 }
 
 // ------------------------------------------------------------------ standard solver
