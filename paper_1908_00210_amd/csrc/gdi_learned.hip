@@ -55,14 +55,25 @@ __global__ void k_features(const int32_t *rp, const int2 *adj, const int8_t *spi
     if (o < 0) return;  // padding id
     const int32_t s = spin[v];
     const int32_t M = (int32_t)state[0];
-    int32_t deg = 0, wabs = 0, other = 0, h = 0;
-    for (int32_t k = rp[v]; k < rp[v + 1]; ++k) {
-        const int2 e = adj[k];
-        const int32_t sj = spin[e.x];
-        ++deg;
-        wabs += e.y < 0 ? -e.y : e.y;
-        other += sj != s;
-        h += e.y * sj;
+    int32_t wabs = 0, other = 0, h = 0;
+    const int32_t r0 = rp[v], r1 = rp[v + 1];
+    const int32_t deg = r1 - r0;
+    // eight entries per round, every load of a round issued before any is used; entries
+    // past the row are not loaded and count for nothing
+    for (int32_t k = r0; k < r1; k += 8) {
+        int2 e[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) e[u] = k + u < r1 ? adj[k + u] : make_int2(v, 0);
+        int32_t sj[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sj[u] = spin[e[u].x];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k + u < r1) {
+                wabs += e[u].y < 0 ? -e[u].y : e[u].y;
+                other += sj[u] != s;
+                h += e[u].y * sj[u];
+            }
     }
     float f[8];
     f[0] = deg / 16.0f;
