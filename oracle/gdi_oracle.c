@@ -53,7 +53,8 @@
 #define OR_MODE_SNAPSHOT 1
 /* Acceptance rules. Metropolis: flip iff dE <= 0 or x0 < thr_t(dE). The paper's
  * rule (Sec. V, Alg. 2 and 3): the spin takes the value minimising its local energy
- * (flip iff dE < 0) and is then flipped with probability P_f(t), drawn as
+ * (flip iff dE < 0; at dE = 0 the local field is zero and the value is random,
+ * Sec. III: +1 iff x2 is odd) and is then flipped with probability P_f(t), drawn as
  * x0 < min(2^32 - 1, floor(2^32 P_f(t))); the two flips compose. */
 #define OR_RULE_METROPOLIS 0
 #define OR_RULE_PAPER 1
@@ -324,8 +325,12 @@ int oracle_anneal(int32_t n, const int32_t *row_ptr, const int32_t *col, const i
                 }
                 const int64_t dE = B * si * h + 4 * A * (1 - si * Mi);
                 int accept;
-                if (p->rule == OR_RULE_PAPER) accept = (dE < 0) != (x[0] < pf_thr);
-                else if (dE <= 0) accept = 1;
+                if (p->rule == OR_RULE_PAPER) {
+                    /* the energy-minimising value; a tie leaves it to word x2 */
+                    const int64_t tie_value = (x[2] & 1u) ? 1 : -1;
+                    const int argmin_flips = dE < 0 || (dE == 0 && tie_value != si);
+                    accept = argmin_flips != (x[0] < pf_thr);
+                } else if (dE <= 0) accept = 1;
                 else if (dE > width) accept = 0;
                 else accept = x[0] < thr[dE];
                 flip[q] = (uint8_t)accept;

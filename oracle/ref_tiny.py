@@ -63,7 +63,8 @@ def anneal(n, edges, temps, seed, A=1, B=1, replica=0, gated=True, init=None, st
     Nodes in ``skip`` make no decision (their spins stay, they still count in the
     magnetisation); ``last_flip`` (a list of n ints) receives each flip's sweep. With
     ``paper_rule`` temps are flip probabilities: a spin takes its energy-minimising
-    value (flips iff dE < 0) and then flips again when x0 < floor(2^32 P_f).
+    value (flips iff dE < 0; when dE = 0 its value is random, +1 iff Philox word x2 is
+    odd) and then flips again when x0 < floor(2^32 P_f).
     """
     skip = set(skip)
     adj = [[] for _ in range(n)]
@@ -101,7 +102,13 @@ def anneal(n, edges, temps, seed, A=1, B=1, replica=0, gated=True, init=None, st
                     seen = M0
                 dE = B * s[i] * h + 4 * A * (1 - s[i] * seen)
                 if paper_rule:
-                    if (dE < 0) != (x[0] < flip_threshold(T)):
+                    if dE < 0:
+                        argmin = -s[i]
+                    elif dE > 0:
+                        argmin = s[i]
+                    else:
+                        argmin = 1 if x[2] & 1 else -1
+                    if (argmin != s[i]) != (x[0] < flip_threshold(T)):
                         flips.append(i)
                 elif dE <= 0 or x[0] < threshold(dE, T):
                     flips.append(i)

@@ -134,6 +134,16 @@ __device__ __forceinline__ uint32_t thr_at(const uint32_t *thr_l, const uint32_t
     return thr_g[i];
 }
 
+// The paper's acceptance rule (Sec. V, Alg. 2/3): the spin takes the value of lower
+// local energy -- flip iff dE < 0; on a tie (dE = 0, a zero local field) the value is
+// random (Sec. III), +1 iff Philox word x2 is odd -- and then flips with probability
+// P_f, i.e. iff x0 < pf_thr = min(2^32 - 1, floor(2^32 P_f)). The two flips compose.
+__device__ __forceinline__ bool paper_flip(int32_t dE, int32_t sigma, uint32_t x0, uint32_t x2, uint32_t pf_thr)
+{
+    const bool argmin_flips = dE < 0 || (dE == 0 && ((x2 & 1u) ? 1 : -1) != sigma);
+    return argmin_flips != (x0 < pf_thr);
+}
+
 // Metropolis decision of one node (original id o) given its local field h and spin
 // sigma (eq. 5 / eq. 6 flip cost with the gated balance term). Philox words are
 // drawn only when the gate or the threshold lookup needs them. The threshold row is
@@ -143,30 +153,28 @@ __device__ __forceinline__ bool decide_id(const GdiSweepArgs &a, uint32_t o, uin
                                           const uint32_t *thr_l = nullptr)
 {
     const bool need_gate = !a.snapshot && pv.D > 0 && sigma == pv.s;
-    uint32_t x0 = 0, x1 = 0;
+    Words4 r{0u, 0u, 0u, 0u};
     bool have = false;
     if (need_gate) {
-        const Words4 r = philox10(o, t, a.replica, 0u, a.key0, a.key1);
-        x0 = r.w0;
-        x1 = r.w1;
+        r = philox10(o, t, a.replica, 0u, a.key0, a.key1);
         have = true;
     }
     int32_t m_seen;
     if (a.snapshot) {
         m_seen = pv.M0;
     } else {
-        const bool gated = need_gate && ((uint64_t)x1 * pv.O < ((uint64_t)(uint32_t)pv.D << 32));
+        const bool gated = need_gate && ((uint64_t)r.w1 * pv.O < ((uint64_t)(uint32_t)pv.D << 32));
         m_seen = gated ? pv.M0 : 0;
     }
     const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
     if (a.rule) {  // the paper's rule: the argmin value, then a random flip with probability P_f
-        if (!have) x0 = philox10(o, t, a.replica, 0u, a.key0, a.key1).w0;
-        return (dE < 0) != (x0 < thr_at(thr_l, thr_row, thr_l != nullptr, 0));
+        if (!have) r = philox10(o, t, a.replica, 0u, a.key0, a.key1);
+        return paper_flip(dE, sigma, r.w0, r.w2, thr_at(thr_l, thr_row, thr_l != nullptr, 0));
     }
     if (dE <= 0) return true;
     if (dE > a.K) return false;
-    if (!have) x0 = philox10(o, t, a.replica, 0u, a.key0, a.key1).w0;
-    return x0 < thr_at(thr_l, thr_row, thr_l != nullptr, dE);
+    if (!have) r = philox10(o, t, a.replica, 0u, a.key0, a.key1);
+    return r.w0 < thr_at(thr_l, thr_row, thr_l != nullptr, dE);
 }
 
 // Launch gate of the masked sweeps: the active-set kernel and the full-graph
@@ -806,7 +814,8 @@ struct RowAhead {
 };
 
 struct NodePrefetch {
-    int32_t r0, deg;
+    uint32_t r0t;              // row start (< 2^31) | low bit of Philox word x2 << 31 (paper rule's tie)
+    int32_t deg;
     uint32_t x0, x1;
     uint32_t e[GDI_HALO_PF];  // packed entries (see ent_word / ent_bit / ent_w)
 };
@@ -899,7 +908,7 @@ __device__ __forceinline__ int32_t row_field(const GdiHaloArgs &h, const uint32_
     }
     for (int32_t k0 = GDI_HALO_PF; k0 < q.deg; k0 += GDI_HALO_PF) {
         uint32_t ex[GDI_HALO_PF];
-        load_run(h.adjL, q.r0 + k0, ex);
+        load_run(h.adjL, (int32_t)(q.r0t & 0x7FFFFFFFu) + k0, ex);
         hv += field_sum(bits, ex, q.deg - k0, UNIT);
     }
     return hv;
@@ -922,7 +931,6 @@ __device__ __forceinline__ void load_entries(const GdiHaloArgs &h, const RowAhea
     // in order, and a wait for a value loaded earlier would count the new loads too).
     uint32_t id = (uint32_t)ra.id;
     asm volatile("" : "+v"(id));
-    pf.r0 = ra.r0;
     pf.deg = ra.r1 - ra.r0;
     // every load is issued unconditionally, whatever the degree (field_sum drops the
     // entries past the row): a register that is zeroed and then conditionally loaded
@@ -931,13 +939,14 @@ __device__ __forceinline__ void load_entries(const GdiHaloArgs &h, const RowAhea
     const Words4 w = philox10(id, t, a.replica, 0u, a.key0, a.key1);
     pf.x0 = w.w0;
     pf.x1 = w.w1;
+    pf.r0t = (uint32_t)ra.r0 | (w.w2 << 31);
 }
 
 // Metropolis decision with the node's Philox words already drawn. The threshold
 // row is read from LDS when staged there (thr_l), else from global memory (thr_g).
 __device__ __forceinline__ bool decide_words(const GdiSweepArgs &a, int32_t sigma, int32_t h,
                                              const PhaseView &pv, const uint32_t *thr_l, const uint32_t *thr_g,
-                                             bool in_lds, uint32_t x0, uint32_t x1)
+                                             bool in_lds, uint32_t x0, uint32_t x1, uint32_t x2)
 {
     int32_t m_seen;
     if (a.snapshot) {
@@ -948,7 +957,7 @@ __device__ __forceinline__ bool decide_words(const GdiSweepArgs &a, int32_t sigm
         m_seen = gated ? pv.M0 : 0;
     }
     const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * m_seen);
-    if (a.rule) return (dE < 0) != (x0 < thr_at(thr_l, thr_g, in_lds, 0));
+    if (a.rule) return paper_flip(dE, sigma, x0, x2, thr_at(thr_l, thr_g, in_lds, 0));
     if (dE <= 0) return true;
     if (dE > a.K) return false;
     return x0 < thr_at(thr_l, thr_g, in_lds, dE);
@@ -1156,6 +1165,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     // this thread's tail node in the current sweep: Philox words, drawn while the last
     // grid phase's dM travels
     uint32_t tx0 = 0, tx1 = 0;
+    bool ttie = false;  // low bit of its word x2
     for (uint32_t t = a.t0; t < a.S; ++t) {
         const uint32_t *thr_l = thr_sh + (t & 1u) * K1;
         const uint32_t *thr_g = a.thr + (size_t)t * K1;
@@ -1191,7 +1201,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                         const int32_t hv = base == e.node_lo && h_ready ? h_pre : row_field<UNIT>(h, bits, q);
                         const int32_t lb = (e.lds_off + (v >> 5) - e.win_lo) * 32 + (v & 31);
                         const int32_t sigma = lds_spin(bits, lb);
-                        flip = decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, q.x0, q.x1);
+                        flip = decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, q.x0, q.x1, q.r0t >> 31);
                         sigma_l = sigma;
                         if (flip) {
                             dcut += (int64_t)sigma * hv;
@@ -1256,6 +1266,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                     const Words4 xw = philox10((uint32_t)my_id, t, a.replica, 0u, a.key0, a.key1);
                     tx0 = xw.w0;
                     tx1 = xw.w1;
+                    ttie = (xw.w2 & 1u) != 0;
                 }
                 if (pre_next) {
                     if (lane == 0) __hip_atomic_fetch_add(&wdone, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1327,7 +1338,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                     const int32_t hv = lds_field(bits, tent, trp[tid], trp[tid + 1]);
                     const int32_t lb = (h.tail_off + ((v - tail_base) >> 5)) * 32 + (v & 31);
                     const int32_t sigma = lds_spin(bits, lb);
-                    if (decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, tx0, tx1)) {
+                    if (decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, tx0, tx1, ttie ? 1u : 0u)) {
                         // members of a class are never neighbours: concurrent readers of this
                         // word only look at bits that do not change in this class
                         atomicXor(&bits[lb >> 5], 1u << (lb & 31));
@@ -1622,10 +1633,10 @@ __global__ void __launch_bounds__(1024) k_sweep_racy(GdiSweepArgs a, uint32_t t)
             const int32_t M = m_sh;
             const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * M);
             const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)(a.K + 1);
-            const uint32_t x0 = philox10((uint32_t)o, t, a.replica, 0u, a.key0, a.key1).w0;
+            const Words4 xw = philox10((uint32_t)o, t, a.replica, 0u, a.key0, a.key1);
             bool flip;
-            if (a.rule) flip = (dE < 0) != (x0 < thr_row[0]);
-            else flip = dE <= 0 || (dE <= a.K && x0 < thr_row[dE]);
+            if (a.rule) flip = paper_flip(dE, sigma, xw.w0, xw.w2, thr_row[0]);
+            else flip = dE <= 0 || (dE <= a.K && xw.w0 < thr_row[dE]);
             if (flip) {
                 __hip_atomic_store(&a.spin[v], (int8_t)(-sigma), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 dM = -2 * sigma;

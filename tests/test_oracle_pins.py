@@ -13,6 +13,7 @@ import random
 import shutil
 import subprocess
 from decimal import Decimal, getcontext
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -292,10 +293,57 @@ def test_torus_close_to_bisection_width(oracle_lib):
     assert min(r["cut"] for r in runs) <= 3 * 2 * L
 
 
+def test_crossing_edge_count_closed_forms(oracle_lib):
+    """The crossing-edge count (the paper's "cut", Sec. VI) on +-1-weighted graphs, where it
+    differs from the weighted cut: an even cycle with alternating spins crosses all n
+    edges; K_{a,b} split along its sides crosses all a*b edges; a path crosses once per
+    sign change. The weighted cut is the sum of the crossing weights in each case."""
+    n = 30
+    w = np.where(np.arange(n) % 3 == 0, -1, 1)
+    g = gs.from_edges(n, np.arange(n), (np.arange(n) + 1) % n, w)
+    s = np.where(np.arange(n) % 2 == 0, 1, -1).astype(np.int8)
+    assert oracle_lib.cut(g, s) == (int(w.sum()), n, 0)
+    a_, b_ = 5, 7
+    ai, bi = np.meshgrid(np.arange(a_), a_ + np.arange(b_), indexing="ij")
+    wk = np.where((ai + bi) % 2 == 0, 1, -1).ravel()
+    g = gs.from_edges(a_ + b_, ai.ravel(), bi.ravel(), wk)
+    s = np.array([1] * a_ + [-1] * b_, dtype=np.int8)
+    assert oracle_lib.cut(g, s) == (int(wk.sum()), a_ * b_, a_ - b_)
+    m = 25
+    wp = np.where(np.arange(m - 1) % 2 == 0, 1, -1)
+    g = gs.from_edges(m, np.arange(m - 1), np.arange(1, m), wp)
+    changes = [3, 4, 11, 20]
+    s = np.ones(m, dtype=np.int8)
+    for c in changes:
+        s[c + 1:] = -s[c + 1:]
+    assert oracle_lib.cut(g, s)[1] == len(changes)
+    assert oracle_lib.cut(g, s)[0] == int(sum(wp[c] for c in changes))
+
+
+def test_crossing_edges_exhaustive(oracle_lib):
+    """Over all 2^12 states of a +-1-weighted graph, the oracle's crossing count equals the
+    edge-list count and the weighted cut of the same graph with |w| weights, and differs
+    from its own weighted cut wherever a -1 edge crosses."""
+    g = gs.er_graph(12, 0.4, 35, "pm1")
+    assert (g.w < 0).any() and (g.w > 0).any()
+    gabs = gs.Graph(n=g.n, row_ptr=g.row_ptr, col=g.col, w=np.abs(g.w), name="abs")
+    S = exhaustive.all_states(g.n)
+    count = exhaustive.crossing_edges(g, S)
+    differ = 0
+    for k in range(S.shape[0]):
+        cw, ce, m = oracle_lib.cut(g, S[k])
+        assert ce == count[k] == oracle_lib.cut(gabs, S[k])[0]
+        differ += cw != ce
+    assert differ > S.shape[0] // 2
+
+
 # ---------------------------------------------------------------- the schedule itself (P6, P7)
 
-def decide_from_definitions(g, prev, i, c_members, t, T, seed, replica, A, B, gated_mode):
-    """One node's decision recomputed from eq. 5/6 energies, the gate and exact thresholds."""
+def decide_from_definitions(g, prev, i, c_members, t, T, seed, replica, A, B, gated_mode, paper_rule=False):
+    """One node's decision recomputed from eq. 5/6 energies, the gate and exact thresholds.
+    With paper_rule, T is the flip probability P_f: the node takes the value of lower local
+    energy (either value on a tie, chosen by Philox word x2), then flips with probability
+    P_f, decided by x0 < floor(2^32 P_f) in exact arithmetic."""
     M0 = int(prev.sum())
     s = (M0 > 0) - (M0 < 0)
     D = abs(M0) // 2
@@ -310,6 +358,17 @@ def decide_from_definitions(g, prev, i, c_members, t, T, seed, replica, A, B, ga
     d_cut = cut_from_scratch(g, flipped) - cut_from_scratch(g, prev)
     d_bal = (m_seen - 2 * int(prev[i])) ** 2 - m_seen ** 2
     dE = B * d_cut + A * d_bal
+    if paper_rule:
+        e_keep, e_flip = 0, dE  # local energies of the two values, relative to the current one
+        if e_flip < e_keep:
+            value = -int(prev[i])
+        elif e_flip > e_keep:
+            value = int(prev[i])
+        else:
+            value = 1 if x[2] & 1 else -1
+        pf_thr = min(2 ** 32 - 1, math.floor(Fraction(T) * 2 ** 32))  # exact: T is a double
+        random_flip = x[0] < pf_thr
+        return (value != prev[i]) != random_flip
     if dE <= 0:
         return True
     thr, _ = exact_threshold(dE, T)
@@ -317,14 +376,17 @@ def decide_from_definitions(g, prev, i, c_members, t, T, seed, replica, A, B, ga
 
 
 @pytest.mark.parametrize("gated_mode", [True, False])
-def test_phase_audit_from_definitions(oracle_lib, gated_mode):
-    """Every phase of the oracle's trajectory, re-derived node by node from definitions."""
+@pytest.mark.parametrize("paper_rule", [False, True])
+def test_phase_audit_from_definitions(oracle_lib, gated_mode, paper_rule):
+    """Every phase of the oracle's trajectory, re-derived node by node from definitions
+    (Metropolis, and the paper's argmin + random flip rule with its random tie value)."""
     cases = [(gs.er_graph(40, 0.15, 31, "pm1"), 2, 1), (gs.rgg_graph(60, 6.0, 32, "unit"), 1, 1),
-             (gs.er_graph(37, 0.2, 33, "unit"), 1, 2)]
+             (gs.er_graph(37, 0.2, 33, "unit"), 1, 2), (gs.rgg_graph(50, 4.0, 34, "unit"), 0, 1)]
+    ties = 0
     for g, A, B in cases:
-        T = gs.geometric_temps(2.5, 0.3, 8)
+        T = gs.geometric_temps(0.4, 0.02, 8) if paper_rule else gs.geometric_temps(2.5, 0.3, 8)
         seed, replica = 77, 3
-        r = oracle_lib.anneal(g, T, seed, A=A, B=B, replica=replica,
+        r = oracle_lib.anneal(g, T, seed, A=A, B=B, replica=replica, rule=1 if paper_rule else 0,
                               mode=0 if gated_mode else 1, phase_trace=True, phase_spins=True)
         col, C = oracle_lib.colour(g)
         prev = np.array([1 if ref_tiny.philox4x32_10(seed, (i, 0, replica, 1))[0] & 1 else -1
@@ -336,12 +398,17 @@ def test_phase_audit_from_definitions(oracle_lib, gated_mode):
                 assert np.array_equal(nxt[col != c], prev[col != c])
                 for i in members:
                     flip = decide_from_definitions(g, prev, i, members, t, T[t], seed, replica, A, B,
-                                                   gated_mode)
+                                                   gated_mode, paper_rule)
                     assert nxt[i] == (-prev[i] if flip else prev[i]), (t, c, i)
+                    if paper_rule:
+                        flipped = prev.copy(); flipped[i] = -flipped[i]
+                        ties += int(B * (cut_from_scratch(g, flipped) - cut_from_scratch(g, prev)) == 0 and A == 0)
                 assert r["phase_m"][t, c] == nxt.sum()
                 assert r["phase_cut"][t, c] == cut_from_scratch(g, nxt)
                 prev = nxt
         assert np.array_equal(prev, r["spins"])
+    if paper_rule:
+        assert ties > 0  # the audit saw tied decisions
 
 
 @pytest.mark.parametrize("gated", [True, False])
