@@ -5,6 +5,9 @@
 * ``balanced_min_cut``: the minimum weighted cut over all partitions with
   |V1| - |V2| in {0} (n even) or {-1, +1} (n odd) -- the problem statement of
   Sec. IV-A -- by enumerating every such partition.
+* ``crossing_edges``: the number of edges whose ends lie in different parts (the
+  paper's "cut", Sec. VI), for every row of a state matrix, counted over the
+  undirected edge list.
 """
 from __future__ import annotations
 
@@ -42,3 +45,10 @@ def balanced_min_cut(g) -> tuple:
     ok = np.abs(M) == target
     best = int(cut[ok].min())
     return best, int(np.count_nonzero(ok & (cut == best)))
+
+
+def crossing_edges(g, states) -> np.ndarray:
+    """Crossing-edge count of each state (rows of +-1 spins), over the undirected edge list."""
+    S = np.atleast_2d(np.asarray(states, dtype=np.int64))
+    a, b, _ = _edges(g)
+    return (S[:, a] != S[:, b]).sum(axis=1)

@@ -14,13 +14,21 @@ Proposals:
   * network    -- skip nodes whose logit exceeds logit(p) for a 6 -> 64 -> 64 -> 1
                   ReLU network on six per-node features.
 
-Precision. Features and the network's decision (an integer: skip or not) are
-taken in the precision the kernels use -- features in FP32 rounded to BF16,
-weights W1, W2 in BF16, hidden activations H1 in BF16, FP32 accumulation --
-following the kernels' order of FP32 operations (see ``mlp_logits_f32``). The
-loss and gradient reference (``mlp_loss_grad``) is FP64 with optional BF16
-rounding at the same storage points; with rounding off it is pinned by finite
-differences.
+Precision. The network is defined with BF16 storage points: features, W1, W2 and
+the first hidden layer H1 hold BF16 values, everything else is exact. ``mlp_logits``
+and ``mlp_loss_grad`` evaluate that definition in FP64 (with rounding off, the
+gradient is pinned by finite differences and autograd). A device computes the same
+definition in FP32; ``mlp_error_model`` bounds how far any FP32 evaluation may land
+from the FP64 one: every short dot product (at most 67 terms) by the worst-case
+bound gamma_k = k u / (1 - k u), every sum over minibatch rows by the probabilistic
+bound lambda sqrt(N) u of Higham and Mary (SIAM J. Sci. Comput. 41(5), 2019) with
+lambda = 8, and every BF16 storage point by rounding both ends of the value's
+interval (rounding is monotone), so that a value near a BF16 rounding boundary
+carries the full width of the two candidates. u is taken as 2^-23 (twice FP32's
+unit roundoff), which also covers accumulators that round less carefully than
+round-to-nearest. A skip decision is the FP64 one, skip iff z > logit(p); it is
+fixed only where |z - logit(p)| exceeds the logit's bound plus the error of an FP32
+evaluation of logit(p) -- nodes inside that band may go either way.
 
 Weights travel as one flat array in the order w1[64][6], b1[64], w2[64][64],
 b2[64], w3[64], b3.
@@ -102,51 +110,11 @@ def heuristic_skip(last_flip, t: int, k: int) -> np.ndarray:
     return (t - np.asarray(last_flip, dtype=np.int64)) >= k
 
 
-# ---------------------------------------------------------------- network, kernel precision
-def _fma32(a, b, c):
-    """FP32 fused multiply-add: a*b is exact in FP64, one rounding of the sum to FP32."""
-    return (a.astype(np.float64) * b.astype(np.float64) + c.astype(np.float64)).astype(np.float32)
-
-
-def mlp_logits_f32(w, X) -> np.ndarray:
-    """Logits in the kernels' precision and FP32 operation order.
-
-    Layer 1: BF16 products summed exactly, rounded once to FP32, + b1 in FP32,
-    ReLU, rounded to BF16. Layer 2: four 16-input partial sums (exact), each added
-    to the FP32 accumulator with one rounding, + b2, ReLU. Output: for each of the
-    four row groups g, a running FP32 fused multiply-add over hidden units 16m + 4g
-    + i (m outer, i inner), then (p0 + p1) + (p2 + p3) + b3.
-    """
-    P = unflatten(w)
-    Xb = bf16(np.asarray(X, dtype=np.float32)[:, :6]).astype(np.float64)
-    W1 = bf16(P["w1"].astype(np.float32)).astype(np.float64)
-    W2 = bf16(P["w2"].astype(np.float32)).astype(np.float64)
-    b1 = P["b1"].astype(np.float32)
-    b2 = P["b2"].astype(np.float32)
-    w3 = P["w3"].astype(np.float32)
-    b3 = np.float32(P["b3"])
-    pre1 = (Xb @ W1.T).astype(np.float32) + b1
-    h1 = bf16(np.maximum(pre1, np.float32(0))).astype(np.float64)
-    acc = np.zeros((Xb.shape[0], 64), dtype=np.float32)
-    for kb in range(4):
-        part = h1[:, 16 * kb:16 * kb + 16] @ W2[:, 16 * kb:16 * kb + 16].T
-        acc = (acc.astype(np.float64) + part).astype(np.float32)
-    h2 = np.maximum(acc + b2, np.float32(0))
-    parts = []
-    for g in range(4):
-        p = np.zeros(Xb.shape[0], dtype=np.float32)
-        for m in range(4):
-            for i in range(4):
-                u = 16 * m + 4 * g + i
-                p = _fma32(np.full_like(p, w3[u]), h2[:, u], p)
-        parts.append(p)
-    return ((parts[0] + parts[1]) + (parts[2] + parts[3])) + b3
-
-
-def threshold_logit(p: float) -> np.float32:
-    """logit(p) in FP32: log(p / (1 - p)) with p, 1 - p and the quotient in FP32."""
-    p32 = np.float32(p)
-    return np.float32(np.log(p32 / (np.float32(1) - p32)))
+# ---------------------------------------------------------------- decision threshold
+def threshold_logit(p: float) -> float:
+    """logit(p) = log(p / (1 - p)) in FP64 for the FP32 value of p (skip iff sigmoid(z) > p)."""
+    p64 = float(np.float32(p))
+    return float(np.log(p64 / (1.0 - p64)))
 
 
 # ---------------------------------------------------------------- network, FP64 reference
@@ -194,6 +162,124 @@ def mlp_loss_grad(w, X, y, round_points: bool = True):
     return float(loss), flatten(g)
 
 
+# ---------------------------------------------------------------- error model of an FP32 evaluation
+U_FP32 = 2.0 ** -23   # twice FP32's unit roundoff (see the module docstring)
+LAMBDA = 8.0          # probabilistic bound: fails with probability <= 2 exp(-LAMBDA^2 / 2) per sum
+
+
+def _gamma(k: int) -> float:
+    """Worst-case relative error of a k-term FP32 sum or dot product (Higham, Thm. 3.1)."""
+    return k * U_FP32 / (1.0 - k * U_FP32)
+
+
+def _gamma_rows(n: int) -> float:
+    """Probabilistic relative error of a sum over n rows (Higham and Mary 2019, Thm. 3.1)."""
+    return LAMBDA * np.sqrt(n) * U_FP32 + n * U_FP32 ** 2
+
+
+def _w32(w) -> dict:
+    """The FP32 master weights a device holds, as FP64 values."""
+    return {k: np.asarray(v, dtype=np.float32).astype(np.float64) for k, v in unflatten(w).items()}
+
+
+def _bf16_64(a):
+    """Round FP64 values to FP32, then to BF16 (the storage a device applies to an FP32 value)."""
+    return bf16(np.asarray(a, dtype=np.float64).astype(np.float32)).astype(np.float64)
+
+
+def _bf16_spread(v, e):
+    """Largest distance between bf16(v) and bf16 of any value within e of v (monotone rounding)."""
+    c = _bf16_64(v)
+    return np.maximum(_bf16_64(v + e) - c, c - _bf16_64(v - e))
+
+
+def mlp_error_model(w, X, y=None) -> dict:
+    """The FP64 definition of the network on rows X (n x 6) with FP32 master weights w,
+    and bounds on how far an FP32 evaluation with the same BF16 storage points may be
+    from it.
+
+    Returns z (logits) and z_bound; with labels y also loss, loss_bound, grad (flat,
+    gdi_mlp_weights order) and grad_bound (flat, elementwise).
+    """
+    P = _w32(w)
+    x = bf16(np.asarray(X, dtype=np.float32)[:, :6]).astype(np.float64)
+    W1, W2 = _bf16_64(P["w1"]), _bf16_64(P["w2"])
+    b1, b2, w3, b3 = P["b1"], P["b2"], P["w3"], float(P["b3"])
+    n = x.shape[0]
+    # layer 1: six exact products and the bias per hidden unit, then ReLU and BF16 storage
+    pre1 = x @ W1.T + b1
+    e1 = _gamma(8) * (np.abs(x) @ np.abs(W1).T + np.abs(b1))
+    h1 = _bf16_64(np.maximum(pre1, 0.0))
+    dh1 = _bf16_spread(np.maximum(pre1, 0.0), e1)
+    h1_lo = _bf16_64(np.maximum(pre1 - e1, 0.0))
+    amb1 = (h1_lo == 0.0) & (_bf16_64(np.maximum(pre1 + e1, 0.0)) > 0.0)  # ReLU gate undecided
+    # layer 2: 64 exact BF16 products and the bias, ReLU (1-Lipschitz), kept unrounded
+    pre2 = h1 @ W2.T + b2
+    e2 = _gamma(66) * ((h1 + dh1) @ np.abs(W2).T + np.abs(b2)) + dh1 @ np.abs(W2).T
+    h2 = np.maximum(pre2, 0.0)
+    dh2 = e2
+    # output: 64 FP32 products and the bias
+    z = h2 @ w3 + b3
+    ez = _gamma(67) * ((h2 + dh2) @ np.abs(w3) + abs(b3)) + dh2 @ np.abs(w3)
+    out = dict(z=z, z_bound=ez)
+    if y is None:
+        return out
+    y = np.asarray(y, dtype=np.float64)
+    gN = _gamma_rows(n)
+    sig = 1.0 / (1.0 + np.exp(-z))
+    sig_lo, sig_hi = 1.0 / (1.0 + np.exp(-(z - ez))), 1.0 / (1.0 + np.exp(-(z + ez)))
+    # sigmoid through exp, an addition and a division: eight roundings' worth of slack
+    dsig = np.maximum(sig_hi - sig, sig - sig_lo) + 8 * U_FP32 * sig_hi
+    dz = (sig - y) / n
+    ddz = (dsig + 3 * U_FP32 * (np.abs(sig - y) + dsig)) / n
+    # loss: softplus(z) - y z per row, mean over rows
+    terms = np.maximum(z, 0.0) + np.log1p(np.exp(-np.abs(z))) - y * z
+    dterm = np.abs(sig - y) * ez + ez ** 2 + 8 * U_FP32 * (np.abs(terms) + np.abs(y * z) + np.abs(z))
+    out["loss"] = float(np.mean(terms))
+    out["loss_bound"] = float((np.sum(dterm) + gN * np.sum(np.abs(terms) + dterm)) / n)
+    # backward through the output layer
+    gw3 = h2.T @ dz
+    gw3_b = (ddz @ (h2 + dh2) + np.abs(dz) @ dh2 + U_FP32 * (np.abs(dz) @ (h2 + dh2))
+             + gN * ((np.abs(dz) + ddz) @ (h2 + dh2)))
+    gb3 = float(dz.sum())
+    gb3_b = float(ddz.sum() + gN * np.sum(np.abs(dz) + ddz))
+    amb2 = np.abs(pre2) <= e2  # ReLU gate of layer 2 undecided
+    dzw = dz[:, None] * w3[None, :]
+    dpre2 = np.where(pre2 > 0, dzw, 0.0)
+    ddpre2 = ddz[:, None] * np.abs(w3)[None, :] + U_FP32 * np.abs(dzw)
+    ddpre2 = np.where(amb2, ddpre2 + np.abs(dzw), np.where(pre2 > 0, ddpre2, 0.0))
+    gb2 = dpre2.sum(axis=0)
+    gb2_b = ddpre2.sum(axis=0) + gN * (np.abs(dpre2) + ddpre2).sum(axis=0)
+    dp2 = _bf16_64(dpre2)
+    ddp2 = _bf16_spread(dpre2, ddpre2)
+    gw2 = dp2.T @ h1
+    gw2_b = ddp2.T @ (h1 + dh1) + np.abs(dp2).T @ dh1 + gN * ((np.abs(dp2) + ddp2).T @ (h1 + dh1))
+    # back into layer 1
+    dH1 = dp2 @ W2
+    ddH1 = ddp2 @ np.abs(W2) + _gamma(65) * ((np.abs(dp2) + ddp2) @ np.abs(W2))
+    dpre1 = np.where(h1 > 0, dH1, 0.0)
+    ddpre1 = np.where((h1 > 0) | amb1, ddH1, 0.0) + np.where(amb1, np.abs(dH1), 0.0)
+    gb1 = dpre1.sum(axis=0)
+    gb1_b = ddpre1.sum(axis=0) + gN * (np.abs(dpre1) + ddpre1).sum(axis=0)
+    dp1 = _bf16_64(dpre1)
+    ddp1 = _bf16_spread(dpre1, ddpre1)
+    gw1 = dp1.T @ x
+    gw1_b = ddp1.T @ np.abs(x) + gN * ((np.abs(dp1) + ddp1).T @ np.abs(x))
+    out["grad"] = flatten(dict(w1=gw1, b1=gb1, w2=gw2, b2=gb2, w3=gw3, b3=gb3))
+    out["grad_bound"] = flatten(dict(w1=gw1_b, b1=gb1_b, w2=gw2_b, b2=gb2_b, w3=gw3_b, b3=gb3_b))
+    return out
+
+
+def skip_decisions(w, X, p: float):
+    """FP64 skip decisions (z > logit(p)) and the nodes an FP32 evaluation could decide
+    either way: |z - logit(p)| <= z_bound + the error of an FP32 logit(p) (a division,
+    a subtraction and a logarithm: 16 units of roundoff, relative, plus as much absolute)."""
+    m = mlp_error_model(w, X)
+    thr = threshold_logit(p)
+    band = m["z_bound"] + 16 * U_FP32 * (1.0 + abs(thr))
+    return m["z"] > thr, np.abs(m["z"] - thr) <= band, m["z"], thr
+
+
 # ---------------------------------------------------------------- the learned schedule
 def learned_anneal(g, temps, seed: int, k_full: int, proposal: str = "none", weights=None, p: float = 0.5,
                    heuristic_k: int = 1, A: int = 1, B: int = 1, replica: int = 0, mode: int = 0,
@@ -204,8 +290,9 @@ def learned_anneal(g, temps, seed: int, k_full: int, proposal: str = "none", wei
 
     Returns spins, M, cut, masks (one row per full sweep, original order; a full
     sweep with no masked sweeps after it has an all-zero row) and, for the network
-    proposal, logits (one row per full sweep with masked sweeps after it) and margins =
-    min |logit - logit(p)| per row.
+    proposal, logits (FP64, one row per full sweep with masked sweeps after it),
+    margins = min |logit - logit(p)| per row, and ambiguous (per row, the nodes whose
+    decision an FP32 evaluation could take either way, see skip_decisions).
     """
     T = np.ascontiguousarray(temps, dtype=np.float64)
     S = T.size
@@ -215,7 +302,7 @@ def learned_anneal(g, temps, seed: int, k_full: int, proposal: str = "none", wei
     b0 = min(S, max(start_sweep, learn_from))
     rows = (S - b0 + k_full - 1) // k_full
     masks = np.zeros((rows, n), dtype=np.uint8)
-    margins, logits = [], []
+    margins, logits, ambiguous = [], [], []
     kw = dict(A=A, B=B, replica=replica, mode=mode, n_threads=n_threads)
     M = None
     res = None
@@ -234,10 +321,10 @@ def learned_anneal(g, temps, seed: int, k_full: int, proposal: str = "none", wei
         elif proposal == "heuristic":
             skip = heuristic_skip(lf, b, heuristic_k)
         elif proposal == "network":
-            z = mlp_logits_f32(weights, features(g, spins, lf, b, T[b], A, B, M))
-            skip = z > thr
+            skip, amb, z, _ = skip_decisions(weights, features(g, spins, lf, b, T[b], A, B, M), p)
             logits.append(z)
-            margins.append(float(np.min(np.abs(z.astype(np.float64) - np.float64(thr)))))
+            ambiguous.append(amb)
+            margins.append(float(np.min(np.abs(z - thr))))
         else:
             raise ValueError(proposal)
         masks[row] = skip
@@ -247,7 +334,7 @@ def learned_anneal(g, temps, seed: int, k_full: int, proposal: str = "none", wei
         res = oracle_anneal(g, T, seed, start_sweep=S, init=init, **kw)
         spins = res["spins"]
     return dict(spins=spins, M=res["M"], cut=res["cut"], masks=masks, margins=margins, logits=logits,
-                threshold=thr, last_flip=lf)
+                ambiguous=ambiguous, threshold=thr, last_flip=lf)
 
 
 def trace_dataset(g, temps, seed: int, every: int, k_label: int, max_snapshots: int, A: int = 1, B: int = 1,

@@ -1,5 +1,9 @@
 """GPU parity of the learned proposal: masked anneals, features, labels, the network's
-forward pass and gradient, and training, against oracle/learned_ref.py."""
+forward pass and gradient, and training, against oracle/learned_ref.py.
+
+The network's expected values are its FP64 definition (BF16 storage points, exact
+arithmetic otherwise) with the error bounds of learned_ref.mlp_error_model; a skip
+decision is fixed wherever the FP64 logit lies outside its band around the threshold."""
 import numpy as np
 import pytest
 
@@ -40,7 +44,7 @@ def centred_weights(L, g, seed):
     rng = np.random.default_rng(0)
     s = np.where(rng.random(g.n) < .5, 1, -1).astype(np.int8)
     X = L.features(g, s, np.full(g.n, -1, np.int32), 0, 3.0, 1, 1, int(s.sum()))
-    w[-1] = -float(np.median(L.mlp_logits_f32(w, X)))
+    w[-1] = -float(np.median(L.mlp_logits(w.astype(np.float32), X)))
     return w.astype(np.float32)
 
 
@@ -141,13 +145,33 @@ def test_heuristic_resume_and_odd_n(gdi, L, oracle_lib):
     assert np.array_equal(r["spins"], ref["spins"]) and r["cut"] == ref["cut"]
 
 
+def compare_network_run(r, ref):
+    """GPU masks against the oracle's FP64 decisions, row by row: equal at every node outside
+    the band; a node inside it may go either way. While the rows agree completely the two
+    runs are the same schedule; if the GPU takes the other value at a node in the band, the
+    trajectories part there (both are correct), and only the rows up to that one compare.
+    Returns (rows compared, whether the whole run compared)."""
+    rows = len(ref["ambiguous"])
+    amb_total = int(sum(a.sum() for a in ref["ambiguous"]))
+    for row in range(rows):
+        amb = ref["ambiguous"][row]
+        diff = r["masks"][row] != ref["masks"][row]
+        assert not np.any(diff & ~amb), f"row {row}: a mask bit differs outside the band"
+        if diff.any():
+            print(f"row {row}: the GPU took the other value at {int(diff.sum())} of {int(amb.sum())} nodes in the "
+                  f"band; the trajectories part here", flush=True)
+            return row + 1, False
+    assert np.array_equal(r["masks"], ref["masks"])
+    assert np.array_equal(r["spins"], ref["spins"]) and (r["M"], r["cut"]) == (ref["M"], ref["cut"])
+    print(f"all {rows} rows equal ({amb_total} decisions in the band, all taken as in FP64); "
+          f"trajectory bit-exact", flush=True)
+    return rows, True
+
+
 @pytest.mark.parametrize("scope,amax", [(1, 0), (2, 0), (2, -1)])
 def test_network_proposal_matches_oracle(gdi, L, scope, amax):
-    """Masks from the BF16 network on the GPU against the oracle's kernel-precision
-    decisions; with identical masks the whole trajectory is bit-exact. A mask bit may
-    differ only where the oracle's logit lies within 1e-4 of the threshold (FP32
-    accumulation order inside the matrix instruction); after such a row the two
-    trajectories legitimately part, so only the rows up to it are compared."""
+    """Masks from the BF16 network on the GPU against the oracle's FP64 decisions; with
+    identical masks the whole trajectory (spins, M, cut) is bit-exact."""
     g = gs.rgg_graph(3000, 8.0, 60, "pm1")
     T = gs.geometric_temps(3.0, 0.05, 120)
     w = centred_weights(L, g, 26)
@@ -157,17 +181,8 @@ def test_network_proposal_matches_oracle(gdi, L, scope, amax):
         a.tune(scope=scope)
         r = a.anneal_learned(T, 7, 5, skip_mode=gdi.SKIP_MLP, weights=w, skip_threshold=0.5, mask_trace=True,
                              active_max=amax)
-    diff_rows = np.flatnonzero(np.any(r["masks"] != ref["masks"], axis=1))
-    print(f"oracle min margin {min(ref['margins']):.2e}, skipped fraction {ref['masks'].mean():.3f}, "
-          f"rows differing: {diff_rows.tolist()}", flush=True)
-    if diff_rows.size == 0:
-        assert np.array_equal(r["spins"], ref["spins"]) and (r["M"], r["cut"]) == (ref["M"], ref["cut"])
-        return
-    row = int(diff_rows[0])
-    nodes = np.flatnonzero(r["masks"][row] != ref["masks"][row])
-    near = np.abs(ref["logits"][row][nodes].astype(np.float64) - np.float64(ref["threshold"]))
-    print(f"row {row}: {nodes.size} near-tie nodes differ, |logit - threshold| <= {near.max():.2e}", flush=True)
-    assert near.max() < 1e-4, "a mask bit differs at a node far from the threshold"
+    print(f"oracle min margin {min(ref['margins']):.2e}, skipped fraction {ref['masks'].mean():.3f}", flush=True)
+    compare_network_run(r, ref)
 
 
 def test_features_and_labels_match_oracle(gdi, L):
@@ -191,6 +206,7 @@ def test_features_and_labels_match_oracle(gdi, L):
 
 
 def test_mlp_forward_matches_reference(gdi, L):
+    """Every logit within the error model's bound of the FP64 definition."""
     import torch
 
     rng = np.random.default_rng(11)
@@ -202,15 +218,16 @@ def test_mlp_forward_matches_reference(gdi, L):
     out = torch.zeros(n, dtype=torch.float32, device="cuda:0")
     gdi.mlp_forward(w, dx.data_ptr(), n, out.data_ptr())
     z = out.cpu().numpy().astype(np.float64)
-    z32 = L.mlp_logits_f32(w, X).astype(np.float64)
-    err = np.abs(z - z32)
-    print(f"forward: {np.mean(err == 0):.4f} exact, max err {err.max():.2e}", flush=True)
-    # FP32 accumulation order: a few ulps; a BF16 rounding flip of one hidden unit: rare, < 5e-3
-    assert np.mean(err <= 1e-5 * (1 + np.abs(z32))) > 0.999
-    assert err.max() < 5e-3
+    m = L.mlp_error_model(w, X)
+    err = np.abs(z - m["z"])
+    print(f"forward: max err {err.max():.2e}, max err / bound {np.max(err / m['z_bound']):.3f}, "
+          f"median bound {np.median(m['z_bound']):.2e}", flush=True)
+    assert np.all(err <= m["z_bound"])
 
 
 def test_mlp_gradient_matches_reference(gdi, L):
+    """Loss and every gradient element within the error model's bounds of the FP64
+    definition (same BF16 storage points as the network's definition)."""
     import torch
 
     rng = np.random.default_rng(13)
@@ -222,15 +239,15 @@ def test_mlp_gradient_matches_reference(gdi, L):
     dx = torch.from_numpy(X).to(torch.bfloat16).cuda()
     dy = torch.from_numpy(y).cuda()
     grad, loss = gdi.mlp_gradient(w, dx.data_ptr(), dy.data_ptr(), n)
-    loss_ref, g_ref = L.mlp_loss_grad(w.astype(np.float64), X[:, :6], y, round_points=True)
-    assert abs(loss - loss_ref) <= 1e-4 * abs(loss_ref)
-    gu, ru = gdi.mlp_unflatten(grad), L.unflatten(g_ref)
-    for k in ("w1", "b1", "w2", "b2", "w3"):
-        scale = np.abs(ru[k]).max()
-        err = np.abs(np.asarray(gu[k], np.float64) - ru[k]).max()
-        print(f"grad {k}: max err {err:.2e} of scale {scale:.2e}", flush=True)
-        assert err <= 2e-3 * scale + 1e-7, k
-    assert abs(float(gu["b3"]) - ru["b3"]) <= 1e-4 * abs(ru["b3"]) + 1e-7
+    m = L.mlp_error_model(w, X, y)
+    assert abs(loss - m["loss"]) <= m["loss_bound"]
+    err = np.abs(np.asarray(grad, np.float64) - m["grad"])
+    gu, eu, bu = L.unflatten(m["grad"]), L.unflatten(err), L.unflatten(m["grad_bound"])
+    for k in ("w1", "b1", "w2", "b2", "w3", "b3"):
+        e, b = np.asarray(eu[k]), np.asarray(bu[k])
+        print(f"grad {k}: max err {e.max():.2e} (max |g| {np.abs(gu[k]).max():.2e}), max err / bound "
+              f"{np.max(e / b):.3f}", flush=True)
+    assert np.all(err <= m["grad_bound"])
 
 
 def test_training_reduces_loss(gdi, L):
@@ -334,12 +351,5 @@ def test_full_size_learned_schedules(gdi, L):
     with gdi.Annealer(g) as a:
         r = a.anneal_learned(T2, 1, 8, skip_mode=gdi.SKIP_MLP, weights=w, skip_threshold=0.5, learn_from=100,
                              mask_trace=True)
-    diff_rows = np.flatnonzero(np.any(r["masks"] != ref["masks"], axis=1))
-    print(f"skipped fraction {ref['masks'].mean():.3f}, rows differing: {diff_rows.tolist()}", flush=True)
-    if diff_rows.size == 0:
-        assert np.array_equal(r["spins"], ref["spins"]) and (r["M"], r["cut"]) == (ref["M"], ref["cut"])
-    else:
-        row = int(diff_rows[0])
-        nodes = np.flatnonzero(r["masks"][row] != ref["masks"][row])
-        near = np.abs(ref["logits"][row][nodes].astype(np.float64) - np.float64(ref["threshold"]))
-        assert near.max() < 1e-4, "a mask bit differs at a node far from the threshold"
+    print(f"skipped fraction {ref['masks'].mean():.3f}", flush=True)
+    compare_network_run(r, ref)

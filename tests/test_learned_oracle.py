@@ -1,8 +1,8 @@
 """Pins of the learned-proposal reference (oracle/learned_ref.py) against facts outside it:
 torch's BF16 cast, finite differences and torch autograd for the network's gradient,
-closed forms of a constant network, the oracle's brute-force-pinned flip cost for the
-features, the pure-Python annealer for skipped nodes, and the plain schedule for the
-degenerate proposals."""
+closed forms of a constant network, an independent FP32 evaluation for the error model,
+the oracle's brute-force-pinned flip cost for the features, the pure-Python annealer
+for skipped nodes, and the plain schedule for the degenerate proposals."""
 import numpy as np
 import pytest
 
@@ -80,21 +80,74 @@ def test_constant_network_closed_forms():
     assert np.isclose(loss, np.log1p(np.exp(0.75)) - y.mean() * 0.75, rtol=1e-14)
     assert np.isclose(g[-1], 1 / (1 + np.exp(-0.75)) - y.mean(), rtol=1e-14)
     assert not np.any(g[:-1])
-    assert np.all(L.mlp_logits_f32(w, X.astype(np.float32)) == np.float32(0.75))
+    assert np.all(L.mlp_logits(w, X) == 0.75)
+    m = L.mlp_error_model(w, X.astype(np.float32), y)
+    assert np.all(m["z"] == 0.75) and np.allclose(m["z_bound"], L._gamma(67) * 0.75, rtol=1e-12)
 
 
-def test_kernel_precision_logits_follow_the_definition():
-    """The FP32 operation-order emulation stays within FP32 accumulation error of the FP64
-    definition with the same BF16 storage points."""
-    rng = np.random.default_rng(7)
-    w = rand_weights(8)
-    X = L.bf16(rng.normal(0, 1, (5000, 6)).astype(np.float32))
-    z32 = L.mlp_logits_f32(w, X).astype(np.float64)
-    z64 = L.mlp_logits(w, X, round_points=True)
-    # rare BF16 rounding flips of h1 (FP32 vs FP64 pre-activation) are the only large differences
-    err = np.abs(z32 - z64)
-    assert np.quantile(err, 0.99) < 1e-5 * (1 + np.abs(z64).max())
-    assert err.max() < 1e-2
+def fp32_network(w, X, y):
+    """The network evaluated in FP32 with numpy's float32 matrix products (BLAS order, not
+    any device's) and BF16 storage at the definition's points: a second, independent FP32
+    evaluation for checking the error model. Returns logits, loss and flat gradient."""
+    P = {k: np.asarray(v, dtype=np.float32) for k, v in L.unflatten(w).items()}
+    f32 = np.float32
+    x = L.bf16(np.asarray(X, np.float32)[:, :6])
+    W1, W2 = L.bf16(P["w1"]), L.bf16(P["w2"])
+    h1 = L.bf16(np.maximum(x @ W1.T + P["b1"], f32(0)))
+    pre2 = h1 @ W2.T + P["b2"]
+    h2 = np.maximum(pre2, f32(0))
+    z = h2 @ P["w3"] + f32(P["b3"])
+    n = x.shape[0]
+    yf = np.asarray(y, np.float32)
+    sig = f32(1) / (f32(1) + np.exp(-z))
+    loss = np.sum(np.maximum(z, f32(0)) + np.log1p(np.exp(-np.abs(z))) - yf * z, dtype=np.float32) / f32(n)
+    dz = (sig - yf) * (f32(1) / f32(n))
+    dpre2 = np.where(pre2 > 0, dz[:, None] * P["w3"][None, :], f32(0))
+    dp2 = L.bf16(dpre2)
+    dpre1 = np.where(h1 > 0, dp2 @ W2, f32(0))
+    g = dict(w1=L.bf16(dpre1).T @ x, b1=dpre1.sum(axis=0), w2=dp2.T @ h1, b2=dpre2.sum(axis=0),
+             w3=h2.T @ dz, b3=dz.sum())
+    return z.astype(np.float64), float(loss), L.flatten({k: np.asarray(v, np.float64) for k, v in g.items()})
+
+
+@pytest.mark.parametrize("seed", [7, 8, 9])
+def test_error_model_contains_an_fp32_evaluation(seed):
+    """An FP32 evaluation of the network in another summation order (numpy's float32
+    BLAS) lands within the error model's bounds of the FP64 definition, for every logit and
+    every gradient element; and the bounds are not vacuous."""
+    rng = np.random.default_rng(seed)
+    w = rand_weights(seed + 10).astype(np.float32)
+    X = L.bf16(rng.normal(0, 1, (3000, 6)).astype(np.float32))
+    y = (rng.random(3000) < 0.4).astype(np.uint8)
+    m = L.mlp_error_model(w, X, y)
+    z32, loss32, g32 = fp32_network(w, X, y)
+    assert np.all(np.abs(z32 - m["z"]) <= m["z_bound"])
+    assert abs(loss32 - m["loss"]) <= m["loss_bound"]
+    assert np.all(np.abs(g32 - m["grad"]) <= m["grad_bound"])
+    # the FP64 definition is the reference's: same loss and gradient as mlp_loss_grad
+    loss64, g64 = L.mlp_loss_grad(w.astype(np.float32).astype(np.float64), X, y, round_points=True)
+    assert m["loss"] == pytest.approx(loss64, rel=1e-12) and np.allclose(m["grad"], g64, rtol=1e-12, atol=1e-18)
+    # not vacuous: logit bounds below 1e-3 (1 + |z|) at the median, gradient bounds a few
+    # per mille of each tensor's largest entry
+    assert np.median(m["z_bound"] / (1 + np.abs(m["z"]))) < 1e-3
+    gu, bu = L.unflatten(m["grad"]), L.unflatten(m["grad_bound"])
+    for k in ("w1", "b1", "w2", "b2", "w3"):
+        assert bu[k].max() < 2e-2 * np.abs(gu[k]).max(), k
+
+
+def test_skip_decisions_band():
+    """Nodes outside the band are decided by the FP64 logit; the band is the logit bound
+    plus the threshold's FP32 error, and an FP32 evaluation never contradicts a decision
+    outside it."""
+    rng = np.random.default_rng(12)
+    w = rand_weights(13).astype(np.float32)
+    X = L.bf16(rng.normal(0, 1, (20000, 6)).astype(np.float32))
+    skip, amb, z, thr = L.skip_decisions(w, X, 0.5)
+    assert thr == 0.0 and np.array_equal(skip, z > 0)
+    z32 = fp32_network(w, X, np.zeros(20000))[0]
+    thr32 = np.log(np.float32(0.5) / (np.float32(1) - np.float32(0.5)))
+    assert np.array_equal((z32 > thr32)[~amb], skip[~amb])
+    assert amb.mean() < 1e-2
 
 
 def test_features_against_flip_cost_and_cut():
