@@ -283,10 +283,17 @@ def skip_decisions(w, X, p: float):
 # ---------------------------------------------------------------- the learned schedule
 def learned_anneal(g, temps, seed: int, k_full: int, proposal: str = "none", weights=None, p: float = 0.5,
                    heuristic_k: int = 1, A: int = 1, B: int = 1, replica: int = 0, mode: int = 0,
-                   start_sweep: int = 0, init=None, n_threads: int = 0, learn_from: int = 0) -> dict:
+                   start_sweep: int = 0, init=None, n_threads: int = 0, learn_from: int = 0,
+                   replay_masks=None) -> dict:
     """The annealing schedule: sweeps start_sweep .. b0-1 plain (b0 = max(start_sweep,
     learn_from)), then a full sweep at b0, b0 + k_full, ... and the proposal's skip set
     applied to the sweeps in between.
+
+    replay_masks (rows x n, original order) replaces the skip set of every row by the
+    given one after the proposal has been evaluated on the schedule's own state: the run
+    then follows another implementation's masks, and ``proposed`` holds what the
+    proposal itself decided at each row, so that both can be compared row by row even
+    after the two have taken different values inside the ambiguity band.
 
     Returns spins, M, cut, masks (one row per full sweep, original order; a full
     sweep with no masked sweeps after it has an all-zero row) and, for the network
@@ -302,6 +309,11 @@ def learned_anneal(g, temps, seed: int, k_full: int, proposal: str = "none", wei
     b0 = min(S, max(start_sweep, learn_from))
     rows = (S - b0 + k_full - 1) // k_full
     masks = np.zeros((rows, n), dtype=np.uint8)
+    proposed = np.zeros((rows, n), dtype=np.uint8)
+    if replay_masks is not None:
+        replay_masks = np.asarray(replay_masks, dtype=np.uint8)
+        if replay_masks.shape != (rows, n):
+            raise ValueError(f"replay_masks must be {rows} x {n}")
     margins, logits, ambiguous = [], [], []
     kw = dict(A=A, B=B, replica=replica, mode=mode, n_threads=n_threads)
     M = None
@@ -327,14 +339,17 @@ def learned_anneal(g, temps, seed: int, k_full: int, proposal: str = "none", wei
             margins.append(float(np.min(np.abs(z - thr))))
         else:
             raise ValueError(proposal)
+        proposed[row] = skip
+        if replay_masks is not None:
+            skip = replay_masks[row] != 0
         masks[row] = skip
         res = oracle_anneal(g, T[:end], seed, start_sweep=b + 1, init=spins, skip=skip, last_flip=lf, **kw)
         spins, M = res["spins"], res["M"]
     if res is None:  # start_sweep == S: nothing runs
         res = oracle_anneal(g, T, seed, start_sweep=S, init=init, **kw)
         spins = res["spins"]
-    return dict(spins=spins, M=res["M"], cut=res["cut"], masks=masks, margins=margins, logits=logits,
-                ambiguous=ambiguous, threshold=thr, last_flip=lf)
+    return dict(spins=spins, M=res["M"], cut=res["cut"], masks=masks, proposed=proposed, margins=margins,
+                logits=logits, ambiguous=ambiguous, threshold=thr, last_flip=lf)
 
 
 def trace_dataset(g, temps, seed: int, every: int, k_label: int, max_snapshots: int, A: int = 1, B: int = 1,

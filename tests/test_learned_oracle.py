@@ -235,6 +235,31 @@ def test_skip_everything_runs_only_the_full_sweeps():
     assert r["masks"][:-1].all() and not r["masks"][-1].any()
 
 
+def test_mask_replay():
+    """Replaying a run's own masks reproduces it; replaying the all-skip masks with a
+    network that never skips runs only the full sweeps while ``proposed`` still holds
+    the network's own (all-zero) decisions."""
+    import oracle
+
+    g = gs.er_graph(700, 0.01, 42, "pm1")
+    T = gs.geometric_temps(2.0, 0.1, 21)
+    w = np.zeros(L.MLP_PARAMS)
+    w[-1] = -5.0  # never skips
+    own = L.learned_anneal(g, T, 3, k_full=4, proposal="network", weights=w, p=0.5)
+    again = L.learned_anneal(g, T, 3, k_full=4, proposal="network", weights=w, p=0.5, replay_masks=own["masks"])
+    assert np.array_equal(again["spins"], own["spins"]) and again["cut"] == own["cut"]
+    assert not own["masks"].any() and np.array_equal(again["proposed"], own["masks"])
+    forced = np.ones_like(own["masks"])
+    forced[-1] = 0
+    r = L.learned_anneal(g, T, 3, k_full=4, proposal="network", weights=w, p=0.5, replay_masks=forced)
+    spins = None
+    for b in range(0, 21, 4):
+        spins = oracle.anneal(g, T[:b + 1], 3, start_sweep=b, init=spins)["spins"]
+    assert np.array_equal(r["spins"], spins) and not r["proposed"].any()
+    with pytest.raises(ValueError):
+        L.learned_anneal(g, T, 3, k_full=4, proposal="network", weights=w, p=0.5, replay_masks=forced[:-1])
+
+
 def test_trace_labels_follow_per_sweep_states():
     """Label 1 iff the spin does not change in any of the k_label sweeps that follow the
     snapshot (a node decides once per sweep; checked with one-sweep oracle calls)."""
