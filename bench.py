@@ -29,16 +29,106 @@ def algorithmic_bytes_per_sweep(n: int, nnz: int) -> int:
     return 4 * (n + 1) + 8 * nnz + 2 * n
 
 
-def cpu_baseline(g, temps, seed, sweeps):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(g, temps, seed, sweeps_all, sweeps_one, reps=3):
+    """The C oracle on the first sweeps of the same workload, timed over its sweep loop
+    only (colouring, thresholds and the initial cut excluded): all host threads and one
+    thread, median of reps runs each."""
+    import numpy as np
+
     import oracle
 
-    t0 = time.perf_counter()
-    oracle.anneal(g, temps[:sweeps], seed)
-    dt = time.perf_counter() - t0
-    return {"value": g.n * sweeps / dt, "unit": "spin-updates/s", "cores": oracle.max_threads(),
-            "kind": "oracle",
-            "sample": f"first {sweeps} of the {temps.size} sweeps of the same workload "
-                      f"(n={g.n}), C oracle with OpenMP, {dt:.2f} s wall incl. colouring"}
+    med = {}
+    for label, threads, k in (("all", 0, sweeps_all), ("one", 1, sweeps_one)):
+        ts = [oracle.anneal(g, temps[:k], seed, n_threads=threads)["sweep_s"] for _ in range(reps)]
+        med[label] = (k, float(np.median(ts)))
+    (k, t), (k1, t1) = med["all"], med["one"]
+    return {"value": g.n * k / t, "unit": "spin-updates/s", "cores": oracle.max_threads(), "kind": "oracle",
+            "sample": f"first {k} of the {temps.size} sweeps of the same workload (n={g.n}), C oracle with "
+                      f"OpenMP over each colour class, sweep loop timed, median of {reps}: {t:.2f} s",
+            "cpu_model": cpu_model(), "median_of": reps,
+            "one_thread": {"value": g.n * k1 / t1, "sweeps": k1, "median_s": t1}}
+
+
+def gpu_runs(ann, temps, seed, out_ptr, reps):
+    """Device time (ms) of reps anneals of the whole schedule after one warm-up."""
+    ann.anneal_dev(temps, seed, out_ptr)
+    ann.result()
+    ms = []
+    for _ in range(reps):
+        ann.anneal_dev(temps, seed, out_ptr)
+        ms.append(ann.result().sweep_ms)
+    return ms
+
+
+def layout_variants(gdi, g, temps, seed, torch, reps=3):
+    """The same 1M-node anneal with the unit-weight form switched off (the packed entries'
+    11-bit weights summed as general weights) and with the uncompressed layout (int32
+    column + int32 weight per entry, spins gathered from global memory, fenced grid
+    sweep). Same results; device time of the sweep launch, median of reps."""
+    import numpy as np
+
+    out = {}
+    d_out = torch.empty(g.n, dtype=torch.int8, device="cuda:0")
+    bpl = algorithmic_bytes_per_sweep(g.n, g.nnz) * temps.size
+    for name, tune in (("packed_general_weights", dict(general_weights=1)),
+                       ("uncompressed_int32_col_weight", dict(scope=gdi.SCOPE_GRID_FENCED))):
+        with gdi.Annealer(g) as a:
+            a.set_stream(torch.cuda.current_stream().cuda_stream)
+            a.tune(**tune)
+            ms = float(np.median(gpu_runs(a, temps, seed, d_out.data_ptr(), reps)))
+            r = a.result()
+        out[name] = {"kernel_ms": ms, "algorithmic_gbs": bpl / (ms / 1e3) / 1e9,
+                     "spin_updates_per_s": g.n * temps.size / (ms / 1e3), "scope": int(r.scope),
+                     "M": int(r.magnetization), "cut": int(r.cut_weighted)}
+    return out
+
+
+def config_runs(gdi, gs, torch, seed, names, reps=5):
+    """Configurations measured beside the headline: device time of the whole schedule
+    (median of reps), the oracle's sweep loop on the full schedule for the small ones
+    (all host threads), and whether the GPU's final state equals the oracle's."""
+    import numpy as np
+
+    import oracle
+
+    out = {}
+    for name in names:
+        g, T = gs.workload(name)
+        d_out = torch.empty(g.n, dtype=torch.int8, device="cuda:0")
+        with gdi.Annealer(g) as a:
+            a.set_stream(torch.cuda.current_stream().cuda_stream)
+            ms = float(np.median(gpu_runs(a, T, seed, d_out.data_ptr(), reps)))
+            r = a.result()
+            cw, ce, m = a.cut_dev(d_out.data_ptr())
+        kern_s = ms / 1e3
+        row = {"n": g.n, "nnz": g.nnz, "sweeps": int(T.size), "scope": int(r.scope), "grid": int(r.grid),
+               "colours": int(r.n_colours), "kernel_ms": ms, "sweeps_per_s": T.size / kern_s,
+               "spin_updates_per_s": g.n * T.size / kern_s,
+               "algorithmic_gbs": algorithmic_bytes_per_sweep(g.n, g.nnz) * T.size / kern_s / 1e9,
+               "M": int(m), "cut_weighted": int(cw), "cut_edges": int(ce)}
+        if g.n <= 100_000:
+            ref = oracle.anneal(g, T, seed)
+            row["oracle_sweep_s"] = ref["sweep_s"]
+            row["oracle_spin_updates_per_s"] = g.n * T.size / ref["sweep_s"]
+            row["oracle_threads"] = oracle.max_threads()
+            spins = d_out.cpu().numpy()
+            row["bit_exact_vs_oracle"] = bool(np.array_equal(spins, ref["spins"]) and int(m) == ref["M"]
+                                              and int(cw) == ref["cut"])
+        out[name] = row
+    return out
 
 
 def best_state(Ms, cuts, A=1, B=1):
@@ -201,23 +291,27 @@ def forms_standard(gdi, gs, sweeps=50):
 
 def forms_racy(gdi, gs, seed, runs=3):
     """Price of determinism on the 1M-node RGG: the deterministic colour-phase sweep
-    against Alg. 3's asynchronous racy sweep (one launch per sweep, no phases)."""
+    against Alg. 3 as printed (asynchronous, per-thread reads of G and one atomic add per
+    flip, one persistent launch) with every co-resident workgroup and with 8 workgroups
+    (fewer nodes in flight, so more of them see their neighbours' new spins)."""
     import numpy as np
 
     g, T = gs.workload("rgg1m")
     out = {}
     with gdi.Annealer(g) as a:
-        for name, flags in (("deterministic", 0), ("racy", gdi.FLAG_RACY)):
+        for name, flags, grid in (("deterministic", 0, 0), ("asynchronous", gdi.FLAG_RACY, 0),
+                                  ("asynchronous_8wg", gdi.FLAG_RACY, 8)):
+            a.tune(grid=grid)
             a.anneal(T[:10], seed, flags=flags)
             ms, cuts, Ms = [], [], []
             for r in range(runs):
-                t0 = time.perf_counter()
                 res = a.anneal(T, seed, replica=r, flags=flags)
-                ms.append((time.perf_counter() - t0) * 1e3)
+                ms.append(res["result"]["sweep_ms"])
                 cuts.append(res["cut"])
                 Ms.append(res["M"])
-            out[name] = {"mean_ms": float(np.mean(ms)), "cuts": [int(c) for c in cuts], "M": [int(m) for m in Ms]}
-    out["racy_speedup"] = out["deterministic"]["mean_ms"] / out["racy"]["mean_ms"]
+            out[name] = {"mean_kernel_ms": float(np.mean(ms)), "cuts": [int(c) for c in cuts],
+                         "M": [int(m) for m in Ms], "grid": int(res["result"]["grid"])}
+    out["random_state_cut"] = int(g.nnz // 4)
     return out
 
 
@@ -228,7 +322,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rgg1m")
     ap.add_argument("--sweeps", type=int, default=0, help="override the schedule length")
-    ap.add_argument("--cpu-sweeps", type=int, default=2000)
+    ap.add_argument("--cpu-sweeps", type=int, default=1000, help="oracle sweeps timed on all host threads")
+    ap.add_argument("--cpu-sweeps-one", type=int, default=100, help="oracle sweeps timed on one thread")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other configurations and layouts")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched / learned comparisons")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
@@ -304,6 +400,8 @@ def main():
             src = hashlib.sha256(f.read()).hexdigest()[:16]
         if tj.get("workload") == args.workload and tj.get("kernel_source_sha256_16") == src:
             traffic = tj["hbm_bytes_per_sweep"] * S
+    counter_gbs = traffic / kern_s / 1e9 if traffic is not None else None
+    grid_phases = int(info.n_colours)
     line = {
         "metric": METRIC,
         "value": value,
@@ -324,10 +422,16 @@ def main():
             "lanes_per_node": int(res.lanes_per_node), "parallelism": "single-gpu",
         },
         "sweeps_per_s": S * args.steps / elapsed,
-        "hbm_gbs": achieved,
+        # HBM bytes the counters saw per launch over the kernel's time (null without counters
+        # for this kernel source); the algorithmic figure is roofline.achieved
+        "hbm_gbs": counter_gbs,
+        "algorithmic_gbs": achieved,
+        "us_per_phase": kern_s * 1e6 / (S * grid_phases),
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "achieved_counters_gbs": counter_gbs,
+            "frac_counters": counter_gbs / HBM_PEAK_GBS if counter_gbs is not None else None,
             "kernel": {gdi.SCOPE_GRID: "k_sweep_halo", gdi.SCOPE_GRID_FENCED: "k_sweep_grid"}.get(res.scope, "k_sweep_wg"),
             "entry_layout": ("packed 32-bit CSR entries (16-bit LDS word, 11-bit weight, 5-bit bit position); "
                              "achieved counts the algorithmic 8 bytes per entry, traffic the bytes the counters saw")
@@ -338,13 +442,18 @@ def main():
                    "tracked_cut": int(res.cut_weighted), "create_s": create_s},
     }
     ann.close()
+    if not args.no_configs and args.workload == "rgg1m":
+        line["layouts_rgg1m"] = layout_variants(gdi, g, temps, seed, torch)
+    if not args.no_configs:
+        line["configs"] = config_runs(gdi, gs, torch, seed, [w for w in ("er800", "torus100", "rgg8m")
+                                                             if w != args.workload])
     if not args.no_forms:
         line["forms"] = forms_batched(gdi, gs, torch, seed)
         line["forms"]["learned_rgg200k"] = forms_learned(gdi, gs, torch, seed)
         line["forms"]["gdi_vs_standard_torus"] = forms_standard(gdi, gs)
         line["forms"]["determinism_rgg1m"] = forms_racy(gdi, gs, seed)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(g, temps, seed, min(args.cpu_sweeps, S))
+        line["cpu_baseline"] = cpu_baseline(g, temps, seed, min(args.cpu_sweeps, S), min(args.cpu_sweeps_one, S))
     print(json.dumps(line), flush=True)
 
 

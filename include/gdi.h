@@ -78,8 +78,9 @@ typedef struct gdi_graph gdi_graph;
 
 /* Acceptance rules. Metropolis: flip iff dE <= 0 or x0 < floor(2^32 exp(-dE/T_t)).
  * Paper (Sec. V, Alg. 2/3): the spin first takes the value that minimises its local
- * energy (flip iff dE < 0), then flips with probability P_f(t): flip iff
- * (dE < 0) != (x0 < min(2^32 - 1, floor(2^32 P_f(t)))). */
+ * energy (flip iff dE < 0; at dE = 0 the value is random, Sec. III: +1 iff Philox
+ * word x2 is odd), then flips with probability P_f(t): flip iff
+ * argmin_flips != (x0 < min(2^32 - 1, floor(2^32 P_f(t)))). */
 #define GDI_ACCEPT_METROPOLIS 0u
 #define GDI_ACCEPT_PAPER 1u
 
@@ -107,10 +108,15 @@ typedef struct {
  * one workgroup (n_pad <= 65536) only; GDI_ERANGE otherwise. */
 #define GDI_FLAG_DENSE_BALANCE 1u
 
-/* Alg. 3 as printed, asynchronous and racy: all nodes of a sweep decide in one launch
- * against whatever neighbour spins and magnetisation they read, without colour phases
- * or a gate; results are NOT reproducible (for pricing determinism). The returned M
- * and cut are recounted from the final spins. No traces. */
+/* Alg. 3 as printed (Sec. V-C), asynchronous and racy, in one persistent launch: every
+ * sweep, each thread takes its nodes in turn, reads the neighbour spins and the global
+ * magnetisation G as it finds them (other nodes may or may not have flipped yet), and
+ * when its spin flips stores it and adds the change to G with one atomic add; a
+ * device-wide barrier separates sweeps. No colour phases, no gate; results are NOT
+ * reproducible (for pricing determinism). The returned M is G as the atomic adds left
+ * it (equal to the sum of the final spins); the cut is recounted from the final spins.
+ * tuning.grid (0 = every co-resident workgroup of 1024 threads) sets how many nodes are
+ * in flight at once. No traces. */
 #define GDI_FLAG_RACY 2u
 
 /* Launch tuning; zero fields mean "choose automatically". */
@@ -130,6 +136,9 @@ typedef struct {
                                  phase sums of their XCD (blocks 0..7) hold no nodes, so
                                  that no node work queues ahead of their polls; < 0 =
                                  they hold nodes like every workgroup; 0 = automatic */
+    int32_t general_weights;  /* GDI_SCOPE_GRID: > 0 = run the general-weight form of the
+                                 sweep even when every weight is 1 (for measuring what the
+                                 unit-weight form saves; same results); 0 = automatic */
 } gdi_tuning;
 
 /* Outcome of the last anneal on a handle. */

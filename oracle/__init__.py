@@ -165,7 +165,7 @@ def anneal(g, temps, seed: int, A: int = 1, B: int = 1, replica: int = 0, mode: 
     pm = np.zeros(S * C, dtype=np.int64) if phase_trace else None
     pc = np.zeros(S * C, dtype=np.int64) if phase_trace else None
     ps = np.zeros((S * C, g.n), dtype=np.int8) if phase_spins else None
-    res = np.zeros(4, dtype=np.int64)
+    res = np.zeros(5, dtype=np.int64)
     sk = None if skip is None else np.ascontiguousarray(skip, dtype=np.uint8)
     if last_flip is not None and (last_flip.dtype != np.int32 or not last_flip.flags.c_contiguous):
         raise TypeError("last_flip must be a contiguous int32 array")
@@ -174,7 +174,8 @@ def anneal(g, temps, seed: int, A: int = 1, B: int = 1, replica: int = 0, mode: 
                              _p(last_flip))
     if rc != 0:
         raise RuntimeError(f"oracle_anneal failed: {rc}")
-    out = dict(spins=spins, M=int(res[0]), cut=int(res[1]), C=int(res[2]), flips=int(res[3]))
+    out = dict(spins=spins, M=int(res[0]), cut=int(res[1]), C=int(res[2]), flips=int(res[3]),
+               sweep_s=float(res[4]) * 1e-9)
     if trace:
         out["trace_m"], out["trace_cut"] = tm, tc
     if phase_trace:

@@ -203,7 +203,8 @@ typedef struct {
  *   trace_m/trace_cut  optional, n_sweeps entries: M and cut after sweep t
  *   phase_m/phase_cut  optional, n_sweeps*C entries: M and cut after each phase
  *   phase_spins optional, n_sweeps*C*n spins after each phase (small n only)
- *   result[0..3] = final M, final cut (tracked), number of colours, total flips
+ *   result[0..4] = final M, final cut (tracked), number of colours, total flips,
+ *                  wall time of the sweep loop in nanoseconds (timing only)
  *   skip        optional, n bytes: a node with a non-zero byte makes no decision in
  *               these sweeps (it keeps its spin and draws nothing) but still counts
  *               in M and in its class's over-side count
@@ -277,6 +278,7 @@ int oracle_anneal(int32_t n, const int32_t *row_ptr, const int32_t *col, const i
     thr = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(thr_cap + 1));
     if (!thr) { rc = OR_ENOMEM; goto done; }
     int64_t total_flips = 0;
+    const double wall0 = omp_get_wtime();
 
     for (int32_t t = p->start_sweep; t < p->n_sweeps; ++t) {
         int64_t width = 0;
@@ -354,12 +356,14 @@ int oracle_anneal(int32_t n, const int32_t *row_ptr, const int32_t *col, const i
         if (trace_m) trace_m[t] = M;
         if (trace_cut) trace_cut[t] = cut;
     }
+    const double wall1 = omp_get_wtime();
     memcpy(spins_out, s, (size_t)n);
     if (result) {
         result[0] = M;
         result[1] = cut;
         result[2] = C;
         result[3] = total_flips;
+        result[4] = (int64_t)((wall1 - wall0) * 1e9);
     }
 done:
     free(thr);

@@ -63,7 +63,7 @@ class Schedule(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("scope", ctypes.c_uint32), ("block", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("lanes_per_node", ctypes.c_uint32), ("tail_max", ctypes.c_int32), ("spin_limit", ctypes.c_uint64),
-                ("leaders", ctypes.c_int32)]
+                ("leaders", ctypes.c_int32), ("general_weights", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -208,11 +208,11 @@ def set_stream(h, stream_ptr: int | None):
 
 
 def set_tuning(h, scope: int = 0, block: int = 0, grid: int = 0, lanes_per_node: int = 0,
-               spin_limit: int = 0, tail_max: int = 0, leaders: int = 0, reset=False):
+               spin_limit: int = 0, tail_max: int = 0, leaders: int = 0, general_weights: int = 0, reset=False):
     if reset:
         _check(lib().gdi_set_tuning(h, None))
         return
-    t = Tuning(scope, block, grid, lanes_per_node, tail_max, spin_limit, leaders)
+    t = Tuning(scope, block, grid, lanes_per_node, tail_max, spin_limit, leaders, general_weights)
     _check(lib().gdi_set_tuning(h, ctypes.byref(t)))
 
 

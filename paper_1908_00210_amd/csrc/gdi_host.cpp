@@ -76,11 +76,7 @@ struct gdi_graph {
     int64_t max_abs_wdeg = 0;
     int32_t max_degree = 0;
     std::vector<int32_t> colour;      // original order
-    std::vector<int32_t> cbeg, csz;   // per class, new ids
-    std::vector<int32_t> orig;        // new -> original (-1 padding)
-    std::vector<int32_t> h_rp;        // new-id CSR kept on the host for launch layouts
-    std::vector<int2> h_adj;
-    std::vector<int32_t> cls;         // class of each new id (-1 padding)
+    gdi_layout::Relabelled rl;        // colour-major relabelling; new-id CSR kept for launch layouts
 
     // halo layout for one grid size (k_sweep_halo)
     int32_t halo_G = 0, halo_nwork = 0, halo_lead = 0;
@@ -137,67 +133,9 @@ namespace {
 int validate_csr(const int32_t *rp, const int32_t *col, const int32_t *w, int32_t n, int64_t *max_wdeg,
                  int32_t *max_deg)
 {
-    if (!rp || !col || !w) return fail(GDI_EINVAL, "NULL CSR array");
-    if (n < 2) return fail(GDI_EINVAL, "n must be >= 2");
-    if (rp[0] != 0) return fail(GDI_EINVAL, "row_ptr[0] must be 0");
-    for (int32_t i = 0; i < n; ++i)
-        if (rp[i + 1] < rp[i])
-            return fail(GDI_EINVAL, "row_ptr is decreasing at row " + std::to_string(i));
-    int64_t mw = 0;
-    int32_t md = 0;
-    for (int32_t i = 0; i < n; ++i) {
-        int64_t s = 0;
-        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-            const int32_t j = col[k];
-            if (j < 0 || j >= n)
-                return fail(GDI_EINVAL, "column out of range in row " + std::to_string(i));
-            if (j == i) return fail(GDI_EINVAL, "self-loop at node " + std::to_string(i));
-            if (k > rp[i] && col[k - 1] >= j)
-                return fail(GDI_EINVAL, "columns not strictly increasing (or duplicate) in row " +
-                                            std::to_string(i));
-            s += std::llabs((long long)w[k]);
-        }
-        if (s > (int64_t(1) << 30))
-            return fail(GDI_ERANGE, "sum of |weights| exceeds 2^30 at node " + std::to_string(i));
-        mw = std::max(mw, s);
-        md = std::max(md, rp[i + 1] - rp[i]);
-    }
-    // symmetry: every (i, j, w) has its mirror (j, i, w); rows are sorted, so binary search
-    for (int32_t i = 0; i < n; ++i) {
-        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-            const int32_t j = col[k];
-            const int32_t *b = col + rp[j], *e = col + rp[j + 1];
-            const int32_t *f = std::lower_bound(b, e, i);
-            if (f == e || *f != i)
-                return fail(GDI_EINVAL, "edge (" + std::to_string(i) + "," + std::to_string(j) +
-                                            ") has no mirror");
-            if (w[f - col] != w[k])
-                return fail(GDI_EINVAL, "edge (" + std::to_string(i) + "," + std::to_string(j) +
-                                            ") has a different mirror weight");
-        }
-    }
-    *max_wdeg = mw;
-    *max_deg = md;
-    return GDI_OK;
-}
-
-// First-fit greedy colouring in ascending node id. used[c] == i marks colour c as
-// taken by an already coloured neighbour of node i.
-int32_t colour_first_fit(const int32_t *rp, const int32_t *col, int32_t n, int32_t *colour)
-{
-    std::vector<int32_t> used((size_t)n + 1, -1);
-    int32_t ncol = 0;
-    for (int32_t i = 0; i < n; ++i) {
-        for (int32_t k = rp[i]; k < rp[i + 1]; ++k) {
-            const int32_t j = col[k];
-            if (j < i) used[(size_t)colour[j]] = i;
-        }
-        int32_t c = 0;
-        while (used[(size_t)c] == i) ++c;
-        colour[i] = c;
-        ncol = std::max(ncol, c + 1);
-    }
-    return ncol;
+    std::string msg;
+    const int rc = gdi_layout::validate_csr(rp, col, w, n, max_wdeg, max_deg, &msg);
+    return rc ? fail(rc, msg) : GDI_OK;
 }
 
 uint32_t threshold_of(int64_t d, double T)
@@ -317,51 +255,15 @@ int check_device()
 
 int upload(gdi_graph *g, const int32_t *rp, const int32_t *col, const int32_t *w)
 {
+    std::string msg;
+    if (int rc = gdi_layout::relabel(rp, col, w, g->n, g->colour.data(), g->C, &g->rl, &msg)) return fail(rc, msg);
+    g->n_pad = g->rl.n_pad;
+    const std::vector<int32_t> &nrp = g->rl.rp;
+    const std::vector<gdi_layout::Edge> &adj = g->rl.adj;
     const int32_t n = g->n;
-    // colour-major relabel: class c in ascending original id, class starts aligned
-    std::vector<int32_t> cnt((size_t)g->C, 0);
-    for (int32_t i = 0; i < n; ++i) cnt[(size_t)g->colour[i]]++;
-    g->cbeg.assign((size_t)g->C, 0);
-    g->csz = cnt;
-    int64_t pos = 0;
-    for (int32_t c = 0; c < g->C; ++c) {
-        g->cbeg[(size_t)c] = (int32_t)pos;
-        pos += cnt[(size_t)c];
-        pos = (pos + GDI_CLASS_ALIGN - 1) / GDI_CLASS_ALIGN * GDI_CLASS_ALIGN;
-    }
-    if (pos > INT32_MAX - 1) return fail(GDI_ERANGE, "padded node count exceeds int32");
-    g->n_pad = (int32_t)pos;
-    std::vector<int32_t> inv((size_t)n);
-    g->orig.assign((size_t)g->n_pad, -1);
-    std::vector<int32_t> fillc((size_t)g->C, 0);
-    for (int32_t i = 0; i < n; ++i) {
-        const int32_t c = g->colour[i];
-        const int32_t v = g->cbeg[(size_t)c] + fillc[(size_t)c]++;
-        inv[(size_t)i] = v;
-        g->orig[(size_t)v] = i;
-    }
-    std::vector<int32_t> nrp((size_t)g->n_pad + 1, 0);
-    for (int32_t v = 0; v < g->n_pad; ++v) {
-        const int32_t o = g->orig[(size_t)v];
-        nrp[(size_t)v + 1] = nrp[(size_t)v] + (o >= 0 ? rp[o + 1] - rp[o] : 0);
-    }
-    std::vector<int2> adj((size_t)g->nnz);
-    std::vector<std::pair<int32_t, int32_t>> row;
-    for (int32_t v = 0; v < g->n_pad; ++v) {
-        const int32_t o = g->orig[(size_t)v];
-        if (o < 0) continue;
-        row.clear();
-        for (int32_t k = rp[o]; k < rp[o + 1]; ++k) row.emplace_back(inv[(size_t)col[k]], w[k]);
-        std::sort(row.begin(), row.end());
-        int64_t base = nrp[(size_t)v];
-        for (size_t q = 0; q < row.size(); ++q) adj[(size_t)base + q] = make_int2(row[q].first, row[q].second);
-    }
-    g->cls.assign((size_t)g->n_pad, -1);
-    for (int32_t c = 0; c < g->C; ++c)
-        for (int32_t k = 0; k < g->csz[(size_t)c]; ++k) g->cls[(size_t)(g->cbeg[(size_t)c] + k)] = c;
     HIP_TRY(g->d_rp.reserve(nrp.size()), "hipMalloc row_ptr");
     HIP_TRY(g->d_adj.reserve(adj.size()), "hipMalloc adjacency");
-    HIP_TRY(g->d_orig.reserve(g->orig.size()), "hipMalloc orig");
+    HIP_TRY(g->d_orig.reserve(g->rl.orig.size()), "hipMalloc orig");
     HIP_TRY(g->d_cbeg.reserve((size_t)g->C), "hipMalloc classes");
     HIP_TRY(g->d_csz.reserve((size_t)g->C), "hipMalloc classes");
     HIP_TRY(g->d_P.reserve((size_t)g->C + 2), "hipMalloc P");
@@ -371,256 +273,67 @@ int upload(gdi_graph *g, const int32_t *rp, const int32_t *col, const int32_t *w
     HIP_TRY(g->d_red.reserve(4), "hipMalloc state");
     HIP_TRY(hipMemcpy(g->d_rp.p, nrp.data(), nrp.size() * 4, hipMemcpyHostToDevice), "upload row_ptr");
     if (!adj.empty())
-        HIP_TRY(hipMemcpy(g->d_adj.p, adj.data(), adj.size() * sizeof(int2), hipMemcpyHostToDevice),
+        HIP_TRY(hipMemcpy(g->d_adj.p, adj.data(), adj.size() * sizeof(gdi_layout::Edge), hipMemcpyHostToDevice),
                 "upload adjacency");
-    HIP_TRY(hipMemcpy(g->d_orig.p, g->orig.data(), g->orig.size() * 4, hipMemcpyHostToDevice), "upload orig");
-    HIP_TRY(hipMemcpy(g->d_cbeg.p, g->cbeg.data(), g->cbeg.size() * 4, hipMemcpyHostToDevice), "upload classes");
-    HIP_TRY(hipMemcpy(g->d_csz.p, g->csz.data(), g->csz.size() * 4, hipMemcpyHostToDevice), "upload classes");
+    HIP_TRY(hipMemcpy(g->d_orig.p, g->rl.orig.data(), g->rl.orig.size() * 4, hipMemcpyHostToDevice), "upload orig");
+    HIP_TRY(hipMemcpy(g->d_cbeg.p, g->rl.cbeg.data(), g->rl.cbeg.size() * 4, hipMemcpyHostToDevice), "upload classes");
+    HIP_TRY(hipMemcpy(g->d_csz.p, g->rl.csz.data(), g->rl.csz.size() * 4, hipMemcpyHostToDevice), "upload classes");
     HIP_TRY(hipEventCreate(&g->ev0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&g->ev1), "hipEventCreate");
-    g->h_rp.swap(nrp);
-    g->h_adj.swap(adj);
     return GDI_OK;
 }
 
-// Workgroup b handles chunk q(b) of every class; consecutive block ids are spread
-// over the 8 XCDs, so XCD x gets a contiguous chunk range. With `lead` dedicated
-// group leaders (8, blocks 0..7, one per XCD) those hold no chunk (-1) and the other
-// G - lead blocks share the chunks.
-inline int32_t chunk_of_block(int32_t b, int32_t G, int32_t lead)
-{
-    if (b < lead) return -1;
-    const int32_t Gw = G - lead, bw = b - lead;  // bw % 8 == b % 8
-    return (Gw % 8 == 0) ? (bw % 8) * (Gw / 8) + bw / 8 : bw;
-}
-
-// Packed halo CSR entry from an LDS bit index lb: (lb / 32) << 16 | the weight's low 11
-// bits << 5 | lb % 32.
-inline uint32_t pack_entry(int32_t lb, int32_t w)
-{
-    return ((uint32_t)(lb >> 5) << 16) | (((uint32_t)w & 0x7FFu) << 5) | ((uint32_t)lb & 31u);
-}
-
-// Halo layout with the tail starting at class T0 (T0 == C: none).
+// Halo layout with the tail starting at class T0 (T0 == C: none), uploaded.
 int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0, int32_t lead)
 {
-    const int32_t C = g->C;
-    g->halo_unit_w = 1;
-    for (const int2 &e : g->h_adj) {
-        if (e.y < -GDI_HALO_WMAX - 1 || e.y > GDI_HALO_WMAX) {
-            g->halo_lds_words = -3;  // weights beyond the packed entries' range
-            return GDI_OK;
-        }
-        if (e.y != 1) g->halo_unit_w = 0;
-    }
-    const int32_t Gw = G - lead;  // blocks holding nodes
-    std::vector<int32_t> chunk((size_t)C), blk_of_q((size_t)Gw);
-    for (int32_t b = lead; b < G; ++b) blk_of_q[(size_t)chunk_of_block(b, G, lead)] = b;
-    for (int32_t c = 0; c < C; ++c) {
-        const int64_t per = ((int64_t)g->csz[(size_t)c] + Gw - 1) / Gw;
-        chunk[(size_t)c] = (int32_t)std::max<int64_t>(GDI_CLASS_ALIGN, (per + GDI_CLASS_ALIGN - 1) / GDI_CLASS_ALIGN * GDI_CLASS_ALIGN);
-    }
-    const size_t GC = (size_t)G * (size_t)C;
-    std::vector<GdiHaloEntry> tab(GC);
-    std::vector<int32_t> wlo(GC, INT32_MAX), whi(GC, -1);
-    for (int32_t b = 0; b < G; ++b) {
-        const int32_t q = chunk_of_block(b, G, lead);
-        for (int32_t c = 0; c < C; ++c) {
-            GdiHaloEntry &e = tab[(size_t)b * C + c];
-            std::memset(&e, 0, sizeof(e));
-            if (c >= T0 || q < 0) continue;  // tail classes and dedicated leaders: no own chunks
-            const int64_t lo = (int64_t)g->cbeg[(size_t)c] + (int64_t)q * chunk[(size_t)c];
-            const int64_t hi = std::min<int64_t>((int64_t)g->cbeg[(size_t)c] + g->csz[(size_t)c], lo + chunk[(size_t)c]);
-            if (lo < hi) {
-                e.node_lo = (int32_t)lo;
-                e.node_hi = (int32_t)hi;
-                const size_t i = (size_t)b * C + c;
-                wlo[i] = std::min<int32_t>(wlo[i], (int32_t)(lo >> 5));
-                whi[i] = std::max<int32_t>(whi[i], (int32_t)((hi + 31) >> 5));
-            }
-        }
-    }
-    auto owner = [&](int32_t v) {
-        const int32_t c = g->cls[(size_t)v];
-        return blk_of_q[(size_t)((v - g->cbeg[(size_t)c]) / chunk[(size_t)c])];
-    };
-    // gather lists: the packed words of classes < T0 that tail nodes read
-    std::vector<std::vector<int32_t>> gat((size_t)T0);
-    for (int32_t v = 0; v < g->n_pad; ++v) {
-        const int32_t cv = g->cls[(size_t)v];
-        if (cv < 0) continue;
-        for (int32_t k = g->h_rp[(size_t)v]; k < g->h_rp[(size_t)v + 1]; ++k) {
-            const int32_t j = g->h_adj[(size_t)k].x;
-            const int32_t cj = g->cls[(size_t)j];
-            if (cj >= T0) continue;  // tail neighbours live in the tail region
-            if (cv >= T0) {
-                gat[(size_t)cj].push_back(j >> 5);
-                continue;
-            }
-            const size_t i = (size_t)owner(v) * C + cj;
-            wlo[i] = std::min<int32_t>(wlo[i], j >> 5);
-            whi[i] = std::max<int32_t>(whi[i], (j >> 5) + 1);
-        }
-    }
-    std::vector<int32_t> gat_beg((size_t)T0 + 1, 0), gat_words;
-    for (int32_t c = 0; c < T0; ++c) {
-        std::vector<int32_t> &L = gat[(size_t)c];
-        std::sort(L.begin(), L.end());
-        L.erase(std::unique(L.begin(), L.end()), L.end());
-        gat_words.insert(gat_words.end(), L.begin(), L.end());
-        gat_beg[(size_t)c + 1] = (int32_t)gat_words.size();
-    }
-    int32_t lds_words = 0;
-    for (int32_t b = 0; b < G; ++b) {
-        int32_t off = 0;
-        for (int32_t c = 0; c < C; ++c) {
-            const size_t i = (size_t)b * C + c;
-            GdiHaloEntry &e = tab[i];
-            if (whi[i] < 0) {
-                e.win_lo = 0;
-                e.win_len = 0;
-            } else {
-                e.win_lo = wlo[i];
-                e.win_len = whi[i] - wlo[i];
-            }
-            e.lds_off = off;
-            off += e.win_len;
-        }
-        lds_words = std::max(lds_words, off);
-    }
-    const int32_t tail_base = T0 < C ? g->cbeg[(size_t)T0] : g->n_pad;  // multiple of 64
-    int32_t tail_n = 0, tail_nnz = 0;
-    for (int32_t c = T0; c < C; ++c) {
-        tail_n += g->csz[(size_t)c];
-        for (int32_t v = g->cbeg[(size_t)c]; v < g->cbeg[(size_t)c] + g->csz[(size_t)c]; ++v)
-            tail_nnz += g->h_rp[(size_t)v + 1] - g->h_rp[(size_t)v];
-    }
-    // LDS image: windows | gather words | tail spin bits | tail row offsets | tail entries
-    const int32_t gather_off = lds_words;
-    const int32_t tail_off = gather_off + (int32_t)gat_words.size();
-    const int32_t trp_off = tail_off + (g->n_pad - tail_base) / 32;
-    const int32_t tent_off = (trp_off + (T0 < C ? tail_n + 1 : 0) + 1) & ~1;  // 8-byte aligned
-    lds_words = tent_off + 2 * tail_nnz;
-    // (packed entries hold LDS word indices in 16 bits)
-    if (gdi_halo_lds_bytes(lds_words, C, 0) > lds_budget || lds_words > 65536) {
-        g->halo_lds_words = -2;
+    gdi_layout::HaloLayout L;
+    std::string msg;
+    if (int rc = gdi_layout::halo_layout(g->rl, g->C, G, lds_budget, T0, lead, &L, &msg)) return fail(rc, msg);
+    g->halo_unit_w = L.unit_w;
+    if (L.status) {
+        g->halo_lds_words = L.status;
         return GDI_OK;
     }
-    auto tail_lb = [&](int32_t j) { return (tail_off + ((j - tail_base) >> 5)) * 32 + (j & 31); };
-    auto gather_lb = [&](int32_t j) {
-        const int32_t c = g->cls[(size_t)j];
-        const auto b0 = gat_words.begin() + gat_beg[(size_t)c], b1 = gat_words.begin() + gat_beg[(size_t)c + 1];
-        const auto it = std::lower_bound(b0, b1, j >> 5);
-        if (it == b1 || *it != (j >> 5)) return -1;  // rejected by the range check below
-        return (gather_off + (int32_t)(it - gat_words.begin())) * 32 + (j & 31);
-    };
-    std::vector<int32_t> tail_v, tail_beg((size_t)(C - T0) + 1, 0), tail_rp(1, 0);
-    std::vector<uint32_t> tail_ent;
-    for (int32_t c = T0; c < C; ++c) {
-        for (int32_t v = g->cbeg[(size_t)c]; v < g->cbeg[(size_t)c] + g->csz[(size_t)c]; ++v) {
-            tail_v.push_back(v);
-            for (int32_t k = g->h_rp[(size_t)v]; k < g->h_rp[(size_t)v + 1]; ++k) {
-                const int32_t j = g->h_adj[(size_t)k].x;
-                const int32_t lb = g->cls[(size_t)j] >= T0 ? tail_lb(j) : gather_lb(j);
-                if (lb < 0 || lb >= trp_off * 32) return fail(GDI_EDEVICE, "internal error: tail index out of range");
-                tail_ent.push_back(pack_entry(lb, g->h_adj[(size_t)k].y));
-            }
-            tail_rp.push_back((int32_t)tail_ent.size());
-        }
-        tail_beg[(size_t)(c - T0) + 1] = (int32_t)tail_v.size();
-    }
-    // after the last row: GDI_HALO_PF zero entries; the sweep reads GDI_HALO_PF entries
-    // from any row start, so these keep it in bounds
-    std::vector<uint32_t> adjL(g->h_adj.size() + GDI_HALO_PF, 0u);
-    for (int32_t v = 0; v < g->n_pad; ++v) {
-        const int32_t cv = g->cls[(size_t)v];
-        if (cv < 0) continue;
-        const int32_t b = cv < T0 ? owner(v) : -1;
-        for (int32_t k = g->h_rp[(size_t)v]; k < g->h_rp[(size_t)v + 1]; ++k) {
-            const int32_t j = g->h_adj[(size_t)k].x;
-            const int32_t cj = g->cls[(size_t)j];
-            int32_t lb;
-            if (cj >= T0) {
-                lb = tail_lb(j);
-            } else if (cv >= T0) {
-                lb = gather_lb(j);
-            } else {
-                const GdiHaloEntry &e = tab[(size_t)b * C + cj];
-                lb = (e.lds_off + (j >> 5) - e.win_lo) * 32 + (j & 31);
-            }
-            // every index must land inside this workgroup's LDS image (checked here so
-            // that a layout error surfaces as an error code, never as a device fault)
-            if (lb < 0 || lb >= lds_words * 32) return fail(GDI_EDEVICE, "internal error: halo index out of range");
-            adjL[(size_t)k] = pack_entry(lb, g->h_adj[(size_t)k].y);
-        }
-    }
-    // Rows longer than GDI_HALO_PF keep their entries from GDI_HALO_PF - 1 on in an
-    // overflow region at the end of the owner workgroup's LDS image, and the row's entry
-    // GDI_HALO_PF - 1 then holds the LDS word where they start, so that no row needs a
-    // second trip to memory. Only when every workgroup's region fits beside its image;
-    // otherwise the sweep reads those entries from the packed CSR.
-    std::vector<std::vector<uint32_t>> ovf((size_t)G);
-    std::vector<std::pair<size_t, int32_t>> links;  // (entry index, position in the owner's region)
-    for (int32_t v = 0; v < g->n_pad; ++v) {
-        const int32_t cv = g->cls[(size_t)v];
-        const int32_t r0 = g->h_rp[(size_t)v], r1 = g->h_rp[(size_t)v + 1];
-        if (cv < 0 || cv >= T0 || r1 - r0 <= GDI_HALO_PF) continue;
-        std::vector<uint32_t> &L = ovf[(size_t)owner(v)];
-        links.emplace_back((size_t)r0 + GDI_HALO_PF - 1, (int32_t)L.size());
-        L.insert(L.end(), adjL.begin() + r0 + GDI_HALO_PF - 1, adjL.begin() + r1);
-    }
-    int64_t ovf_max = 0;
-    for (const auto &L : ovf) ovf_max = std::max<int64_t>(ovf_max, (int64_t)L.size());
-    int32_t ovf_len = 0;
-    const int32_t ovf_off = lds_words;
-    if (ovf_max > 0 && ovf_max < INT32_MAX / 8 &&
-        gdi_halo_lds_bytes(lds_words + (int32_t)ovf_max, C, 0) <= lds_budget) {
-        ovf_len = (int32_t)ovf_max;
-        lds_words += ovf_len;
-        for (const auto &l : links) adjL[l.first] = (uint32_t)(ovf_off + l.second);
-    }
-    std::vector<uint32_t> ovf_flat((size_t)G * (size_t)ovf_len, 0u);
-    for (int32_t b = 0; b < G && ovf_len > 0; ++b)
-        std::copy(ovf[(size_t)b].begin(), ovf[(size_t)b].end(), ovf_flat.begin() + (size_t)b * ovf_len);
-    HIP_TRY(g->d_ovf.reserve(std::max<size_t>(ovf_flat.size(), 1)), "hipMalloc halo overflow");
-    if (!ovf_flat.empty())
-        HIP_TRY(hipMemcpy(g->d_ovf.p, ovf_flat.data(), ovf_flat.size() * 4, hipMemcpyHostToDevice),
-                "upload halo overflow");
-    HIP_TRY(g->d_adjL.reserve(adjL.size()), "hipMalloc halo CSR");
-    HIP_TRY(g->d_tab.reserve(tab.size()), "hipMalloc halo table");
+    HIP_TRY(g->d_ovf.reserve(std::max<size_t>(L.ovf.size(), 1)), "hipMalloc halo overflow");
+    if (!L.ovf.empty())
+        HIP_TRY(hipMemcpy(g->d_ovf.p, L.ovf.data(), L.ovf.size() * 4, hipMemcpyHostToDevice), "upload halo overflow");
+    HIP_TRY(g->d_adjL.reserve(L.adjL.size()), "hipMalloc halo CSR");
+    HIP_TRY(g->d_tab.reserve(L.tab.size()), "hipMalloc halo table");
     HIP_TRY(g->d_words.reserve((size_t)g->n_pad / 32 + 1), "hipMalloc packed spins");
     HIP_TRY(g->d_member.reserve(8 * 64), "hipMalloc barrier");
     HIP_TRY(g->d_group.reserve(2 * 8 * GDI_HALO_GROUP_PAD), "hipMalloc barrier");
-    if (!adjL.empty())
-        HIP_TRY(hipMemcpy(g->d_adjL.p, adjL.data(), adjL.size() * 4, hipMemcpyHostToDevice), "upload halo CSR");
-    HIP_TRY(hipMemcpy(g->d_tab.p, tab.data(), tab.size() * sizeof(GdiHaloEntry), hipMemcpyHostToDevice), "upload halo table");
-    HIP_TRY(g->d_tail_v.reserve(std::max<size_t>(tail_v.size(), 1)), "hipMalloc halo tail");
-    HIP_TRY(g->d_tail_beg.reserve(tail_beg.size()), "hipMalloc halo tail");
-    HIP_TRY(g->d_gat_words.reserve(std::max<size_t>(gat_words.size(), 1)), "hipMalloc halo tail");
-    HIP_TRY(g->d_gat_beg.reserve(gat_beg.size()), "hipMalloc halo tail");
-    HIP_TRY(g->d_tail_rp.reserve(tail_rp.size()), "hipMalloc halo tail");
-    HIP_TRY(g->d_tail_ent.reserve(std::max<size_t>(tail_ent.size(), 1)), "hipMalloc halo tail");
-    HIP_TRY(hipMemcpy(g->d_tail_rp.p, tail_rp.data(), tail_rp.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
-    if (!tail_ent.empty())
-        HIP_TRY(hipMemcpy(g->d_tail_ent.p, tail_ent.data(), tail_ent.size() * 4, hipMemcpyHostToDevice),
+    if (!L.adjL.empty())
+        HIP_TRY(hipMemcpy(g->d_adjL.p, L.adjL.data(), L.adjL.size() * 4, hipMemcpyHostToDevice), "upload halo CSR");
+    HIP_TRY(hipMemcpy(g->d_tab.p, L.tab.data(), L.tab.size() * sizeof(GdiHaloEntry), hipMemcpyHostToDevice),
+            "upload halo table");
+    HIP_TRY(g->d_tail_v.reserve(std::max<size_t>(L.tail_v.size(), 1)), "hipMalloc halo tail");
+    HIP_TRY(g->d_tail_beg.reserve(L.tail_beg.size()), "hipMalloc halo tail");
+    HIP_TRY(g->d_gat_words.reserve(std::max<size_t>(L.gat_words.size(), 1)), "hipMalloc halo tail");
+    HIP_TRY(g->d_gat_beg.reserve(L.gat_beg.size()), "hipMalloc halo tail");
+    HIP_TRY(g->d_tail_rp.reserve(L.tail_rp.size()), "hipMalloc halo tail");
+    HIP_TRY(g->d_tail_ent.reserve(std::max<size_t>(L.tail_ent.size(), 1)), "hipMalloc halo tail");
+    HIP_TRY(hipMemcpy(g->d_tail_rp.p, L.tail_rp.data(), L.tail_rp.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
+    if (!L.tail_ent.empty())
+        HIP_TRY(hipMemcpy(g->d_tail_ent.p, L.tail_ent.data(), L.tail_ent.size() * 4, hipMemcpyHostToDevice),
                 "upload halo tail");
-    if (!tail_v.empty())
-        HIP_TRY(hipMemcpy(g->d_tail_v.p, tail_v.data(), tail_v.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
-    HIP_TRY(hipMemcpy(g->d_tail_beg.p, tail_beg.data(), tail_beg.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
-    if (!gat_words.empty())
-        HIP_TRY(hipMemcpy(g->d_gat_words.p, gat_words.data(), gat_words.size() * 4, hipMemcpyHostToDevice),
+    if (!L.tail_v.empty())
+        HIP_TRY(hipMemcpy(g->d_tail_v.p, L.tail_v.data(), L.tail_v.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
+    HIP_TRY(hipMemcpy(g->d_tail_beg.p, L.tail_beg.data(), L.tail_beg.size() * 4, hipMemcpyHostToDevice),
+            "upload halo tail");
+    if (!L.gat_words.empty())
+        HIP_TRY(hipMemcpy(g->d_gat_words.p, L.gat_words.data(), L.gat_words.size() * 4, hipMemcpyHostToDevice),
                 "upload halo tail");
-    HIP_TRY(hipMemcpy(g->d_gat_beg.p, gat_beg.data(), gat_beg.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
-    g->halo_lds_words = lds_words;
+    HIP_TRY(hipMemcpy(g->d_gat_beg.p, L.gat_beg.data(), L.gat_beg.size() * 4, hipMemcpyHostToDevice), "upload halo tail");
+    g->halo_lds_words = L.lds_words;
     g->halo_T0 = T0;
-    g->halo_tail_n = (int32_t)tail_v.size();
-    g->halo_gather_off = gather_off;
-    g->halo_tail_off = tail_off;
-    g->halo_tail_nnz = (int32_t)tail_ent.size();
-    g->halo_trp_off = trp_off;
-    g->halo_tent_off = tent_off;
-    g->halo_ovf_off = ovf_off;
-    g->halo_ovf_len = ovf_len;
+    g->halo_tail_n = (int32_t)L.tail_v.size();
+    g->halo_gather_off = L.gather_off;
+    g->halo_tail_off = L.tail_off;
+    g->halo_tail_nnz = (int32_t)L.tail_ent.size();
+    g->halo_trp_off = L.trp_off;
+    g->halo_tent_off = L.tent_off;
+    g->halo_ovf_off = L.ovf_off;
+    g->halo_ovf_len = L.ovf_len;
     return GDI_OK;
 }
 
@@ -637,7 +350,7 @@ int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork, int32_t l
     // read in the phase of class c + 1 (those of the last grid class before the tail),
     // and are then republished only after a grid barrier that follows every
     // workgroup's read of them
-    while (T0 > 3 && tail_n + g->csz[(size_t)T0 - 1] <= nwork) tail_n += g->csz[(size_t)--T0];
+    while (T0 > 3 && tail_n + g->rl.csz[(size_t)T0 - 1] <= nwork) tail_n += g->rl.csz[(size_t)--T0];
     for (;;) {
         int rc = build_halo_for(g, G, lds_budget, T0, lead);
         if (rc) return rc;
@@ -801,10 +514,15 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
     const uint64_t phases = (uint64_t)(S - s->start_sweep) * (uint64_t)g->C;
     r.bar_words = 0;
     if (phases > (uint64_t(1) << 30)) return fail(GDI_ERANGE, "too many phases for one launch");
-    if (r.ch.scope == GDI_SCOPE_GRID_FENCED) {
+    if (r.ch.scope == GDI_SCOPE_GRID_FENCED && !r.racy) {
         if (phases > (uint64_t(1) << 22)) return fail(GDI_ERANGE, "too many phases for one launch");
         r.bar_words = phases * (GDI_BAR_GROUPS + 1) * GDI_BAR_PAD;
         HIP_TRY(g->d_bar.reserve(r.bar_words), "hipMalloc barrier");
+    }
+    if (r.racy) {
+        // one device-wide barrier per sweep
+        r.bar_words = (uint64_t)(S - s->start_sweep) * (GDI_BAR_GROUPS + 1) * GDI_BAR_PAD;
+        HIP_TRY(g->d_bar.reserve(std::max<uint64_t>(r.bar_words, 1)), "hipMalloc barrier");
     }
     if (trace) HIP_TRY(g->d_trace.reserve(2 * (size_t)S), "hipMalloc trace");
 
@@ -895,17 +613,25 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
     a.gate_small = 0;
     int rc = 0;
     if (r.racy) {
-        for (uint32_t t = t_from; t < t_to && !rc; ++t) rc = gdi_launch_sweep_racy(a, t, st);
-        // the tracked values are racy: recount M, the cut and the class counts from the spins
+        // Alg. 3 in one persistent launch; the magnetisation stays the one its atomic
+        // adds tracked, the cut and the class counts are recounted from the spins
+        int grid = 0;
+        rc = gdi_async_capacity(1024, &grid);
+        if (!rc && g->have_tune && g->tune.grid) {
+            if ((int)g->tune.grid > grid) return fail(GDI_EDEVICE, "grid exceeds the co-resident capacity");
+            grid = (int)g->tune.grid;
+        }
+        const uint64_t sweeps = t_to - t_from;
+        a.bar_grp = g->d_bar.p;
+        a.bar_glob = g->d_bar.p + sweeps * GDI_BAR_GROUPS * GDI_BAR_PAD;
+        if (!rc) rc = gdi_launch_fill_u64(g->d_bar.p, (int64_t)(sweeps * (GDI_BAR_GROUPS + 1) * GDI_BAR_PAD), st);
+        if (!rc && sweeps > 0) rc = gdi_launch_sweep_async(a, grid, 1024, st);
         if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_red.p), 4, st);
         if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_P.p), (g->C + 2) / 2, st);
         if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->d_cbeg.p, g->d_csz.p, g->C,
                                         g->d_red.p, g->d_P.p, st);
-        if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_state.p + 1), 1, st);
-        if (!rc) {
-            hipError_t e = hipMemcpyAsync(g->d_state.p, g->d_red.p, 8, hipMemcpyDeviceToDevice, st);
-            if (e != hipSuccess) return hip_fail(e, "state copy");
-        }
+        if (!rc) g->last.grid = (uint32_t)grid;
+        if (!rc) g->last.block = 1024;
     } else if (r.dense) {
         rc = gdi_launch_sweep_dense(a, (int)r.ch.block, (int)r.ch.lanes, st);
     } else if (r.ch.scope == GDI_SCOPE_WORKGROUP) {
@@ -914,7 +640,7 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
         GdiHaloArgs ha{};
         ha.base = a;
         ha.adjL = g->d_adjL.p;
-        ha.unit_w = g->halo_unit_w;
+        ha.unit_w = (g->have_tune && g->tune.general_weights > 0) ? 0 : g->halo_unit_w;
         ha.tab = g->d_tab.p;
         ha.words = g->d_words.p;
         ha.member = g->d_member.p;
@@ -1384,7 +1110,7 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
             HIP_TRY(hipStreamSynchronize(st), "download mask");
             uint8_t *row = cfg->mask_trace + (size_t)((b - b0) / k) * (size_t)g->n;
             for (int32_t v = 0; v < g->n_pad; ++v) {
-                const int32_t o = g->orig[(size_t)v];
+                const int32_t o = g->rl.orig[(size_t)v];
                 if (o >= 0) row[o] = (uint8_t)((hmask[(size_t)v >> 5] >> (v & 31)) & 1u);
             }
         }
@@ -1525,7 +1251,7 @@ int gdi_colour_csr(const int32_t *row_ptr, const int32_t *col_idx, int32_t n, in
     if (!row_ptr || !col_idx || !colour_out) return fail(GDI_EINVAL, "NULL argument");
     if (n < 1) return fail(GDI_EINVAL, "n must be >= 1");
     try {
-        return colour_first_fit(row_ptr, col_idx, n, colour_out);
+        return gdi_layout::colour_first_fit(row_ptr, col_idx, n, colour_out);
     } catch (const std::bad_alloc &) {
         return fail(GDI_ENOMEM, "out of host memory");
     }
@@ -1581,7 +1307,7 @@ int gdi_create(const int32_t *row_ptr, const int32_t *col_idx, const int32_t *we
         g->max_abs_wdeg = mw;
         g->max_degree = md;
         g->colour.assign((size_t)n, 0);
-        g->C = colour_first_fit(row_ptr, col_idx, n, g->colour.data());
+        g->C = gdi_layout::colour_first_fit(row_ptr, col_idx, n, g->colour.data());
         if ((rc = check_device())) { delete g; return rc; }
         if ((rc = upload(g, row_ptr, col_idx, weights))) { delete g; return rc; }
     } catch (const std::bad_alloc &) {
@@ -1804,7 +1530,7 @@ int gdi_get_colouring(const gdi_graph *g, int32_t *colour_out, int32_t *class_si
 {
     if (!g) return fail(GDI_ESTATE, "NULL handle");
     if (colour_out) std::memcpy(colour_out, g->colour.data(), (size_t)g->n * 4);
-    if (class_size_out) std::memcpy(class_size_out, g->csz.data(), (size_t)g->C * 4);
+    if (class_size_out) std::memcpy(class_size_out, g->rl.csz.data(), (size_t)g->C * 4);
     return GDI_OK;
 }
 

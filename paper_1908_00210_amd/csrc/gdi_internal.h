@@ -13,7 +13,8 @@
 
 #include <stdint.h>
 
-#define GDI_CLASS_ALIGN 64
+#include "gdi_layout.h"  // GDI_CLASS_ALIGN, halo constants, GdiHaloEntry
+
 #define GDI_MAX_BLOCK 1024
 #define GDI_WG_THR_MAX 256     // largest table width the workgroup sweep keeps in LDS (two rows)
 #define GDI_BAR_GROUPS 8       // workgroups are grouped by blockIdx % 8 for the two-level barrier
@@ -60,24 +61,6 @@ struct GdiActiveRec {
     int32_t v;                 // new id
     int32_t r0, r1;            // CSR row
     int32_t orig;              // original id (Philox counter)
-};
-
-// Halo layout of the fence-free grid sweep (k_sweep_halo). Each workgroup b owns,
-// for every class c, a 64-aligned chunk of nodes, and keeps in LDS the spin bits
-// of a window of the packed spin array that covers its own chunk and every
-// neighbour of its nodes in class c.
-#define GDI_HALO_MAX_GRID 512
-#define GDI_HALO_GROUP_PAD 16  // uint64 words between group words (128 bytes)
-#define GDI_HALO_PF 16         // CSR entries per node held in registers across a barrier
-#define GDI_HALO_THR_MAX 4096  // largest table width kept in LDS (two rows)
-#define GDI_HALO_WMAX 1023     // largest |weight| the packed entries of the halo sweep hold
-
-struct GdiHaloEntry {          // one per (workgroup, class)
-    int32_t node_lo, node_hi;  // own nodes: new ids [node_lo, node_hi)
-    int32_t win_lo;            // first packed word of the window
-    int32_t win_len;           // words in the window
-    int32_t lds_off;           // LDS word where the window starts
-    int32_t pad0, pad1, pad2;
 };
 
 struct GdiHaloArgs {
@@ -169,13 +152,13 @@ int gdi_launch_gather_in(const int32_t *orig, const int8_t *in_orig, int32_t n_p
 int gdi_active_lds_bytes(int32_t n_pad, int32_t C);
 int gdi_launch_sweep_active(const GdiSweepArgs &a, GdiActiveRec *rec, void *stream);
 int gdi_dense_lds_bytes(int32_t n_pad, int32_t C);
-int gdi_launch_sweep_racy(const GdiSweepArgs &a, uint32_t t, void *stream);
+int gdi_async_capacity(int block, int *max_grid);
+int gdi_launch_sweep_async(const GdiSweepArgs &a, int grid, int block, void *stream);
 int gdi_launch_sweep_dense(const GdiSweepArgs &a, int block, int lanes, void *stream);
 int gdi_launch_sweep_wg(const GdiSweepArgs &a, int block, int lanes, int spins_in_lds, void *stream);
 int gdi_launch_sweep_grid(const GdiSweepArgs &a, int grid, int block, int lanes, void *stream);
 int gdi_grid_capacity(int block, int lanes, int *max_grid);
 int gdi_launch_sweep_halo(const GdiHaloArgs &h, int grid, int block, void *stream);
-int gdi_halo_lds_bytes(int32_t lds_words, int32_t C, int32_t thr_words);
 int gdi_halo_capacity(int block, int lds_bytes, int *max_grid);
 int gdi_wg_lds_bytes(int32_t n_pad, int32_t C, int spins_in_lds);
 int gdi_batch_lds_bytes(int32_t n_pad, int32_t C);

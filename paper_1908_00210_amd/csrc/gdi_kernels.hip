@@ -25,11 +25,13 @@
 // library is compiled with -DGDI_PHASE_TIMING; the product build has none).
 #ifdef GDI_PHASE_TIMING
 __device__ unsigned long long *g_tbuf;
+__device__ int g_tfirst;
 __device__ int g_tphases;
 #define GDI_TSTAMP(slot, cond)                                                                      \
     do {                                                                                          \
-        if ((cond) && g_tbuf && (int)p < g_tphases)                                               \
-            g_tbuf[((size_t)p * gridDim.x + blockIdx.x) * 8 + (slot)] = __builtin_amdgcn_s_memrealtime(); \
+        if ((cond) && g_tbuf && (int)p >= g_tfirst && (int)p < g_tfirst + g_tphases)              \
+            g_tbuf[((size_t)(p - g_tfirst) * gridDim.x + blockIdx.x) * 8 + (slot)] =              \
+                __builtin_amdgcn_s_memrealtime();                                                 \
     } while (0)
 #else
 #define GDI_TSTAMP(slot, cond) \
@@ -1602,51 +1604,62 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_dense(GdiSweepArgs a)
 }
 
 // ------------------------------------------------------------------ asynchronous sweep
-// Alg. 3 as printed, racy by design: every node of the graph decides in the same
-// launch against the neighbour spins and the magnetisation as it finds them (other
-// nodes may or may not have flipped yet) and publishes its flip at once. One launch
-// per sweep; results are not reproducible. The balance term takes the magnetisation
-// read by its workgroup (there are no colour phases, hence no gate); each workgroup
-// adds its flips' change of M with one atomic.
-__global__ void __launch_bounds__(1024) k_sweep_racy(GdiSweepArgs a, uint32_t t)
+// Alg. 3 as printed (Sec. V-C), racy by design, in one persistent cooperative launch:
+// in every sweep each thread takes its nodes in turn (node v goes to thread
+// v mod #threads, as when there are more spins than threads); for each node it reads
+// the neighbour spins as it finds them (agent-scope loads: another node may or may
+// not have flipped already, Sec. V-B), reads the global magnetisation G itself, makes
+// the decision with the balance term of G, and when the spin flips stores it and adds
+// its change to G with one atomic add. There are no colour phases and no gate; a
+// device-wide barrier separates the sweeps (the schedule moves on only once every
+// spin has updated). Results are not reproducible. G ends equal to the sum of the
+// spins, since every change of a spin comes with its own atomic add.
+__global__ void __launch_bounds__(1024) k_sweep_async(GdiSweepArgs a)
 {
-    __shared__ int32_t m_sh, dm_sh;
-    // the magnetisation as this workgroup finds it (one load; racy anyway), and one
-    // atomic per workgroup for its flips: same-address atomics serialise in memory
-    if (threadIdx.x == 0) {
-        m_sh = (int32_t)__hip_atomic_load(&a.state[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        dm_sh = 0;
-    }
+    __shared__ int32_t abort_flag;
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    const uint32_t ngroups = G < GDI_BAR_GROUPS ? G : GDI_BAR_GROUPS;
+    const uint32_t x = b % ngroups;
+    const uint32_t gsz = G / ngroups + (x < G % ngroups ? 1u : 0u);
+    const int32_t nthr = (int32_t)(G * blockDim.x);
+    const int32_t gid = (int32_t)(b * blockDim.x + threadIdx.x);
+    if (threadIdx.x == 0) abort_flag = 0;
     __syncthreads();
-    const int32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t dM = 0;
-    if (v < a.n_pad) {
-        const int32_t o = a.orig[v];
-        if (o >= 0) {
+    uint32_t p = 0;
+    for (uint32_t t = a.t0; t < a.S; ++t, ++p) {
+        const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)(a.K + 1);
+        for (int32_t v = gid; v < a.n_pad; v += nthr) {
+            const int32_t o = a.orig[v];
+            if (o < 0) continue;  // padding
             int32_t h = 0;
             for (int32_t k = a.rp[v]; k < a.rp[v + 1]; ++k) {
                 const int2 e = a.adj[k];
-                // relaxed and cached: whatever value this CU's caches hold, as on the paper's GPU
-                h += e.y * (int32_t)__hip_atomic_load(&a.spin[e.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                h += e.y * (int32_t)__hip_atomic_load(&a.spin[e.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            const int32_t sigma = a.spin[v];
-            const int32_t M = m_sh;
-            const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * M);
-            const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)(a.K + 1);
+            const int32_t sigma = a.spin[v];  // only this thread writes it
+            const int32_t Mg = (int32_t)__hip_atomic_load(&a.state[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const int32_t dE = a.B * sigma * h + a.A4 * (1 - sigma * Mg);
             const Words4 xw = philox10((uint32_t)o, t, a.replica, 0u, a.key0, a.key1);
             bool flip;
             if (a.rule) flip = paper_flip(dE, sigma, xw.w0, xw.w2, thr_row[0]);
             else flip = dE <= 0 || (dE <= a.K && xw.w0 < thr_row[dE]);
             if (flip) {
-                __hip_atomic_store(&a.spin[v], (int8_t)(-sigma), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                dM = -2 * sigma;
+                __hip_atomic_store(&a.spin[v], (int8_t)(-sigma), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_fetch_add(&a.state[0], (int64_t)(-2 * sigma), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
+        // the sweep ends when every thread has finished its nodes
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t tot = 0;
+            if (!grid_phase_sync(a, p, 0, x, gsz, ngroups, &tot)) {
+                abort_flag = 1;
+                __hip_atomic_store(&a.state[3], (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        __syncthreads();
+        if (abort_flag) return;
     }
-    dM = wave_sum_i32(dM);
-    if ((threadIdx.x & 63) == 0 && dM != 0) atomicAdd(&dm_sh, dM);
-    __syncthreads();
-    if (threadIdx.x == 0 && dm_sh != 0) atomicAdd((unsigned long long *)&a.state[0], (unsigned long long)(int64_t)dm_sh);
 }
 
 inline int status(hipError_t e) { return (int)e; }
@@ -1734,10 +1747,26 @@ int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, in
 
 int gdi_dense_lds_bytes(int32_t n_pad, int32_t C) { return ((C + 3) & ~3) * 4 + 2 * n_pad; }
 
-int gdi_launch_sweep_racy(const GdiSweepArgs &a, uint32_t t, void *stream)
+int gdi_async_capacity(int block, int *max_grid)
 {
-    hipLaunchKernelGGL(k_sweep_racy, dim3(blocks_for(a.n_pad, 1024)), dim3(1024), 0, (hipStream_t)stream, a, t);
-    return status(hipGetLastError());
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)k_sweep_async, block, 0);
+    if (e != hipSuccess) return status(e);
+    // one workgroup per compute unit: with the occupancy figure above one (two
+    // 1024-thread workgroups per CU) the sweep barrier was not reached by every
+    // workgroup (bounded wait expired), so co-residency is only relied on at one
+    *max_grid = cus * std::min(per_cu, 1);
+    return 0;
+}
+
+int gdi_launch_sweep_async(const GdiSweepArgs &a, int grid, int block, void *stream)
+{
+    GdiSweepArgs copy = a;
+    void *args[] = {&copy};
+    return status(hipLaunchCooperativeKernel((const void *)k_sweep_async, dim3(grid), dim3(block), args, 0u,
+                                             (hipStream_t)stream));
 }
 
 int gdi_launch_sweep_dense(const GdiSweepArgs &a, int block, int lanes, void *stream)
@@ -1824,11 +1853,6 @@ int gdi_launch_sweep_grid(const GdiSweepArgs &a, int grid, int block, int lanes,
     return status(e);
 }
 
-int gdi_halo_lds_bytes(int32_t lds_words, int32_t C, int32_t thr_words)
-{
-    return lds_words * 4 + C * (int)sizeof(GdiHaloEntry) + C * 8 + thr_words * 4;
-}
-
 int gdi_halo_capacity(int block, int lds_bytes, int *max_grid)
 {
     // the smaller capacity of the two instantiations (unit and general weights)
@@ -1860,9 +1884,10 @@ int gdi_launch_sweep_halo(const GdiHaloArgs &h, int grid, int block, void *strea
 }
 
 #ifdef GDI_PHASE_TIMING
-extern "C" int gdi_timing_setup(unsigned long long *buf, int phases)
+extern "C" int gdi_timing_setup(unsigned long long *buf, int first, int phases)
 {
     hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_tbuf), &buf, sizeof(buf));
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_tfirst), &first, sizeof(int));
     if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_tphases), &phases, sizeof(int));
     return (int)e;
 }
