@@ -70,7 +70,8 @@ extern "C" {
 #define GDI_SCOPE_AUTO 0u
 #define GDI_SCOPE_WORKGROUP 1u /* whole instance inside one workgroup */
 #define GDI_SCOPE_GRID 2u      /* instance spread over the whole device; spins exchanged through
-                                  per-workgroup LDS windows, no cache-wide fences */
+                                  per-workgroup LDS copies of the spin words each
+                                  workgroup reads, no cache-wide fences */
 #define GDI_SCOPE_GRID_FENCED 3u /* whole device, spins gathered from global memory with
                                     release/acquire fences per phase (any graph) */
 

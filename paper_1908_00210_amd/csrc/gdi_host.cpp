@@ -87,7 +87,9 @@ struct gdi_graph {
     DevBuf<int32_t> d_tail_v, d_tail_beg, d_gat_words, d_gat_beg, d_tail_rp;
     DevBuf<uint32_t> d_tail_ent;
     int32_t halo_ovf_off = 0, halo_ovf_len = 0, halo_unit_w = 0;
+    int32_t halo_list_off = 0, halo_flist_len = 0;
     DevBuf<uint32_t> d_ovf;
+    DevBuf<int32_t> d_flist;
     DevBuf<GdiHaloEntry> d_tab;
     DevBuf<uint64_t> d_words, d_member, d_group;
 
@@ -120,7 +122,7 @@ struct gdi_graph {
         d_adj.release(); d_spin.release(); d_io.release(); d_state.release(); d_red.release();
         d_trace.release(); d_thr.release(); d_bar.release();
         d_adjL.release(); d_tail_v.release(); d_tail_beg.release(); d_gat_words.release(); d_gat_beg.release();
-        d_tail_rp.release(); d_tail_ent.release(); d_ovf.release();
+        d_tail_rp.release(); d_tail_ent.release(); d_ovf.release(); d_flist.release();
         d_tab.release(); d_words.release(); d_member.release(); d_group.release();
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
@@ -228,7 +230,7 @@ int pick_launch(gdi_graph *g, Choice *ch)
         if (t.scope == GDI_SCOPE_GRID)
             return fail(GDI_ERANGE, g->halo_lds_words == -3
                                         ? "the grid scope packs weights into 11 bits: |w| must be <= 1023"
-                                        : "the spin windows of this graph do not fit one workgroup's LDS");
+                                        : "the spin words this graph needs per workgroup do not fit its LDS");
         ch->scope = GDI_SCOPE_GRID_FENCED;  // automatic choice falls back
     }
     int cap = 0;
@@ -294,6 +296,9 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0, int32_t 
         g->halo_lds_words = L.status;
         return GDI_OK;
     }
+    HIP_TRY(g->d_flist.reserve(std::max<size_t>(L.flist.size(), 1)), "hipMalloc halo lists");
+    if (!L.flist.empty())
+        HIP_TRY(hipMemcpy(g->d_flist.p, L.flist.data(), L.flist.size() * 4, hipMemcpyHostToDevice), "upload halo lists");
     HIP_TRY(g->d_ovf.reserve(std::max<size_t>(L.ovf.size(), 1)), "hipMalloc halo overflow");
     if (!L.ovf.empty())
         HIP_TRY(hipMemcpy(g->d_ovf.p, L.ovf.data(), L.ovf.size() * 4, hipMemcpyHostToDevice), "upload halo overflow");
@@ -334,10 +339,12 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0, int32_t 
     g->halo_tent_off = L.tent_off;
     g->halo_ovf_off = L.ovf_off;
     g->halo_ovf_len = L.ovf_len;
+    g->halo_list_off = L.list_off;
+    g->halo_flist_len = L.flist_len;
     return GDI_OK;
 }
 
-// Builds the halo layout for grid size G: own chunks, windows of the packed spin
+// Builds the halo layout for grid size G: own chunks, foreign words of the packed spin
 // array per (workgroup, class), LDS offsets and the CSR with LDS bit indices.
 // Classes T0..C-1 form the redundant tail when they hold at most nwork nodes.
 int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork, int32_t lead)
@@ -662,6 +669,9 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
         ha.ovf_off = g->halo_ovf_off;
         ha.ovf_len = g->halo_ovf_len;
         ha.ovf = g->d_ovf.p;
+        ha.list_off = g->halo_list_off;
+        ha.flist_len = g->halo_flist_len;
+        ha.flist = g->d_flist.p;
         ha.thr_in_lds = r.thr_in_lds;
         rc = gdi_launch_fill_u64(g->d_words.p, (int64_t)g->n_pad / 32 + 1, st);
         if (!rc) rc = gdi_launch_fill_u64(g->d_member.p, 8 * 64, st);

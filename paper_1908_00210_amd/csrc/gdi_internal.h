@@ -74,7 +74,7 @@ struct GdiHaloArgs {
     uint64_t *words;           // packed spins: (epoch << 32) | 32 spin bits (bit = 1 for +1)
     uint64_t *member;          // 8 x 64 words: workgroup b posts (epoch << 32) | uint32(dM) at (b % 8) * 64 + b / 8
     uint64_t *group;           // 2 x 8 words (phase parity x group), GDI_HALO_GROUP_PAD apart
-    int32_t lds_words;         // LDS words per workgroup: windows, then the tail's gather and tail regions
+    int32_t lds_words;         // LDS words per workgroup: image (own and foreign words per class), the tail's gather and tail regions, the foreign-id lists
     int32_t thr_in_lds;        // 1: the current and next threshold rows are staged in LDS
     // Redundant tail: the last classes T0..C-1 hold at most one node per worker thread
     // in total; every workgroup runs them itself (identical results everywhere), so
@@ -101,6 +101,11 @@ struct GdiHaloArgs {
     // holds the LDS word where they start. With ovf_len == 0 they are read from adjL.
     int32_t ovf_off, ovf_len;
     const uint32_t *ovf;
+    // Foreign-word ids: workgroup b's lists for all classes, flist_len entries at
+    // flist + b * flist_len, copied into LDS at list_off at launch (GdiHaloEntry.list_off
+    // points into that copy).
+    int32_t list_off, flist_len;
+    const int32_t *flist;
 };
 
 // Batched form: one instance (graph, replica) per queue entry.

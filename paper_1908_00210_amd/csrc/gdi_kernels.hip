@@ -732,15 +732,16 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_grid(GdiSweepArgs a)
 // cache-wide release/acquire fence is needed: a reader that sees the epoch it
 // waits for sees the payload of the same store.
 //   * spins: after the phase of class c, each owner republishes every packed word
-//     of its chunk with the phase's epoch; readers poll only the words of their
-//     window of class c and copy the bits into LDS;
+//     of its chunk with the phase's epoch; readers poll only their foreign words of
+//     class c (the words of that class their nodes read and another workgroup owns)
+//     and copy the bits into LDS;
 //   * dM: each workgroup posts (epoch, dM) in its member word (the members of one
 //     group are contiguous, so a leader polls two cache lines); the leader of each
 //     group (workgroups b = x mod 8) sums its members' words and posts
 //     (epoch, group sum) in the group word of the phase's parity; everyone sums
 //     the 8 group words.
 // A word can only be overwritten after every reader has consumed it: member and
-// window words are rewritten at the earliest one full barrier later, group words
+// chunk words are rewritten at the earliest one full barrier later, group words
 // alternate by phase parity. All waits are bounded by spin_limit.
 
 __device__ __forceinline__ uint64_t ld_agent(const uint64_t *p)
@@ -787,17 +788,18 @@ __device__ __forceinline__ uint32_t pack_spins(const int8_t *spin, int32_t wd)
     return word;
 }
 
-// Polls the words of one window until they carry `epoch`, copying their bits to LDS.
-// Returns false when the bounded wait expires or another thread has aborted.
-__device__ __forceinline__ bool poll_window(const GdiHaloArgs &h, const GdiHaloEntry &e, uint32_t *bits,
-                                            uint32_t epoch, int first, int stride, int32_t *abort_sh)
+// Polls foreign words first, first + stride, ... of one class until they carry
+// `epoch`, copying their bits to LDS. Returns false when the bounded wait expires or
+// another thread has aborted.
+__device__ __forceinline__ bool poll_foreign(const GdiHaloArgs &h, const GdiHaloEntry &e, uint32_t *bits,
+                                             uint32_t epoch, int first, int stride, int32_t *abort_sh)
 {
-    for (int32_t i = first; i < e.win_len; i += stride) {
-        const uint64_t *src = h.words + e.win_lo + i;
+    for (int32_t i = first; i < e.for_len; i += stride) {
+        const uint64_t *src = h.words + (int32_t)bits[e.list_off + i];
         for (int64_t tries = 0;; ++tries) {
             const uint64_t w = ld_agent(src);
             if ((uint32_t)(w >> 32) >= epoch) {
-                bits[e.lds_off + i] = (uint32_t)w;
+                bits[e.for_off + i] = (uint32_t)w;
                 break;
             }
             if (tries >= h.base.spin_limit || aborted(abort_sh)) return false;
@@ -981,7 +983,7 @@ __device__ __forceinline__ bool poll_word(const uint64_t *w, uint32_t epoch, int
 }
 
 // Polls the tail's gather words of class c until they carry `epoch`, copying their
-// bits into the gather region. Same bounded wait as poll_window.
+// bits into the gather region. Same bounded wait as poll_foreign.
 __device__ __forceinline__ bool poll_gather(const GdiHaloArgs &h, int32_t c, uint32_t *bits, uint32_t epoch,
                                             int first, int stride, int32_t *abort_sh)
 {
@@ -1001,23 +1003,24 @@ __device__ __forceinline__ bool poll_gather(const GdiHaloArgs &h, int32_t c, uin
     return true;
 }
 
-// The polls after the phase of class c: the window of class c (words carrying `epoch`)
-// and, with a tail, the gather words of class cg = c - 1 (carrying `epoch_g`, published
-// a phase earlier, so they are there by now and no workgroup waits here for the
-// slowest owner anywhere in the grid). A thread's first window word and first gather
-// word (packed-word id gidx, loaded earlier, or -1) are loaded together, so their
-// latencies overlap; further words, if any, use the loops above.
+// The polls after the phase of class c: the foreign words of class c (carrying
+// `epoch`) and, with a tail, the gather words of class cg = c - 1 (carrying `epoch_g`,
+// published a phase earlier, so they are there by now and no workgroup waits here for
+// the slowest owner anywhere in the grid). A thread's first foreign word and first
+// gather word (packed-word id gidx, loaded earlier, or -1) are loaded together, so
+// their latencies overlap; further words, if any, use the loops above.
 __device__ __forceinline__ bool poll_phase_words(const GdiHaloArgs &h, const GdiHaloEntry &e, int32_t cg, int32_t gidx,
                                                  uint32_t *bits, uint32_t epoch, uint32_t epoch_g, int tid, int nwork,
                                                  int32_t *abort_sh)
 {
-    const bool hw = tid < e.win_len, hg = gidx >= 0;
+    const bool hw = tid < e.for_len, hg = gidx >= 0;
+    const uint64_t *fsrc = h.words + (hw ? (int32_t)bits[e.list_off + tid] : 0);
     bool ok0 = !hw, ok1 = !hg;
     for (int64_t tries = 0;; ++tries) {
-        const uint64_t w0 = ok0 ? 0 : ld_agent(h.words + e.win_lo + tid);
+        const uint64_t w0 = ok0 ? 0 : ld_agent(fsrc);
         const uint64_t w1 = ok1 ? 0 : ld_agent(h.words + gidx);
         if (!ok0 && (uint32_t)(w0 >> 32) >= epoch) {
-            bits[e.lds_off + tid] = (uint32_t)w0;
+            bits[e.for_off + tid] = (uint32_t)w0;
             ok0 = true;
         }
         if (!ok1 && (uint32_t)(w1 >> 32) >= epoch_g) {
@@ -1028,7 +1031,7 @@ __device__ __forceinline__ bool poll_phase_words(const GdiHaloArgs &h, const Gdi
         if (tries >= h.base.spin_limit || aborted(abort_sh)) return false;
         __builtin_amdgcn_s_sleep(1);
     }
-    if (e.win_len > nwork && !poll_window(h, e, bits, epoch, tid + nwork, nwork, abort_sh)) return false;
+    if (e.for_len > nwork && !poll_foreign(h, e, bits, epoch, tid + nwork, nwork, abort_sh)) return false;
     if (hg && h.gat_beg[cg + 1] - h.gat_beg[cg] > nwork) {
         for (int32_t i = h.gat_beg[cg] + tid + nwork; i < h.gat_beg[cg + 1]; i += nwork) {
             const uint64_t *src = h.words + h.gat_words[i];
@@ -1060,7 +1063,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     const GdiSweepArgs &a = h.base;
     if (!gate_open(a)) return;
     extern __shared__ uint32_t lds[];
-    uint32_t *bits = lds;                                                   // windows, gather, tail
+    uint32_t *bits = lds;                                                   // image, gather, tail, lists
     GdiHaloEntry *tab = reinterpret_cast<GdiHaloEntry *>(lds + h.lds_words); // C entries
     int32_t *Psh = reinterpret_cast<int32_t *>(tab + a.C);                  // C counts of +1
     int32_t *csz_sh = Psh + a.C;                                            // C class sizes
@@ -1069,7 +1072,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     __shared__ int32_t total_sh;
     __shared__ int32_t abort_sh;
     __shared__ int32_t tacc[3];
-    __shared__ uint32_t wdone;  // worker waves whose window polls are done (running count)
+    __shared__ uint32_t wdone;  // worker waves whose polls are done (running count)
 
     const int tid = threadIdx.x, nth = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = nth >> 6;
@@ -1084,7 +1087,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     // roles: the last wave is the barrier wave: as soon as a phase's nodes are done it
     // posts the workgroup's dM, collects its group's member words when this workgroup
     // leads the group, then reads the group words. All other waves ("workers") update
-    // nodes, prefetch and poll their window words.
+    // nodes, prefetch and poll their foreign words.
     const int nwork = (nwaves - 1) * 64;
     const bool worker = tid < nwork;
     const int32_t T0 = h.T0;
@@ -1116,12 +1119,18 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     int32_t M = (int32_t)a.state[0];
     __syncthreads();
 
-    // prologue: every window and gather word and the tail region straight from the spin
-    // array, which no workgroup writes before its epilogue, so no workgroup waits for
-    // another here (words published during the launch carry epochs >= 2)
+    // prologue: the foreign-word ids, then every own, foreign and gather word and the tail
+    // region straight from the spin array, which no workgroup writes before its epilogue,
+    // so no workgroup waits for another here (words published during the launch carry
+    // epochs >= 2)
+    for (int32_t i = tid; i < h.flist_len; i += nth) bits[h.list_off + i] = (uint32_t)h.flist[(size_t)b * h.flist_len + i];
+    __syncthreads();
     for (int32_t c = 0; c < T0; ++c) {
         const GdiHaloEntry e = tab[c];
-        for (int32_t wd = tid; wd < e.win_len; wd += nth) bits[e.lds_off + wd] = pack_spins(a.spin, e.win_lo + wd);
+        const int32_t w0 = e.node_lo >> 5, nown = e.node_hi > e.node_lo ? ((e.node_hi + 31) >> 5) - w0 : 0;
+        for (int32_t wd = tid; wd < nown; wd += nth) bits[e.own_off + wd] = pack_spins(a.spin, w0 + wd);
+        for (int32_t i = tid; i < e.for_len; i += nth)
+            bits[e.for_off + i] = pack_spins(a.spin, (int32_t)bits[e.list_off + i]);
     }
     if (has_tail)
         for (int32_t i = tid; i < h.gat_beg[T0]; i += nth) bits[h.gather_off + i] = pack_spins(a.spin, h.gat_words[i]);
@@ -1201,7 +1210,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                             q = pf;
                         }
                         const int32_t hv = base == e.node_lo && h_ready ? h_pre : row_field<UNIT>(h, bits, q);
-                        const int32_t lb = (e.lds_off + (v >> 5) - e.win_lo) * 32 + (v & 31);
+                        const int32_t lb = (e.own_off + (v >> 5) - (e.node_lo >> 5)) * 32 + (v & 31);
                         const int32_t sigma = lds_spin(bits, lb);
                         flip = decide_words(a, sigma, hv, pv, thr_l, thr_g, thr_lds, q.x0, q.x1, q.r0t >> 31);
                         sigma_l = sigma;
@@ -1219,7 +1228,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                         // own chunk words covered by this wave: flip their bits, republish both
                         const int32_t wd = v0 >> 5;
                         const int32_t w_end = (e.node_hi + 31) >> 5;
-                        uint32_t *lw = bits + e.lds_off + wd - e.win_lo;
+                        uint32_t *lw = bits + e.own_off + wd - (e.node_lo >> 5);
                         lw[0] ^= (uint32_t)fm;
                         st_agent(h.words + wd, ((uint64_t)epoch << 32) | lw[0]);
                         if (wd + 1 < w_end) {
@@ -1257,7 +1266,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                 GDI_TSTAMP(6, tid == 0);
                 good = poll_phase_words(h, e, cg, gidx, bits, epoch, epoch - 1u, tid, nwork, abort_v);
                 GDI_TSTAMP(7, tid == 0);
-                // Once every worker wave has polled, the windows hold every spin the next
+                // Once every worker wave has polled, the image holds every spin the next
                 // phase reads, so the next phase's local fields are summed now, while this
                 // phase's dM is still travelling; only the decisions wait for the new M.
                 // Each worker wave counts itself in whether or not its polls succeeded, so
@@ -1376,7 +1385,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     for (int32_t c = 0; c < T0; ++c) {
         const GdiHaloEntry e = tab[c];
         for (int32_t v = e.node_lo + tid; v < e.node_hi; v += nth) {
-            const int32_t lb = (e.lds_off + (v >> 5) - e.win_lo) * 32 + (v & 31);
+            const int32_t lb = (e.own_off + (v >> 5) - (e.node_lo >> 5)) * 32 + (v & 31);
             a.spin[v] = (int8_t)lds_spin(bits, lb);
         }
     }

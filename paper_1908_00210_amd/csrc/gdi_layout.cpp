@@ -152,39 +152,45 @@ int halo_layout(const Relabelled &g, int32_t C, int32_t G, int lds_budget, int32
         if (e.y != 1) L.unit_w = 0;
     }
     const int32_t Gw = G - lead;  // blocks holding nodes
-    std::vector<int32_t> chunk((size_t)C), blk_of_q((size_t)Gw);
+    std::vector<int32_t> blk_of_q((size_t)Gw);
     for (int32_t b = lead; b < G; ++b) blk_of_q[(size_t)chunk_of_block(b, G, lead)] = b;
-    for (int32_t c = 0; c < C; ++c) {
-        const int64_t per = ((int64_t)g.csz[(size_t)c] + Gw - 1) / Gw;
-        chunk[(size_t)c] = (int32_t)std::max<int64_t>(GDI_CLASS_ALIGN, (per + GDI_CLASS_ALIGN - 1) / GDI_CLASS_ALIGN * GDI_CLASS_ALIGN);
-    }
+    // Chunk q of class c is [bnd(c, q), bnd(c, q + 1)) in class order, with bnd(c, q) =
+    // 64 * round(q * csz / (64 Gw)): every chunk q covers the same fraction of its class,
+    // and classes of a colouring in ascending id spread alike over the id order, so the
+    // nodes a workgroup owns in different classes lie in the same part of the graph and
+    // its foreign words stay few. Interior bounds are multiples of 64 (a packed
+    // spin word never has two owners); chunks hold floor or ceil of csz / Gw rounded to 64.
+    auto bnd = [&](int32_t c, int64_t q) -> int64_t {
+        const int64_t sz = g.csz[(size_t)c];
+        if (q >= Gw) return sz;
+        const int64_t units = (sz + GDI_CLASS_ALIGN - 1) / GDI_CLASS_ALIGN;
+        return std::min<int64_t>(sz, (q * units * 2 + Gw) / (2 * (int64_t)Gw) * GDI_CLASS_ALIGN);
+    };
     const size_t GC = (size_t)G * (size_t)C;
     std::vector<GdiHaloEntry> &tab = L.tab;
     tab.assign(GC, GdiHaloEntry{});
-    std::vector<int32_t> wlo(GC, INT32_MAX), whi(GC, -1);
+    std::vector<int32_t> own((size_t)g.n_pad, -1);  // owner block of every node of a grid class
     for (int32_t b = 0; b < G; ++b) {
         const int32_t q = chunk_of_block(b, G, lead);
         for (int32_t c = 0; c < C; ++c) {
             GdiHaloEntry &e = tab[(size_t)b * C + c];
             std::memset(&e, 0, sizeof(e));
             if (c >= T0 || q < 0) continue;  // tail classes and dedicated leaders: no own chunks
-            const int64_t lo = (int64_t)g.cbeg[(size_t)c] + (int64_t)q * chunk[(size_t)c];
-            const int64_t hi = std::min<int64_t>((int64_t)g.cbeg[(size_t)c] + g.csz[(size_t)c], lo + chunk[(size_t)c]);
+            const int64_t lo = (int64_t)g.cbeg[(size_t)c] + bnd(c, q);
+            const int64_t hi = (int64_t)g.cbeg[(size_t)c] + bnd(c, (int64_t)q + 1);
+            e.node_lo = e.node_hi = (int32_t)lo;
             if (lo < hi) {
-                e.node_lo = (int32_t)lo;
                 e.node_hi = (int32_t)hi;
-                const size_t i = (size_t)b * C + c;
-                wlo[i] = std::min<int32_t>(wlo[i], (int32_t)(lo >> 5));
-                whi[i] = std::max<int32_t>(whi[i], (int32_t)((hi + 31) >> 5));
+                for (int64_t v = lo; v < hi; ++v) own[(size_t)v] = b;
             }
         }
     }
-    auto owner = [&](int32_t v) {
-        const int32_t c = g.cls[(size_t)v];
-        return blk_of_q[(size_t)((v - g.cbeg[(size_t)c]) / chunk[(size_t)c])];
-    };
-    // gather lists: the packed words of classes < T0 that tail nodes read
-    std::vector<std::vector<int32_t>> gat((size_t)T0);
+    auto owner = [&](int32_t v) { return own[(size_t)v]; };
+    // gather lists: the packed words of classes < T0 that tail nodes read; foreign
+    // lists: per (workgroup, class), the packed words of that class its nodes read and
+    // it does not own (an own chunk's words hold only its nodes and padding, since
+    // interior chunk bounds are multiples of 64)
+    std::vector<std::vector<int32_t>> gat((size_t)T0), fw(GC);
     for (int32_t v = 0; v < g.n_pad; ++v) {
         const int32_t cv = g.cls[(size_t)v];
         if (cv < 0) continue;
@@ -196,9 +202,8 @@ int halo_layout(const Relabelled &g, int32_t C, int32_t G, int lds_budget, int32
                 gat[(size_t)cj].push_back(j >> 5);
                 continue;
             }
-            const size_t i = (size_t)owner(v) * C + cj;
-            wlo[i] = std::min<int32_t>(wlo[i], j >> 5);
-            whi[i] = std::max<int32_t>(whi[i], (j >> 5) + 1);
+            const int32_t b = owner(v);
+            if (owner(j) != b) fw[(size_t)b * C + cj].push_back(j >> 5);
         }
     }
     std::vector<int32_t> &gat_beg = L.gat_beg, &gat_words = L.gat_words;
@@ -210,23 +215,28 @@ int halo_layout(const Relabelled &g, int32_t C, int32_t G, int lds_budget, int32
         gat_words.insert(gat_words.end(), W.begin(), W.end());
         gat_beg[(size_t)c + 1] = (int32_t)gat_words.size();
     }
-    int32_t lds_words = 0;
+    // image per workgroup: for each class its own chunk's words, then copies of its
+    // foreign words; every workgroup's image is laid out from LDS word 0
+    int32_t lds_words = 0, flist_max = 0;
+    std::vector<int32_t> list_pos(GC, 0);  // position of each (b, c) list in the block's list
     for (int32_t b = 0; b < G; ++b) {
-        int32_t off = 0;
+        int32_t off = 0, lpos = 0;
         for (int32_t c = 0; c < C; ++c) {
             const size_t i = (size_t)b * C + c;
             GdiHaloEntry &e = tab[i];
-            if (whi[i] < 0) {
-                e.win_lo = 0;
-                e.win_len = 0;
-            } else {
-                e.win_lo = wlo[i];
-                e.win_len = whi[i] - wlo[i];
-            }
-            e.lds_off = off;
-            off += e.win_len;
+            std::vector<int32_t> &W = fw[i];
+            std::sort(W.begin(), W.end());
+            W.erase(std::unique(W.begin(), W.end()), W.end());
+            e.own_off = off;
+            off += e.node_hi > e.node_lo ? ((e.node_hi + 31) >> 5) - (e.node_lo >> 5) : 0;
+            e.for_off = off;
+            e.for_len = (int32_t)W.size();
+            off += e.for_len;
+            list_pos[i] = lpos;
+            lpos += e.for_len;
         }
         lds_words = std::max(lds_words, off);
+        flist_max = std::max(flist_max, lpos);
     }
     const int32_t tail_base = T0 < C ? g.cbeg[(size_t)T0] : g.n_pad;  // multiple of 64
     int32_t tail_n = 0, tail_nnz = 0;
@@ -235,12 +245,15 @@ int halo_layout(const Relabelled &g, int32_t C, int32_t G, int lds_budget, int32
         for (int32_t v = g.cbeg[(size_t)c]; v < g.cbeg[(size_t)c] + g.csz[(size_t)c]; ++v)
             tail_nnz += g.rp[(size_t)v + 1] - g.rp[(size_t)v];
     }
-    // LDS image: windows | gather words | tail spin bits | tail row offsets | tail entries
+    // LDS: images | gather words | tail spin bits | tail row offsets | tail entries |
+    // foreign word ids | overflow entries
     const int32_t gather_off = lds_words;
     const int32_t tail_off = gather_off + (int32_t)gat_words.size();
     const int32_t trp_off = tail_off + (g.n_pad - tail_base) / 32;
     const int32_t tent_off = (trp_off + (T0 < C ? tail_n + 1 : 0) + 1) & ~1;  // 8-byte aligned
     lds_words = tent_off + 2 * tail_nnz;
+    const int32_t list_off = lds_words;
+    lds_words += flist_max;
     // (packed entries hold LDS word indices in 16 bits)
     if (gdi_halo_lds_bytes(lds_words, C, 0) > lds_budget || lds_words > 65536) {
         L.status = -2;
@@ -286,8 +299,15 @@ int halo_layout(const Relabelled &g, int32_t C, int32_t G, int lds_budget, int32
             } else if (cv >= T0) {
                 lb = gather_lb(j);
             } else {
-                const GdiHaloEntry &e = tab[(size_t)b * C + cj];
-                lb = (e.lds_off + (j >> 5) - e.win_lo) * 32 + (j & 31);
+                const size_t i = (size_t)b * C + cj;
+                const GdiHaloEntry &e = tab[i];
+                if (owner(j) == b) {
+                    lb = (e.own_off + (j >> 5) - (e.node_lo >> 5)) * 32 + (j & 31);
+                } else {
+                    const auto it = std::lower_bound(fw[i].begin(), fw[i].end(), j >> 5);
+                    lb = (it == fw[i].end() || *it != (j >> 5)) ? -1
+                                                                : (e.for_off + (int32_t)(it - fw[i].begin())) * 32 + (j & 31);
+                }
             }
             // every index must land inside this workgroup's LDS image (checked here so
             // that a layout error surfaces as an error code, never as a device fault)
@@ -319,6 +339,15 @@ int halo_layout(const Relabelled &g, int32_t C, int32_t G, int lds_budget, int32
         lds_words += ovf_len;
         for (const auto &l : links) adjL[l.first] = (uint32_t)(ovf_off + l.second);
     }
+    L.flist_len = flist_max;
+    L.flist.assign((size_t)G * (size_t)flist_max, 0);
+    for (int32_t b = 0; b < G; ++b)
+        for (int32_t c = 0; c < C; ++c) {
+            const size_t i = (size_t)b * C + c;
+            tab[i].list_off = list_off + list_pos[i];
+            std::copy(fw[i].begin(), fw[i].end(), L.flist.begin() + (size_t)b * flist_max + list_pos[i]);
+        }
+    L.list_off = list_off;
     L.ovf.assign((size_t)G * (size_t)ovf_len, 0u);
     for (int32_t b = 0; b < G && ovf_len > 0; ++b)
         std::copy(ovf[(size_t)b].begin(), ovf[(size_t)b].end(), L.ovf.begin() + (size_t)b * ovf_len);

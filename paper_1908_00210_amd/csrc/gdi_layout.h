@@ -13,9 +13,9 @@
 #define GDI_CLASS_ALIGN 64
 
 // Halo layout of the fence-free grid sweep (k_sweep_halo). Each workgroup b owns,
-// for every class c, a 64-aligned chunk of nodes, and keeps in LDS the spin bits
-// of a window of the packed spin array that covers its own chunk and every
-// neighbour of its nodes in class c.
+// for every class c, a chunk of nodes (interior bounds multiples of 64), and keeps in
+// LDS the spin bits of its chunk's packed words and copies of the foreign words: the
+// packed words of class c that its nodes read and that another workgroup owns.
 #define GDI_HALO_MAX_GRID 512
 #define GDI_HALO_GROUP_PAD 16  // uint64 words between group words (128 bytes)
 #define GDI_HALO_PF 16         // CSR entries per node held in registers across a barrier
@@ -23,11 +23,12 @@
 #define GDI_HALO_WMAX 1023     // largest |weight| the packed entries of the halo sweep hold
 
 struct GdiHaloEntry {          // one per (workgroup, class)
-    int32_t node_lo, node_hi;  // own nodes: new ids [node_lo, node_hi)
-    int32_t win_lo;            // first packed word of the window
-    int32_t win_len;           // words in the window
-    int32_t lds_off;           // LDS word where the window starts
-    int32_t pad0, pad1, pad2;
+    int32_t node_lo, node_hi;  // own nodes: new ids [node_lo, node_hi), node_lo a multiple of 64
+    int32_t own_off;           // LDS word holding packed word node_lo / 32 (the chunk's words follow)
+    int32_t for_off;           // LDS word of the first foreign word's copy
+    int32_t for_len;           // foreign words of this class
+    int32_t list_off;          // LDS word where their packed-word ids are listed (ascending)
+    int32_t pad0, pad1;
 };
 
 // Dynamic LDS bytes of one halo-sweep workgroup: the image, the class table, the class
@@ -92,7 +93,9 @@ struct HaloLayout {
     int32_t lds_words = 0, T0 = 0;
     int32_t gather_off = 0, tail_off = 0, trp_off = 0, tent_off = 0;
     int32_t ovf_off = 0, ovf_len = 0;
+    int32_t list_off = 0, flist_len = 0;     // LDS word of the foreign-id list region; its length
     std::vector<GdiHaloEntry> tab;           // G x C
+    std::vector<int32_t> flist;              // G x flist_len: each workgroup's foreign word ids by class
     std::vector<uint32_t> adjL;              // nnz + GDI_HALO_PF packed entries
     std::vector<int32_t> tail_v, tail_beg, tail_rp;
     std::vector<uint32_t> tail_ent;

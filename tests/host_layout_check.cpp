@@ -181,18 +181,18 @@ long check_layouts(const Csr &g, const char *name)
                 CHECK(gdi_halo_lds_bytes(L.lds_words, C, 0) <= budget && L.lds_words <= 65536, "%s: LDS budget", name);
                 CHECK(L.adjL.size() == r.adj.size() + GDI_HALO_PF, "%s: adjL size", name);
                 for (size_t k = r.adj.size(); k < L.adjL.size(); ++k) CHECK(L.adjL[k] == 0, "%s: zero tail", name);
-                // chunks partition each grid class
+                // chunks partition each grid class; interior bounds are multiples of 64
                 for (int32_t c = 0; c < T0; ++c) {
                     std::vector<char> own((size_t)r.csz[(size_t)c], 0);
                     for (int32_t b = 0; b < G; ++b) {
                         const GdiHaloEntry &e = L.tab[(size_t)b * C + c];
                         if (b < lead) CHECK(e.node_hi == e.node_lo, "%s: leader holds nodes", name);
+                        if (e.node_hi > e.node_lo) CHECK(e.node_lo % 64 == 0, "%s: chunk start", name);
                         for (int32_t v = e.node_lo; v < e.node_hi; ++v) {
                             const int32_t q = v - r.cbeg[(size_t)c];
                             CHECK(q >= 0 && q < r.csz[(size_t)c] && !own[(size_t)q], "%s: chunk overlap", name);
                             own[(size_t)q] = 1;
                         }
-                        CHECK(e.lds_off >= 0 && e.lds_off + e.win_len <= L.gather_off, "%s: window outside", name);
                     }
                     CHECK(std::all_of(own.begin(), own.end(), [](char x) { return x != 0; }), "%s: chunk gap", name);
                 }
@@ -202,13 +202,42 @@ long check_layouts(const Csr &g, const char *name)
                     for (int32_t c = 0; c < T0; ++c)
                         for (int32_t v = L.tab[(size_t)b * C + c].node_lo; v < L.tab[(size_t)b * C + c].node_hi; ++v)
                             owner[(size_t)v] = b;
+                // images: own words then foreign copies per class, inside [0, gather_off);
+                // foreign lists ascending, foreign to the block, copied in the list region
+                for (int32_t b = 0; b < G; ++b) {
+                    int32_t end = 0;
+                    for (int32_t c = 0; c < C; ++c) {
+                        const GdiHaloEntry &e = L.tab[(size_t)b * C + c];
+                        const int32_t nown = e.node_hi > e.node_lo ? ((e.node_hi + 31) >> 5) - (e.node_lo >> 5) : 0;
+                        CHECK(e.own_off >= end && e.for_off >= e.own_off + nown && e.for_len >= 0, "%s: image order", name);
+                        end = e.for_off + e.for_len;
+                        CHECK(end <= L.gather_off, "%s: image outside", name);
+                        CHECK(e.list_off >= L.list_off && e.list_off + e.for_len <= L.list_off + L.flist_len,
+                              "%s: list outside", name);
+                        const int32_t *lst = L.flist.data() + (size_t)b * L.flist_len + (e.list_off - L.list_off);
+                        for (int32_t i = 0; i < e.for_len; ++i) {
+                            const int32_t wd = lst[i];
+                            CHECK(wd >= 0 && wd * 32 < r.n_pad && (i == 0 || lst[i - 1] < wd), "%s: list order", name);
+                            const int32_t j0 = wd * 32;
+                            bool any_c = false, any_own = false;
+                            for (int32_t j = j0; j < j0 + 32; ++j) {
+                                any_c |= r.cls[(size_t)j] == c;
+                                any_own |= owner[(size_t)j] == b;
+                            }
+                            CHECK(any_c && !any_own, "%s: foreign word %d of class %d", name, wd, c);
+                        }
+                    }
+                }
                 const int32_t tail_base = T0 < C ? r.cbeg[(size_t)T0] : r.n_pad;
                 auto expect_lb = [&](int32_t b, int32_t j) {
                     const int32_t cj = r.cls[(size_t)j];
                     if (cj >= T0) return (L.tail_off + ((j - tail_base) >> 5)) * 32 + (j & 31);
                     const GdiHaloEntry &e = L.tab[(size_t)b * C + cj];
-                    CHECK((j >> 5) >= e.win_lo && (j >> 5) < e.win_lo + e.win_len, "%s: neighbour outside window", name);
-                    return (e.lds_off + (j >> 5) - e.win_lo) * 32 + (j & 31);
+                    if (owner[(size_t)j] == b) return (e.own_off + (j >> 5) - (e.node_lo >> 5)) * 32 + (j & 31);
+                    const int32_t *lst = L.flist.data() + (size_t)b * L.flist_len + (e.list_off - L.list_off);
+                    const int32_t *f = std::lower_bound(lst, lst + e.for_len, j >> 5);
+                    CHECK(f != lst + e.for_len && *f == (j >> 5), "%s: neighbour word not listed", name);
+                    return (e.for_off + (int32_t)(f - lst)) * 32 + (j & 31);
                 };
                 for (int32_t v = 0; v < r.n_pad; ++v) {
                     const int32_t cv = r.cls[(size_t)v];
