@@ -220,6 +220,21 @@ int gdi_cut(gdi_graph *g, const int8_t *spins, int64_t *cut_weighted, int64_t *c
 int gdi_cut_dev(gdi_graph *g, const int8_t *d_spins, int64_t *cut_weighted, int64_t *cut_edges,
                 int64_t *magnetization);
 
+/*
+ * gdi_cut_dev_noalloc -- for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): gdi_cut_dev
+ * without any allocation. d_spins: device, n int8 in original order (any non-positive
+ * value counts as -1); d_out: device, 3 int64 receiving the weighted cut, the
+ * crossing-edge count and M. Stream-ordered on the handle's stream (gdi_set_stream);
+ * returns after enqueueing and leaves a pending anneal's outcome untouched. Its scratch
+ * (the relabelled spin copy and the reduction's accumulators) lives in one fixed 16 MiB
+ * device array per GPU, held until the process ends: graphs with n + 64 * colours <=
+ * 16,760,576 and at most 4094 colour classes; GDI_ERANGE otherwise. Every call on one
+ * GPU uses that GPU's array, so calls that overlap on one GPU (any handle, any stream)
+ * race and must be serialised by the caller.
+ */
+int gdi_cut_dev_noalloc(gdi_graph *g, const int8_t *d_spins, int64_t *d_out);
+
 /* gdi_get_info -- graph facts. */
 int gdi_get_info(const gdi_graph *g, gdi_graph_info *out);
 

@@ -132,6 +132,7 @@ SIGNATURES = {
     "gdi_last_result": (ctypes.c_int, [_P, ctypes.POINTER(Result)]),
     "gdi_cut": (ctypes.c_int, [_P, _P, _P, _P, _P]),
     "gdi_cut_dev": (ctypes.c_int, [_P, _P, _P, _P, _P]),
+    "gdi_cut_dev_noalloc": (ctypes.c_int, [_P, _P, _P]),
     "gdi_get_info": (ctypes.c_int, [_P, ctypes.POINTER(GraphInfo)]),
     "gdi_get_colouring": (ctypes.c_int, [_P, _P, _P]),
     "gdi_colour_csr": (ctypes.c_int, [_P, _P, ctypes.c_int32, _P]),
@@ -275,6 +276,11 @@ def cut_dev(h, d_spins: int) -> tuple:
     cw, ce, m = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(lib().gdi_cut_dev(h, ctypes.c_void_p(d_spins), ctypes.byref(cw), ctypes.byref(ce), ctypes.byref(m)))
     return cw.value, ce.value, m.value
+
+
+def cut_dev_noalloc(h, d_spins: int, d_out: int) -> None:
+    """gdi_cut_dev_noalloc: writes (weighted cut, crossing count, M) as 3 int64 to d_out (device)."""
+    _check(lib().gdi_cut_dev_noalloc(h, ctypes.c_void_p(d_spins), ctypes.c_void_p(d_out)))
 
 
 def get_info(h) -> GraphInfo:
@@ -482,6 +488,9 @@ class Annealer:
 
     def cut_dev(self, d_spins: int):
         return cut_dev(self.h, d_spins)
+
+    def cut_dev_noalloc(self, d_spins: int, d_out: int):
+        cut_dev_noalloc(self.h, d_spins, d_out)
 
     def result(self) -> Result:
         return last_result(self.h)

@@ -1319,6 +1319,13 @@ int gdi_create(const int32_t *row_ptr, const int32_t *col_idx, const int32_t *we
         g->colour.assign((size_t)n, 0);
         g->C = gdi_layout::colour_first_fit(row_ptr, col_idx, n, g->colour.data());
         if ((rc = check_device())) { delete g; return rc; }
+        // set-up of the allocation-free entry point on this device: the address of its
+        // fixed scratch array (looked up once per device)
+        void *scratch = nullptr;
+        if (int e = gdi_scratch_ptr(&scratch)) {
+            delete g;
+            return fail(GDI_EDEVICE, std::string("scratch address: ") + gdi_hip_error_string(e));
+        }
         if ((rc = upload(g, row_ptr, col_idx, weights))) { delete g; return rc; }
     } catch (const std::bad_alloc &) {
         delete g;
@@ -1405,6 +1412,31 @@ int gdi_cut_dev(gdi_graph *g, const int8_t *d_spins, int64_t *cut_weighted, int6
     } catch (const std::bad_alloc &) {
         return fail(GDI_ENOMEM, "out of host memory");
     }
+}
+
+int gdi_cut_dev_noalloc(gdi_graph *g, const int8_t *d_spins, int64_t *d_out)
+{
+    if (!g) return fail(GDI_ESTATE, "NULL handle");
+    if (!d_spins || !d_out) return fail(GDI_EINVAL, "NULL device pointer");
+    if ((int64_t)g->n_pad > GDI_NOALLOC_MAX_NODES)
+        return fail(GDI_ERANGE, "graph too large for the fixed scratch array (n + 64 * colours must be <= " +
+                                    std::to_string(GDI_NOALLOC_MAX_NODES) + ")");
+    if (g->C > GDI_NOALLOC_MAX_C)
+        return fail(GDI_ERANGE, "more than " + std::to_string(GDI_NOALLOC_MAX_C) + " colour classes");
+    void *base = nullptr;
+    if (int e = gdi_scratch_ptr(&base)) return fail(GDI_EDEVICE, std::string("scratch address: ") + gdi_hip_error_string(e));
+    int64_t *red = static_cast<int64_t *>(base);
+    int32_t *P = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(base) + 256);
+    int8_t *sp = reinterpret_cast<int8_t *>(static_cast<unsigned char *>(base) + GDI_NOALLOC_SPIN_OFF);
+    hipStream_t st = g->stream;
+    // the accumulators and counts keep the last call's values: cleared by fill kernels
+    int rc = gdi_launch_gather_in(g->d_orig.p, d_spins, g->n_pad, sp, st);
+    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(red), 4, st);
+    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(P), (g->C + 2) / 2, st);
+    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, sp, g->n_pad, g->d_cbeg.p, g->d_csz.p, g->C, red, P, st);
+    if (!rc) rc = gdi_launch_cut_finish(red, d_out, st);
+    if (rc) return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
+    return GDI_OK;
 }
 
 int gdi_anneal_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed,

@@ -143,6 +143,13 @@ struct GdiMlpDev {
 };
 #define GDI_MLP_PARAMS (64 * 6 + 64 + 64 * 64 + 64 + 64 + 1)  // packed FP32 master parameters
 
+// Allocation-free cut (gdi_cut_dev_noalloc): fixed per-GPU scratch array.
+#define GDI_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)  // 16 MiB per GPU
+#define GDI_NOALLOC_MAX_C 4094                         // colour classes
+#define GDI_NOALLOC_SPIN_OFF 16640                     // 256 + 4 (GDI_NOALLOC_MAX_C + 2), 256-aligned
+#define GDI_NOALLOC_MAX_NODES ((int64_t)GDI_NOALLOC_SCRATCH_BYTES - GDI_NOALLOC_SPIN_OFF)  // n_pad limit
+#define GDI_NOALLOC_MAX_DEVICES 64
+
 // host-side launchers (gdi_kernels.hip)
 int gdi_launch_init_spins(const int32_t *orig, const int8_t *init_orig, int8_t *spin, int32_t n_pad,
                           uint32_t key0, uint32_t key1, uint32_t replica, void *stream);
@@ -150,6 +157,8 @@ int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, in
                       const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P,
                       void *stream);
 int gdi_launch_fill_u64(uint64_t *p, int64_t count, void *stream);
+int gdi_launch_cut_finish(const int64_t *red, int64_t *out3, void *stream);
+int gdi_scratch_ptr(void **out);
 int gdi_launch_scatter_out(const int32_t *orig, const int8_t *spin, int32_t n_pad, int8_t *out_orig,
                            void *stream);
 int gdi_launch_gather_in(const int32_t *orig, const int8_t *in_orig, int32_t n_pad, int8_t *spin,

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "gdi_internal.h"
 
@@ -1401,6 +1402,24 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     if (lane == 0 && w != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)w);
 }
 
+// ------------------------------------------------------------------ fixed scratch
+// Device memory of the allocation-free entry point (gdi_cut_dev_noalloc): one array per
+// GPU for the life of the process. Layout: [0, 32) the reduction's four int64
+// accumulators, [256, 256 + 4 (GDI_NOALLOC_MAX_C + 2)) the per-class counts, from
+// GDI_NOALLOC_SPIN_OFF the relabelled spin copy (n_pad bytes). Host code never uses the
+// name: it takes the address from gdi_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[GDI_NOALLOC_SCRATCH_BYTES];
+
+// Weighted cut, crossing count and M from the reduction's accumulators (doubled sums).
+__global__ void k_cut_finish(const int64_t *red, int64_t *out3)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        out3[0] = red[1] / 2;
+        out3[1] = red[2] / 2;
+        out3[2] = red[0];
+    }
+}
+
 // ------------------------------------------------------------------ helpers
 __global__ void k_init_spins(const int32_t *orig, const int8_t *init_orig, int8_t *spin, int32_t n_pad,
                              uint32_t key0, uint32_t key1, uint32_t replica)
@@ -1752,6 +1771,33 @@ int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, in
     hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, (hipStream_t)stream, rp, adj, spin, n_pad, cbeg, csz, C,
                        out3, P);
     return status(hipGetLastError());
+}
+
+int gdi_launch_cut_finish(const int64_t *red, int64_t *out3, void *stream)
+{
+    hipLaunchKernelGGL(k_cut_finish, dim3(1), dim3(64), 0, (hipStream_t)stream, red, out3);
+    return status(hipGetLastError());
+}
+
+// Address of this GPU's scratch array: looked up once per device, with the device
+// current, through hipGetSymbolAddress, and kept (each GPU holds its own copy).
+int gdi_scratch_ptr(void **out)
+{
+    static std::mutex mu;
+    static void *addr[GDI_NOALLOC_MAX_DEVICES] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return status(e);
+    if (dev < 0 || dev >= GDI_NOALLOC_MAX_DEVICES) return (int)hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return status(e);
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return 0;
 }
 
 int gdi_dense_lds_bytes(int32_t n_pad, int32_t C) { return ((C + 3) & ~3) * 4 + 2 * n_pad; }
