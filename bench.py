@@ -455,6 +455,11 @@ def main():
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, temps, seed, min(args.cpu_sweeps, S), min(args.cpu_sweeps_one, S))
     print(json.dumps(line), flush=True)
+    # every handle is closed by now; leave no device work or library object to process exit
+    import gc
+
+    gc.collect()
+    torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

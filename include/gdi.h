@@ -128,9 +128,9 @@ typedef struct {
     uint32_t lanes_per_node;  /* 1, 2, 4, 8, 16, 32 or 64 lanes share one CSR row */
     int32_t tail_max;         /* GDI_SCOPE_GRID: most nodes in the redundant tail of small
                                  classes run by every workgroup without grid barriers
-                                 (0 = automatic: one node per worker thread on grids of
-                                 at most 128 workgroups, none above; < 0 = no tail; > 0 =
-                                 at most this many, capped at one per worker thread) */
+                                 (0 = automatic: at most one node per worker thread;
+                                 < 0 = no tail; > 0 = at most this many, capped at one
+                                 per worker thread) */
     uint64_t spin_limit;      /* polls before a device-side barrier wait gives up with
                                  GDI_ETIMEOUT (0 = default, about a second) */
     int32_t leaders;          /* GDI_SCOPE_GRID: > 0 = the 8 workgroups that collect the

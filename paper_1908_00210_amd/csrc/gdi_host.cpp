@@ -44,6 +44,15 @@ int hip_fail(hipError_t e, const char *what)
         if (e_ != hipSuccess) return hip_fail(e_, (what));    \
     } while (0)
 
+// Fault injection for testing the GDI_ENOMEM paths: with the environment variable
+// GDI_FAULT set to "alloc", every device allocation the library attempts fails as if
+// the device were out of memory (read at each allocation).
+inline bool alloc_fault()
+{
+    const char *f = std::getenv("GDI_FAULT");
+    return f && std::strcmp(f, "alloc") == 0;
+}
+
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
@@ -59,6 +68,7 @@ struct DevBuf {
     {
         if (count <= n && p) return hipSuccess;
         release();
+        if (alloc_fault()) return hipErrorOutOfMemory;
         void *q = nullptr;
         hipError_t e = hipMalloc(&q, std::max<size_t>(count, 1) * sizeof(T));
         if (e != hipSuccess) return e;
@@ -204,10 +214,10 @@ int pick_launch(gdi_graph *g, Choice *ch)
             return fail(GDI_EINVAL, "the grid sweep needs a grid that is a multiple of 8 in [8, 512]");
         const int32_t nwork = (int32_t)block - 64;  // worker threads: all but the barrier wave
         // the redundant tail (its gather words read a phase late) saves its classes'
-        // grid barriers but every workgroup reads every gather word: on by default up to
-        // 128 workgroups (measured: 5-9 % faster on a 2e5-node RGG at 128 workgroups,
-        // 3 % slower on a 1e6-node RGG at 256); tail_max > 0 forces it
-        const int32_t tail_auto = G <= 128 ? nwork : 0;
+        // grid barriers but every workgroup reads every gather word: on by default
+        // (measured with the foreign-word layout: 108.3 -> 104.9 ms on a 1e6-node RGG at
+        // 256 workgroups; 5-9 % faster on a 2e5-node RGG at 128); tail_max < 0 turns it off
+        const int32_t tail_auto = nwork;
         const int32_t tail_cap = t.tail_max < 0 ? 0 : (t.tail_max == 0 ? tail_auto : std::min(t.tail_max, nwork));
         // dedicated group leaders: blocks 0..7 hold no nodes (automatic: never)
         const int32_t lead = t.leaders > 0 ? 8 : 0;
@@ -350,6 +360,10 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0, int32_t 
 int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork, int32_t lead)
 {
     if (g->halo_G == G && g->halo_nwork == nwork && g->halo_lead == lead && g->halo_lds_words != -1) return GDI_OK;
+    // a rebuild reallocates the layout's buffers: the old layout is invalid from here on,
+    // also if the rebuild fails
+    g->halo_G = 0;
+    g->halo_lds_words = -1;
     const int32_t C = g->C;
     int32_t T0 = C;
     int64_t tail_n = 0;
@@ -437,6 +451,10 @@ int ensure_table(gdi_graph *g, const gdi_schedule *s, int64_t de_max)
     int32_t K = 0;
     int rc = build_table(s->temps, S, de_max, &K, tab, s->acceptance);
     if (rc) return rc;
+    // the cached table is gone once its buffer is reallocated: forget it first, so that a
+    // failed allocation or upload never leaves a key that names a released buffer
+    g->thr_K = -1;
+    g->thr_key.clear();
     HIP_TRY(g->d_thr.reserve(tab.size()), "hipMalloc thresholds");
     HIP_TRY(hipMemcpyAsync(g->d_thr.p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, g->stream),
             "upload thresholds");
