@@ -24,6 +24,32 @@ METRIC = "spin-updates/s + HBM GB/s; cut @ fixed wall time: plain vs batched/lea
 HBM_PEAK_GBS = 8000.0
 
 
+def halo_source_hash() -> str:
+    """SHA-256 (16 hex digits) of the halo sweep's sources: its kernel file and the shared
+    device helpers it includes. Counter figures stand only for the source they were taken on."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in ("gdi_halo.hip", "gdi_device.h"):
+        with open(os.path.join(ROOT, "paper_1908_00210_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def counter_bytes_per_sweep(path: str, workload: str):
+    """HBM bytes per sweep of the halo sweep on a workload from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's readings), or None when
+    there is none for this workload or it was taken on another source of the kernel."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tj = json.load(f)
+    if tj.get("kernel_source_sha256_16") != halo_source_hash():
+        return None
+    w = tj.get("workloads", {}).get(workload)
+    return None if w is None else float(w["hbm_bytes_per_sweep"])
+
+
 def algorithmic_bytes_per_sweep(n: int, nnz: int) -> int:
     """row_ptr (4(n+1)) + CSR column and weight (8 nnz) + spin read and write (2n)."""
     return 4 * (n + 1) + 8 * nnz + 2 * n
@@ -119,6 +145,9 @@ def config_runs(gdi, gs, torch, seed, names, reps=5):
                "spin_updates_per_s": g.n * T.size / kern_s,
                "algorithmic_gbs": algorithmic_bytes_per_sweep(g.n, g.nnz) * T.size / kern_s / 1e9,
                "M": int(m), "cut_weighted": int(cw), "cut_edges": int(ce)}
+        cb = counter_bytes_per_sweep(os.path.join(ROOT, "profiles", "traffic.json"), name)
+        if cb is not None and r.scope == gdi.SCOPE_GRID:
+            row["hbm_gbs_counters"] = cb * T.size / kern_s / 1e9
         if g.n <= 100_000:
             ref = oracle.anneal(g, T, seed)
             row["oracle_sweep_s"] = ref["sweep_s"]
@@ -328,6 +357,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched / learned comparisons")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--source-hash", action="store_true", help="print the halo sweep's source hash and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (for scaling HBM counters) and exit")
     args = ap.parse_args()
@@ -337,6 +367,9 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.source_hash:
+        print(halo_source_hash())
+        return
     import numpy as np
     import torch
 
@@ -389,17 +422,8 @@ def main():
     kern_s = float(np.mean(sweep_ms)) / 1e3
     bytes_launch = algorithmic_bytes_per_sweep(n, nnz) * S
     achieved = bytes_launch / kern_s / 1e9
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        # counters only stand for the kernel source they were taken on
-        import hashlib
-
-        with open(args.traffic_json) as f:
-            tj = json.load(f)
-        with open(os.path.join(ROOT, "paper_1908_00210_amd", "csrc", "gdi_kernels.hip"), "rb") as f:
-            src = hashlib.sha256(f.read()).hexdigest()[:16]
-        if tj.get("workload") == args.workload and tj.get("kernel_source_sha256_16") == src:
-            traffic = tj["hbm_bytes_per_sweep"] * S
+    per_sweep = counter_bytes_per_sweep(args.traffic_json, args.workload) if res.scope == gdi.SCOPE_GRID else None
+    traffic = per_sweep * S if per_sweep is not None else None
     counter_gbs = traffic / kern_s / 1e9 if traffic is not None else None
     grid_phases = int(info.n_colours)
     line = {

@@ -140,6 +140,14 @@ typedef struct {
     int32_t general_weights;  /* GDI_SCOPE_GRID: > 0 = run the general-weight form of the
                                  sweep even when every weight is 1 (for measuring what the
                                  unit-weight form saves; same results); 0 = automatic */
+    int32_t csr_lds;          /* GDI_SCOPE_WORKGROUP: the whole graph (spins, ids, 16-bit
+                                 CSR) in LDS; needs n_pad <= 32768, nnz <= 65535 and +-1
+                                 weights. 0 = whenever it fits, < 0 = never, > 0 = required
+                                 (GDI_ERANGE if it does not fit) */
+    int32_t batch_members;    /* batched form: most workgroups one large instance may run on
+                                 (a cluster; instances above twice the per-workgroup share
+                                 of the batch's work); 0 = automatic (up to 16), < 0 or 1 =
+                                 one workgroup per instance */
 } gdi_tuning;
 
 /* Outcome of the last anneal on a handle. */
@@ -303,6 +311,44 @@ int gdi_anneal_batch_dev(gdi_instance *inst, uint32_t n_inst, const gdi_schedule
  */
 int gdi_autotune_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed,
                        uint32_t probe_sweeps, gdi_tuning *best, double *best_ms);
+
+/*
+ * gdi_autotune -- time launch choices for one graph (the workgroup sweep with the CSR in
+ * LDS or global memory, lanes per node and block size; the halo grid sweep on 8 to 256
+ * workgroups, with and without the redundant tail and dedicated leaders) on the first
+ * probe_sweeps sweeps of the schedule (0 = n_sweeps / 50, at least 1; flags must be 0),
+ * install the fastest on the handle as gdi_set_tuning does, and return it in best (and
+ * its device time in best_ms, may be NULL). With use_cache != 0 a cached choice for this
+ * device and graph shape (n, nnz, colours, maximum degree, weight kind) is installed
+ * without timing. Results never depend on the choice. Runs anneals on the handle, so its
+ * last result is overwritten. Errors: GDI_ESTATE (NULL handle), GDI_EINVAL (NULL best,
+ * bad schedule), GDI_EDEVICE, GDI_ENOMEM, GDI_ETIMEOUT; on an error the handle's tuning
+ * is left as it was.
+ */
+int gdi_autotune(gdi_graph *g, const gdi_schedule *s, uint64_t seed, uint32_t probe_sweeps, int use_cache,
+                 gdi_tuning *best, double *best_ms);
+
+/*
+ * The autotuners' cache: choices keyed by device ("<arch>/<CUs>cu") and problem shape,
+ * used by gdi_autotune (use_cache) and by gdi_anneal_batch (tune == NULL). If the
+ * environment variable GDI_TUNE_CACHE names a file, the cache is read from it at the
+ * first lookup of the process and written back after every tuning run (a missing or
+ * malformed file is ignored there). The file is JSON:
+ *   {"format": "gdi-tune-1", "entries": {"<key>": {"scope": .., "block": .., "grid": ..,
+ *    "lanes_per_node": .., "tail_max": .., "leaders": .., "general_weights": ..,
+ *    "csr_lds": .., "batch_members": .., "ms": <measured time>}, ...}}
+ * Entries whose fields are missing or out of range are ignored at lookup. No GPU needed.
+ * gdi_tune_cache_load -- merge the entries of a file (same keys replaced); GDI_EINVAL
+ *   (NULL path, unreadable file, not this format: then nothing is merged).
+ * gdi_tune_cache_save -- write the whole cache to path (through a temporary file and a
+ *   rename); GDI_EINVAL (NULL path, cannot write).
+ * gdi_tune_cache_clear -- empty the in-memory cache (the file is not touched).
+ * gdi_tune_cache_size -- number of entries in the in-memory cache.
+ */
+int gdi_tune_cache_load(const char *path);
+int gdi_tune_cache_save(const char *path);
+int gdi_tune_cache_clear(void);
+int gdi_tune_cache_size(void);
 
 /* ------------------------------------------------------------------ learned proposal
  * A network predicts which nodes stay frozen at the current temperature; masked

@@ -63,7 +63,8 @@ class Schedule(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("scope", ctypes.c_uint32), ("block", ctypes.c_uint32), ("grid", ctypes.c_uint32),
                 ("lanes_per_node", ctypes.c_uint32), ("tail_max", ctypes.c_int32), ("spin_limit", ctypes.c_uint64),
-                ("leaders", ctypes.c_int32), ("general_weights", ctypes.c_int32)]
+                ("leaders", ctypes.c_int32), ("general_weights", ctypes.c_int32), ("csr_lds", ctypes.c_int32),
+                ("batch_members", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -145,6 +146,12 @@ SIGNATURES = {
     "gdi_autotune_batch": (ctypes.c_int, [ctypes.POINTER(Instance), ctypes.c_uint32, ctypes.POINTER(Schedule),
                                           ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(Tuning),
                                           ctypes.POINTER(ctypes.c_double)]),
+    "gdi_autotune": (ctypes.c_int, [_P, ctypes.POINTER(Schedule), ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
+                                    ctypes.POINTER(Tuning), ctypes.POINTER(ctypes.c_double)]),
+    "gdi_tune_cache_load": (ctypes.c_int, [ctypes.c_char_p]),
+    "gdi_tune_cache_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "gdi_tune_cache_clear": (ctypes.c_int, []),
+    "gdi_tune_cache_size": (ctypes.c_int, []),
     "gdi_anneal_learned": (ctypes.c_int, [_P, ctypes.POINTER(Schedule), ctypes.c_uint64, _P,
                                           ctypes.POINTER(LearnedCfg), _P, ctypes.POINTER(LearnedResult)]),
     "gdi_collect_traces": (ctypes.c_int, [_P, ctypes.POINTER(Schedule), ctypes.c_uint64, ctypes.c_uint32,
@@ -209,11 +216,12 @@ def set_stream(h, stream_ptr: int | None):
 
 
 def set_tuning(h, scope: int = 0, block: int = 0, grid: int = 0, lanes_per_node: int = 0,
-               spin_limit: int = 0, tail_max: int = 0, leaders: int = 0, general_weights: int = 0, reset=False):
+               spin_limit: int = 0, tail_max: int = 0, leaders: int = 0, general_weights: int = 0, csr_lds: int = 0,
+               reset=False):
     if reset:
         _check(lib().gdi_set_tuning(h, None))
         return
-    t = Tuning(scope, block, grid, lanes_per_node, tail_max, spin_limit, leaders, general_weights)
+    t = Tuning(scope, block, grid, lanes_per_node, tail_max, spin_limit, leaders, general_weights, csr_lds)
     _check(lib().gdi_set_tuning(h, ctypes.byref(t)))
 
 
@@ -344,7 +352,8 @@ def anneal_batch(items, temps, seed: int, A: int = 1, B: int = 1, mode: int = BA
             arr[i].spins_out = None
     s, T = _schedule(temps, A, B, 0, mode, 0, None, None, None, acceptance)
     t = None if tune is None else ctypes.byref(Tuning(tune.get("scope", 0), tune.get("block", 0), tune.get("grid", 0),
-                                                       tune.get("lanes_per_node", 0), 0, 0))
+                                                       tune.get("lanes_per_node", 0), 0, 0, 0, 0, 0,
+                                                       tune.get("batch_members", 0)))
     ms = ctypes.c_double()
     fn = lib().gdi_anneal_batch_dev if device_outputs is not None else lib().gdi_anneal_batch
     _check(fn(arr, k, ctypes.byref(s), ctypes.c_uint64(seed), t, ctypes.byref(ms)))
@@ -364,7 +373,41 @@ def autotune_batch(items, temps, seed: int, probe_sweeps: int, A: int = 1, B: in
     ms = ctypes.c_double()
     _check(lib().gdi_autotune_batch(arr, k, ctypes.byref(s), ctypes.c_uint64(seed), probe_sweeps, ctypes.byref(best),
                                     ctypes.byref(ms)))
-    return dict(block=best.block, grid=best.grid, lanes_per_node=best.lanes_per_node), ms.value
+    return _tuning_dict(best), ms.value
+
+
+def _tuning_dict(t: Tuning) -> dict:
+    """The non-default fields of a Tuning (the keys set_tuning and anneal_batch take)."""
+    keys = ("scope", "block", "grid", "lanes_per_node", "tail_max", "leaders", "general_weights", "csr_lds",
+            "batch_members")
+    return {k: int(getattr(t, k)) for k in keys if getattr(t, k)}
+
+
+def autotune(h, temps, seed: int, probe_sweeps: int = 0, use_cache: bool = False, A: int = 1, B: int = 1,
+             mode: int = BAL_GATED) -> tuple:
+    """gdi_autotune: installs the fastest launch choice on the handle; returns (tuning dict, probe ms)."""
+    s, T = _schedule(temps, A, B, 0, mode, 0, None, None, None)
+    best = Tuning()
+    ms = ctypes.c_double()
+    _check(lib().gdi_autotune(h, ctypes.byref(s), ctypes.c_uint64(seed), int(probe_sweeps), int(bool(use_cache)),
+                              ctypes.byref(best), ctypes.byref(ms)))
+    return _tuning_dict(best), ms.value
+
+
+def tune_cache_load(path: str):
+    _check(lib().gdi_tune_cache_load(os.fsencode(path)))
+
+
+def tune_cache_save(path: str):
+    _check(lib().gdi_tune_cache_save(os.fsencode(path)))
+
+
+def tune_cache_clear():
+    _check(lib().gdi_tune_cache_clear())
+
+
+def tune_cache_size() -> int:
+    return _check(lib().gdi_tune_cache_size())
 
 
 def _weights(w) -> np.ndarray:
@@ -497,6 +540,9 @@ class Annealer:
 
     def tune(self, **kw):
         set_tuning(self.h, **kw)
+
+    def autotune(self, temps, seed, probe_sweeps=0, use_cache=False, **kw) -> tuple:
+        return autotune(self.h, temps, seed, probe_sweeps, use_cache, **kw)
 
     def set_stream(self, stream_ptr):
         set_stream(self.h, stream_ptr)

@@ -8,9 +8,11 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgdi.so")
-SOURCES = [os.path.join(CSRC, "gdi_kernels.hip"), os.path.join(CSRC, "gdi_learned.hip"),
-           os.path.join(CSRC, "gdi_host.cpp"), os.path.join(CSRC, "gdi_layout.cpp")]
-HEADERS = [os.path.join(CSRC, "gdi_internal.h"), os.path.join(CSRC, "gdi_layout.h"),
+SOURCES = [os.path.join(CSRC, "gdi_kernels.hip"), os.path.join(CSRC, "gdi_halo.hip"),
+           os.path.join(CSRC, "gdi_learned.hip"), os.path.join(CSRC, "gdi_host.cpp"),
+           os.path.join(CSRC, "gdi_layout.cpp"), os.path.join(CSRC, "gdi_tunecache.cpp")]
+HEADERS = [os.path.join(CSRC, "gdi_internal.h"), os.path.join(CSRC, "gdi_device.h"),
+           os.path.join(CSRC, "gdi_layout.h"), os.path.join(CSRC, "gdi_tunecache.h"),
            os.path.join(HERE, "..", "include", "gdi.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -21,6 +21,7 @@
 
 #include "../../include/gdi.h"
 #include "gdi_internal.h"
+#include "gdi_tunecache.h"
 
 namespace {
 
@@ -85,6 +86,7 @@ struct gdi_graph {
     int64_t nnz = 0;
     int64_t max_abs_wdeg = 0;
     int32_t max_degree = 0;
+    int32_t wkind = 0;                // 2: every weight +1; 1: every weight +-1; 0: general
     std::vector<int32_t> colour;      // original order
     gdi_layout::Relabelled rl;        // colour-major relabelling; new-id CSR kept for launch layouts
 
@@ -98,12 +100,20 @@ struct gdi_graph {
     DevBuf<uint32_t> d_tail_ent;
     int32_t halo_ovf_off = 0, halo_ovf_len = 0, halo_unit_w = 0;
     int32_t halo_list_off = 0, halo_flist_len = 0;
+    // epochs of the packed spin, member and group words: the next launch's base, and
+    // whether the words hold only epochs below it (false after they are allocated)
+    uint32_t halo_epoch = 0;
+    bool halo_words_clean = false;
     DevBuf<uint32_t> d_ovf;
     DevBuf<int32_t> d_flist;
     DevBuf<GdiHaloEntry> d_tab;
     DevBuf<uint64_t> d_words, d_member, d_group;
 
     DevBuf<int32_t> d_rp, d_orig, d_cbeg, d_csz, d_P;
+    // 16-bit copies of the relabelled CSR for the LDS-resident workgroup sweep (graphs with
+    // n_pad <= 32768, nnz <= 65535 and +-1 weights; wgl_ok)
+    bool wgl_ok = false;
+    DevBuf<uint16_t> d_rp16, d_ent16;
     DevBuf<int2> d_adj;
     DevBuf<int8_t> d_spin, d_io;
     DevBuf<int64_t> d_state, d_red, d_trace;
@@ -129,6 +139,7 @@ struct gdi_graph {
     ~gdi_graph()
     {
         d_rp.release(); d_orig.release(); d_cbeg.release(); d_csz.release(); d_P.release();
+        d_rp16.release(); d_ent16.release();
         d_adj.release(); d_spin.release(); d_io.release(); d_state.release(); d_red.release();
         d_trace.release(); d_thr.release(); d_bar.release();
         d_adjL.release(); d_tail_v.release(); d_tail_beg.release(); d_gat_words.release(); d_gat_beg.release();
@@ -161,6 +172,7 @@ uint32_t threshold_of(int64_t d, double T)
 struct Choice {
     uint32_t scope, block, grid, lanes;
     bool spins_lds;
+    bool csr_lds;  // workgroup scope with the whole graph in LDS (k_sweep_wgl)
 };
 
 int lanes_for_degree(double avg_deg)
@@ -190,6 +202,7 @@ int pick_launch(gdi_graph *g, Choice *ch)
         return fail(GDI_EINVAL, "unknown scope");
     ch->grid = 1;
     ch->spins_lds = false;
+    ch->csr_lds = false;
     int dev = 0, lds_max = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
@@ -200,6 +213,12 @@ int pick_launch(gdi_graph *g, Choice *ch)
         ch->spins_lds = gdi_wg_lds_bytes(g->n_pad, g->C, 1) + fixed <= lds_max;
         if (gdi_wg_lds_bytes(g->n_pad, g->C, 0) + fixed > lds_max)
             return fail(GDI_ERANGE, "too many colour classes for one workgroup's LDS");
+        // the whole graph in LDS when it fits (+-1 weights, 16-bit CSR)
+        const bool wgl_fits = g->wgl_ok && gdi_wgl_lds_bytes(g->n_pad, g->C, (int32_t)g->nnz) + fixed <= lds_max;
+        if (t.csr_lds > 0 && !wgl_fits)
+            return fail(GDI_ERANGE, "the graph does not fit one workgroup's LDS as a 16-bit CSR "
+                                    "(needs n_pad <= 32768, nnz <= 65535, weights +-1)");
+        ch->csr_lds = wgl_fits && t.csr_lds >= 0;
         return GDI_OK;
     }
     if (ch->scope == GDI_SCOPE_GRID) {
@@ -290,6 +309,20 @@ int upload(gdi_graph *g, const int32_t *rp, const int32_t *col, const int32_t *w
     HIP_TRY(hipMemcpy(g->d_orig.p, g->rl.orig.data(), g->rl.orig.size() * 4, hipMemcpyHostToDevice), "upload orig");
     HIP_TRY(hipMemcpy(g->d_cbeg.p, g->rl.cbeg.data(), g->rl.cbeg.size() * 4, hipMemcpyHostToDevice), "upload classes");
     HIP_TRY(hipMemcpy(g->d_csz.p, g->rl.csz.data(), g->rl.csz.size() * 4, hipMemcpyHostToDevice), "upload classes");
+    g->wkind = 2;
+    for (size_t k = 0; k < adj.size() && g->wkind > 0; ++k)
+        g->wkind = std::min(g->wkind, adj[k].y == 1 ? 2 : (adj[k].y == -1 ? 1 : 0));
+    // the LDS-resident workgroup sweep's 16-bit CSR: column | (weight < 0) << 15
+    g->wgl_ok = g->n_pad <= 32768 && g->nnz <= 65535 && g->wkind > 0;
+    if (g->wgl_ok) {
+        std::vector<uint16_t> rp16(nrp.size()), ent16(std::max<size_t>(adj.size(), 1), 0);
+        for (size_t i = 0; i < nrp.size(); ++i) rp16[i] = (uint16_t)nrp[i];
+        for (size_t k = 0; k < adj.size(); ++k) ent16[k] = (uint16_t)(adj[k].x | (adj[k].y < 0 ? 0x8000 : 0));
+        HIP_TRY(g->d_rp16.reserve(rp16.size()), "hipMalloc 16-bit CSR");
+        HIP_TRY(g->d_ent16.reserve(ent16.size()), "hipMalloc 16-bit CSR");
+        HIP_TRY(hipMemcpy(g->d_rp16.p, rp16.data(), rp16.size() * 2, hipMemcpyHostToDevice), "upload 16-bit CSR");
+        HIP_TRY(hipMemcpy(g->d_ent16.p, ent16.data(), ent16.size() * 2, hipMemcpyHostToDevice), "upload 16-bit CSR");
+    }
     HIP_TRY(hipEventCreate(&g->ev0), "hipEventCreate");
     HIP_TRY(hipEventCreate(&g->ev1), "hipEventCreate");
     return GDI_OK;
@@ -351,6 +384,7 @@ int build_halo_for(gdi_graph *g, int32_t G, int lds_budget, int32_t T0, int32_t 
     g->halo_ovf_len = L.ovf_len;
     g->halo_list_off = L.list_off;
     g->halo_flist_len = L.flist_len;
+    g->halo_words_clean = false;
     return GDI_OK;
 }
 
@@ -660,7 +694,9 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
     } else if (r.dense) {
         rc = gdi_launch_sweep_dense(a, (int)r.ch.block, (int)r.ch.lanes, st);
     } else if (r.ch.scope == GDI_SCOPE_WORKGROUP) {
-        rc = gdi_launch_sweep_wg(a, (int)r.ch.block, (int)r.ch.lanes, r.ch.spins_lds ? 1 : 0, st);
+        rc = r.ch.csr_lds ? gdi_launch_sweep_wgl(a, g->d_rp16.p, g->d_ent16.p, (int32_t)g->nnz, (int)r.ch.block,
+                                                 (int)r.ch.lanes, st)
+                          : gdi_launch_sweep_wg(a, (int)r.ch.block, (int)r.ch.lanes, r.ch.spins_lds ? 1 : 0, st);
     } else if (r.ch.scope == GDI_SCOPE_GRID) {
         GdiHaloArgs ha{};
         ha.base = a;
@@ -691,10 +727,19 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
         ha.flist_len = g->halo_flist_len;
         ha.flist = g->d_flist.p;
         ha.thr_in_lds = r.thr_in_lds;
-        rc = gdi_launch_fill_u64(g->d_words.p, (int64_t)g->n_pad / 32 + 1, st);
-        if (!rc) rc = gdi_launch_fill_u64(g->d_member.p, 8 * 64, st);
-        if (!rc) rc = gdi_launch_fill_u64(g->d_group.p, 2 * 8 * GDI_HALO_GROUP_PAD, st);
+        // epochs continue from launch to launch; the words are cleared only when they may
+        // hold larger ones (new buffers) or the epochs would wrap
+        const uint64_t span = (uint64_t)(t_to - t_from) * (uint64_t)std::max(g->halo_T0, 1) + 4;
+        if (!g->halo_words_clean || (uint64_t)g->halo_epoch + span > 0x7FFFFFFFull) {
+            rc = gdi_launch_fill_u64(g->d_words.p, (int64_t)g->n_pad / 32 + 1, st);
+            if (!rc) rc = gdi_launch_fill_u64(g->d_member.p, 8 * 64, st);
+            if (!rc) rc = gdi_launch_fill_u64(g->d_group.p, 2 * 8 * GDI_HALO_GROUP_PAD, st);
+            g->halo_epoch = 0;
+            g->halo_words_clean = rc == 0;
+        }
+        ha.epoch0 = g->halo_epoch;
         if (!rc) rc = gdi_launch_sweep_halo(ha, (int)r.ch.grid, (int)r.ch.block, st);
+        g->halo_epoch += (uint32_t)span;  // also after a failed launch: its words stay below
     } else {
         const uint64_t phases = (uint64_t)(t_to - t_from) * (uint64_t)g->C;
         const uint64_t words = phases * (GDI_BAR_GROUPS + 1) * GDI_BAR_PAD;
@@ -778,10 +823,116 @@ int cut_impl(gdi_graph *g, const int8_t *spins, bool dev, int64_t *cw, int64_t *
     return GDI_OK;
 }
 
-// ------------------------------------------------------------------ batched form
+// ------------------------------------------------------------------ autotuner cache
+// Launch choices the autotuners found, keyed by "<arch>/<CUs>cu|batch|..." or
+// "<arch>/<CUs>cu|graph|..." (device, then problem shape). Held in memory and, when
+// the environment variable GDI_TUNE_CACHE names a file, in that JSON file: read at the
+// first lookup of the process, rewritten after every tuning run. The file is a hint:
+// a missing, unreadable or malformed one leaves the in-memory cache as it is.
 std::mutex g_tune_mu;
-std::map<std::string, gdi_tuning> g_tune_cache;
+gdi_tunecache::Table g_tune_table;
+bool g_tune_env_read = false;
 
+const char *tune_env_path()
+{
+    const char *p = std::getenv("GDI_TUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+void tune_env_read_locked()
+{
+    if (g_tune_env_read) return;
+    g_tune_env_read = true;
+    const char *p = tune_env_path();
+    std::string text, err;
+    if (p && gdi_tunecache::read_file(p, &text)) (void)gdi_tunecache::parse(text, &g_tune_table, &err);
+}
+
+gdi_tunecache::Fields tuning_fields(const gdi_tuning &t, double ms)
+{
+    gdi_tunecache::Fields f;
+    f["scope"] = t.scope;
+    f["block"] = t.block;
+    f["grid"] = t.grid;
+    f["lanes_per_node"] = t.lanes_per_node;
+    f["tail_max"] = t.tail_max;
+    f["leaders"] = t.leaders;
+    f["general_weights"] = t.general_weights;
+    f["csr_lds"] = t.csr_lds;
+    f["batch_members"] = t.batch_members;
+    f["ms"] = ms;
+    return f;
+}
+
+// false when a field is missing, not an integer or out of its range
+bool fields_tuning(const gdi_tunecache::Fields &f, gdi_tuning *t, double *ms)
+{
+    auto get = [&](const char *k, double lo, double hi, double *v) {
+        auto it = f.find(k);
+        if (it == f.end() || !(it->second >= lo && it->second <= hi) || it->second != std::floor(it->second))
+            return false;
+        *v = it->second;
+        return true;
+    };
+    double v[9];
+    if (!get("scope", 0, GDI_SCOPE_GRID_FENCED, &v[0]) || !get("block", 0, GDI_MAX_BLOCK, &v[1]) ||
+        !get("grid", 0, 1 << 20, &v[2]) || !get("lanes_per_node", 0, 64, &v[3]) ||
+        !get("tail_max", -1, 1 << 20, &v[4]) || !get("leaders", -1, 1, &v[5]) ||
+        !get("general_weights", -1, 1, &v[6]) || !get("csr_lds", -1, 1, &v[7]) ||
+        !get("batch_members", -1, GDI_BATCH_MAX_MEMBERS, &v[8]))
+        return false;
+    gdi_tuning r{};
+    r.scope = (uint32_t)v[0];
+    r.block = (uint32_t)v[1];
+    r.grid = (uint32_t)v[2];
+    r.lanes_per_node = (uint32_t)v[3];
+    r.tail_max = (int32_t)v[4];
+    r.leaders = (int32_t)v[5];
+    r.general_weights = (int32_t)v[6];
+    r.csr_lds = (int32_t)v[7];
+    r.batch_members = (int32_t)v[8];
+    *t = r;
+    auto it = f.find("ms");
+    *ms = it != f.end() ? it->second : 0.0;
+    return true;
+}
+
+bool tune_lookup(const std::string &key, gdi_tuning *t, double *ms)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_env_read_locked();
+    auto it = g_tune_table.find(key);
+    return it != g_tune_table.end() && fields_tuning(it->second, t, ms);
+}
+
+void tune_store(const std::string &key, const gdi_tuning &t, double ms)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_env_read_locked();
+    g_tune_table[key] = tuning_fields(t, ms);
+    if (const char *p = tune_env_path()) (void)gdi_tunecache::write_file(p, gdi_tunecache::dump(g_tune_table));
+}
+
+// "<arch>/<CUs>cu" of the current device ("" if it cannot be queried)
+std::string device_tag()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return arch + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+}
+
+std::string graph_key(const gdi_graph *g)
+{
+    return device_tag() + "|graph|n=" + std::to_string(g->n) + "|nnz=" + std::to_string(g->nnz) +
+           "|C=" + std::to_string(g->C) + "|maxdeg=" + std::to_string(g->max_degree) +
+           "|w=" + (g->wkind == 2 ? "unit" : g->wkind == 1 ? "pm1" : "general");
+}
+
+// ------------------------------------------------------------------ batched form
 std::string batch_key(const gdi_instance *inst, uint32_t n_inst)
 {
     int64_t sn = 0, snnz = 0;
@@ -792,10 +943,122 @@ std::string batch_key(const gdi_instance *inst, uint32_t n_inst)
         mx = std::max(mx, inst[i].graph->n_pad);
         mc = std::max(mc, inst[i].graph->C);
     }
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    return std::to_string(dev) + ":" + std::to_string(n_inst) + ":" + std::to_string(sn) + ":" +
-           std::to_string(snnz) + ":" + std::to_string(mx) + ":" + std::to_string(mc);
+    return device_tag() + "|batch|inst=" + std::to_string(n_inst) + "|n=" + std::to_string(sn) +
+           "|nnz=" + std::to_string(snnz) + "|maxnpad=" + std::to_string(mx) + "|maxC=" + std::to_string(mc);
+}
+
+// Single-graph autotuner: coordinate descent over the launch choices that apply to the
+// graph -- the workgroup sweep (graphs of at most 65536 padded nodes) with the CSR in
+// LDS or global memory, the halo grid sweep on 8 .. 256 workgroups -- then lanes per
+// node and block size (workgroup sweep) or the redundant tail and dedicated leaders
+// (grid sweep). Each candidate is timed as the best device time of two runs over the
+// first probe sweeps of the schedule; a candidate that does not fit is skipped.
+int autotune_graph(gdi_graph *g, const gdi_schedule *s, uint64_t seed, uint32_t probe, gdi_tuning *best,
+                   double *best_ms)
+{
+    if (!g) return fail(GDI_ESTATE, "NULL handle");
+    if (!s || !s->temps || s->n_sweeps < 1) return fail(GDI_EINVAL, "bad schedule");
+    if (s->flags) return fail(GDI_EINVAL, "the autotuner times the deterministic sweep (schedule flags 0)");
+    gdi_schedule ps = *s;
+    ps.n_sweeps = std::max<uint32_t>(1, std::min(probe ? probe : std::max<uint32_t>(1, s->n_sweeps / 50), s->n_sweeps));
+    ps.start_sweep = 0;
+    ps.init_spins = nullptr;
+    ps.trace_m = nullptr;
+    ps.trace_cut = nullptr;
+    std::vector<int8_t> out((size_t)g->n);
+    const gdi_tuning saved = g->tune;
+    const bool saved_have = g->have_tune;
+    int last_err = GDI_OK;
+    auto timed = [&](const gdi_tuning &t, double *ms) -> int {
+        g->tune = t;
+        g->have_tune = true;
+        double a = 1e300;
+        for (int k = 0; k < 2; ++k) {
+            const int r = anneal_impl(g, &ps, seed, out.data(), nullptr);
+            if (r) return r;
+            a = std::min(a, g->last.sweep_ms);
+        }
+        *ms = a;
+        return GDI_OK;
+    };
+    gdi_tuning cur{};
+    double cur_ms = 1e300;
+    bool any = false;
+    // a candidate that does not fit (range, launch shape) is skipped; anything else stops
+    auto consider = [&](const gdi_tuning &t) -> int {
+        double ms = 0;
+        const int r = timed(t, &ms);
+        if (r == GDI_ERANGE || r == GDI_EDEVICE || r == GDI_EINVAL) {
+            last_err = r;
+            return GDI_OK;
+        }
+        if (r) return r;
+        if (!any || ms < cur_ms) {
+            cur_ms = ms;
+            cur = t;
+            any = true;
+        }
+        return GDI_OK;
+    };
+    int rc = GDI_OK;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        rc = fail(GDI_EDEVICE, "device query");
+    if (!rc && g->n_pad <= kWgMaxNodes) {
+        gdi_tuning t{};
+        t.scope = GDI_SCOPE_WORKGROUP;
+        if (!rc) rc = consider(t);
+        if (!rc && g->wgl_ok) {
+            t.csr_lds = -1;
+            rc = consider(t);
+        }
+    }
+    const int32_t g_cap = std::min(cus, GDI_HALO_MAX_GRID) / 8 * 8;
+    for (int32_t G = 8; !rc && G <= g_cap; G *= 2) {
+        if (G > 8 && (int64_t)G * 256 > g->n) break;  // fewer than 256 nodes per workgroup
+        gdi_tuning t{};
+        t.scope = GDI_SCOPE_GRID;
+        t.grid = (uint32_t)G;
+        rc = consider(t);
+    }
+    if (!rc && any && cur.scope == GDI_SCOPE_WORKGROUP) {
+        const gdi_tuning base = cur;
+        for (uint32_t l : {1u, 2u, 4u, 8u, 16u, 32u}) {
+            gdi_tuning t = base;
+            t.lanes_per_node = l;
+            if ((rc = consider(t))) break;
+        }
+        const gdi_tuning base2 = cur;
+        for (uint32_t b : {256u, 512u}) {
+            if (rc) break;
+            gdi_tuning t = base2;
+            t.block = b;
+            if (t.lanes_per_node > b) continue;
+            rc = consider(t);
+        }
+    } else if (!rc && any && cur.scope == GDI_SCOPE_GRID) {
+        gdi_tuning t = cur;
+        t.tail_max = -1;
+        rc = consider(t);
+        if (!rc && cur.grid >= 16) {
+            t = cur;
+            t.leaders = 1;
+            rc = consider(t);
+        }
+    }
+    if (!rc && !any) rc = last_err ? last_err : fail(GDI_EDEVICE, "no launch candidate ran");
+    if (rc) {
+        g->tune = saved;
+        g->have_tune = saved_have;
+        return rc;
+    }
+    g->tune = cur;
+    g->have_tune = true;
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    tune_store(graph_key(g), cur, cur_ms);
+    return GDI_OK;
 }
 
 int check_batch(const gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s)
@@ -843,29 +1106,84 @@ int run_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64
     int per_cu = 0;
     int e = gdi_batch_occupancy((int)block, lds, &per_cu);
     if (e || per_cu < 1) return fail(GDI_EDEVICE, "batched sweep cannot be launched with this block size");
-    uint32_t grid = tn.grid ? tn.grid : (uint32_t)(cus * per_cu);
-    grid = std::max<uint32_t>(1, std::min<uint32_t>(grid, n_inst));
+    // workgroups of the launch (clamped to the number of tickets below)
+    uint32_t grid = std::max<uint32_t>(1, tn.grid ? tn.grid : (uint32_t)(cus * per_cu));
 
     std::vector<uint32_t> tab;
     int32_t K = 0;
     if ((rc = build_table(s->temps, S, de_max, &K, tab, s->acceptance))) return rc;
 
-    // longest instances first
+    // Clusters: an instance whose work (n + nnz) exceeds twice the per-workgroup share of
+    // the batch runs on k workgroups (k about its work over the share, at most
+    // GDI_BATCH_MAX_MEMBERS or tuning.batch_members; graphs with at least two colour
+    // classes). All cluster members are dealt first, so that the launch's first pops
+    // start every member of every cluster at once (the launch is then cooperative).
+    std::vector<int32_t> mem(n_inst, 1);
+    {
+        // Clusters need a co-resident launch: at most 16 waves per CU (the shape every
+        // cooperative launch of this library runs with; a larger occupancy figure was
+        // refused by the cooperative launch or not co-resident), and the grid within it.
+        const uint32_t coop_cap = (uint32_t)cus * (uint32_t)std::max(1, std::min(per_cu, (int)(GDI_MAX_BLOCK / block)));
+        const bool coresident = grid <= coop_cap || !tn.grid;
+        const uint32_t cgrid = std::min(grid, coop_cap);  // the grid if clusters form
+        const int32_t cap = !coresident ? 1
+                            : tn.batch_members > 0 ? std::min<int32_t>(tn.batch_members, GDI_BATCH_MAX_MEMBERS)
+                                                   : (tn.batch_members < 0 ? 1 : GDI_BATCH_MAX_MEMBERS);
+        double total = 0;
+        for (uint32_t i = 0; i < n_inst; ++i) total += (double)(inst[i].graph->nnz + inst[i].graph->n);
+        const double share = total / cgrid;
+        int64_t sum = 0;
+        for (uint32_t i = 0; i < n_inst; ++i) {
+            const gdi_graph *g = inst[i].graph;
+            const double w = (double)(g->nnz + g->n);
+            if (cap > 1 && g->C >= 2 && w > 2.0 * share)
+                mem[i] = (int32_t)std::min<double>(cap, std::ceil(w / share));
+            sum += mem[i] > 1 ? mem[i] : 0;
+        }
+        // all members must start together: shrink the largest clusters until they fit the grid
+        while (sum > (int64_t)cgrid) {
+            uint32_t big = 0;
+            for (uint32_t i = 1; i < n_inst; ++i)
+                if (mem[i] > mem[big]) big = i;
+            if (mem[big] <= 1) break;
+            --mem[big];
+            sum -= mem[big] == 1 ? 2 : 1;
+        }
+        if (sum > 0) grid = cgrid;
+    }
+    // tickets: cluster members first (largest work per member first), then the other
+    // instances longest first
     std::vector<uint32_t> order(n_inst);
     for (uint32_t i = 0; i < n_inst; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
-        const int64_t wx = inst[x].graph->nnz + inst[x].graph->n, wy = inst[y].graph->nnz + inst[y].graph->n;
+        const bool cx = mem[x] > 1, cy = mem[y] > 1;
+        if (cx != cy) return cx;
+        const double wx = (double)(inst[x].graph->nnz + inst[x].graph->n) / mem[x];
+        const double wy = (double)(inst[y].graph->nnz + inst[y].graph->n) / mem[y];
         return wx > wy;
     });
+    size_t n_tickets = 0, sync_words = 0;
+    std::vector<size_t> sync_off(n_inst, 0);
+    for (uint32_t i = 0; i < n_inst; ++i) {
+        n_tickets += (size_t)mem[i];
+        if (mem[i] > 1) {
+            sync_off[i] = sync_words;
+            sync_words += (size_t)inst[i].graph->n_pad / 32 + 1 + 32;
+        }
+    }
+    const bool clusters = sync_words > 0;
+    grid = std::max<uint32_t>(1, std::min<uint32_t>(grid, (uint32_t)n_tickets));
     DevBuf<GdiBatchInstance> d_inst;
     DevBuf<uint64_t> d_queue;
     DevBuf<int64_t> d_res;
     DevBuf<int8_t> d_out;
     DevBuf<uint32_t> d_thr;
+    DevBuf<uint64_t> d_sync;
     struct Release {
         DevBuf<GdiBatchInstance> &a; DevBuf<uint64_t> &b; DevBuf<int64_t> &c; DevBuf<int8_t> &d; DevBuf<uint32_t> &e;
-        ~Release() { a.release(); b.release(); c.release(); d.release(); e.release(); }
-    } rel{d_inst, d_queue, d_res, d_out, d_thr};
+        DevBuf<uint64_t> &f;
+        ~Release() { a.release(); b.release(); c.release(); d.release(); e.release(); f.release(); }
+    } rel{d_inst, d_queue, d_res, d_out, d_thr, d_sync};
     std::vector<size_t> out_off(n_inst, 0);
     size_t out_total = 0;
     if (!probe_S && !dev_out)
@@ -873,42 +1191,55 @@ int run_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64
             out_off[i] = out_total;
             if (inst[i].spins_out) out_total += (size_t)inst[i].graph->n;
         }
-    HIP_TRY(d_inst.reserve(n_inst), "hipMalloc batch");
-    HIP_TRY(d_queue.reserve(1), "hipMalloc batch");
+    HIP_TRY(d_inst.reserve(n_tickets), "hipMalloc batch");
+    HIP_TRY(d_queue.reserve(2), "hipMalloc batch");  // [0] queue, [1] error flag
     HIP_TRY(d_res.reserve(2 * (size_t)n_inst), "hipMalloc batch");
     HIP_TRY(d_thr.reserve(tab.size()), "hipMalloc batch thresholds");
+    if (clusters) HIP_TRY(d_sync.reserve(sync_words), "hipMalloc batch clusters");
     if (out_total) HIP_TRY(d_out.reserve(out_total), "hipMalloc batch outputs");
-    std::vector<GdiBatchInstance> h_inst(n_inst);
-    for (uint32_t q = 0; q < n_inst; ++q) {
-        const uint32_t i = order[q];
+    std::vector<GdiBatchInstance> h_inst(n_tickets);
+    size_t q = 0;
+    for (uint32_t oi = 0; oi < n_inst; ++oi) {
+        const uint32_t i = order[oi];
         const gdi_graph *g = inst[i].graph;
-        GdiBatchInstance &b = h_inst[q];
-        b.rp = g->d_rp.p;
-        b.adj = g->d_adj.p;
-        b.orig = g->d_orig.p;
-        b.cbeg = g->d_cbeg.p;
-        b.csz = g->d_csz.p;
-        b.out = nullptr;
-        if (!probe_S && inst[i].spins_out) b.out = dev_out ? inst[i].spins_out : d_out.p + out_off[i];
-        b.result = d_res.p + 2 * (size_t)i;
-        b.n = g->n;
-        b.n_pad = g->n_pad;
-        b.C = g->C;
-        b.lanes = tn.lanes_per_node ? (int32_t)tn.lanes_per_node
-                                    : lanes_for_degree(g->n ? (double)g->nnz / g->n : 0.0);
-        b.replica = inst[i].replica;
-        b.wide = g->n && (double)g->nnz / g->n >= 4.0 * b.lanes ? 1u : 0u;
+        for (int32_t rnk = 0; rnk < mem[i]; ++rnk, ++q) {
+            GdiBatchInstance &b = h_inst[q];
+            b.rp = g->d_rp.p;
+            b.adj = g->d_adj.p;
+            b.orig = g->d_orig.p;
+            b.cbeg = g->d_cbeg.p;
+            b.csz = g->d_csz.p;
+            b.out = nullptr;
+            if (!probe_S && inst[i].spins_out) b.out = dev_out ? inst[i].spins_out : d_out.p + out_off[i];
+            b.result = d_res.p + 2 * (size_t)i;
+            b.n = g->n;
+            b.n_pad = g->n_pad;
+            b.C = g->C;
+            b.lanes = tn.lanes_per_node ? (int32_t)tn.lanes_per_node
+                                        : lanes_for_degree(g->n ? (double)g->nnz / g->n : 0.0);
+            b.replica = inst[i].replica;
+            b.wide = g->n && (double)g->nnz / g->n >= 4.0 * b.lanes ? 1u : 0u;
+            b.sync = mem[i] > 1 ? d_sync.p + sync_off[i] : nullptr;
+            b.members = mem[i];
+            b.rank = rnk;
+        }
     }
     hipStream_t st = inst[0].graph->stream;
     HIP_TRY(hipMemcpyAsync(d_inst.p, h_inst.data(), h_inst.size() * sizeof(GdiBatchInstance), hipMemcpyHostToDevice, st),
             "upload batch");
     HIP_TRY(hipMemcpyAsync(d_thr.p, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, st), "upload thresholds");
-    if ((e = gdi_launch_fill_u64(d_queue.p, 1, st))) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
+    if ((e = gdi_launch_fill_u64(d_queue.p, 2, st))) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
+    if ((e = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(d_res.p), 2 * (int64_t)n_inst, st)))
+        return fail(GDI_EDEVICE, gdi_hip_error_string(e));
+    if (clusters && (e = gdi_launch_fill_u64(d_sync.p, (int64_t)sync_words, st)))
+        return fail(GDI_EDEVICE, gdi_hip_error_string(e));
     GdiBatchArgs ba{};
     ba.inst = d_inst.p;
     ba.queue = reinterpret_cast<int32_t *>(d_queue.p);
     ba.thr = d_thr.p;
-    ba.n_inst = (int32_t)n_inst;
+    ba.n_inst = (int32_t)n_tickets;
+    ba.error = reinterpret_cast<int64_t *>(d_queue.p + 1);
+    ba.spin_limit = kSpinLimit;
     ba.K = K;
     ba.S = S;
     ba.A4 = 4 * s->A;
@@ -925,13 +1256,16 @@ int run_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64
         ~Ev() { if (a) (void)hipEventDestroy(a); if (b) (void)hipEventDestroy(b); }
     } ev{e0, e1};
     HIP_TRY(hipEventRecord(e0, st), "hipEventRecord");
-    if ((e = gdi_launch_sweep_batch(ba, (int)grid, (int)block, lds, st)))
+    if ((e = gdi_launch_sweep_batch(ba, (int)grid, (int)block, lds, clusters ? 1 : 0, st)))
         return fail(GDI_EDEVICE, std::string("batched sweep launch: ") + gdi_hip_error_string(e));
     HIP_TRY(hipEventRecord(e1, st), "hipEventRecord");
     HIP_TRY(hipStreamSynchronize(st), "batched sweep");
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
     if (kernel_ms) *kernel_ms = ms;
+    int64_t err_flag = 0;
+    HIP_TRY(hipMemcpy(&err_flag, d_queue.p + 1, 8, hipMemcpyDeviceToHost), "read batch error flag");
+    if (err_flag) return fail(GDI_ETIMEOUT, "a cluster's device-side wait expired; results are invalid");
     if (probe_S) return GDI_OK;
     std::vector<int64_t> res(2 * (size_t)n_inst);
     HIP_TRY(hipMemcpy(res.data(), d_res.p, res.size() * 8, hipMemcpyDeviceToHost), "download batch results");
@@ -998,10 +1332,30 @@ int autotune_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, u
         if (r) return r;
         if (ms < cur_ms) { cur_ms = ms; cur = t; }
     }
+    // cluster size of the large instances (none, or up to 2..16 workgroups), then the
+    // grid once more: clusters run in a cooperative launch of at most 16 waves per CU
+    for (int32_t m : {-1, 2, 4, 8, 16}) {
+        gdi_tuning t = cur;
+        t.batch_members = m;
+        double ms = 0;
+        int r = timed(t, &ms);
+        if (r == GDI_EDEVICE) continue;
+        if (r) return r;
+        if (ms < cur_ms) { cur_ms = ms; cur = t; }
+    }
+    for (uint32_t g : {0u, (uint32_t)cus, 2u * (uint32_t)cus, 4u * (uint32_t)cus}) {
+        gdi_tuning t = cur;
+        if (g == t.grid) continue;
+        t.grid = g;
+        double ms = 0;
+        int r = timed(t, &ms);
+        if (r == GDI_EDEVICE) continue;
+        if (r) return r;
+        if (ms < cur_ms) { cur_ms = ms; cur = t; }
+    }
     *best = cur;
     if (best_ms) *best_ms = cur_ms;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[batch_key(inst, n_inst)] = cur;
+    tune_store(batch_key(inst, n_inst), cur, cur_ms);
     return GDI_OK;
 }
 
@@ -1014,13 +1368,8 @@ int anneal_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uin
     if (tune) {
         t = *tune;
     } else {
-        bool have = false;
-        {
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            auto it = g_tune_cache.find(batch_key(inst, n_inst));
-            if (it != g_tune_cache.end()) { t = it->second; have = true; }
-        }
-        if (!have) {
+        double cached_ms = 0;
+        if (!tune_lookup(batch_key(inst, n_inst), &t, &cached_ms)) {
             double ms = 0;
             rc = autotune_batch(inst, n_inst, s, seed, std::max<uint32_t>(1, s->n_sweeps / 50), &t, &ms);
             if (rc) return rc;
@@ -1486,6 +1835,73 @@ int gdi_autotune_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *
     } catch (const std::bad_alloc &) {
         return fail(GDI_ENOMEM, "out of host memory");
     }
+}
+
+int gdi_autotune(gdi_graph *g, const gdi_schedule *s, uint64_t seed, uint32_t probe_sweeps, int use_cache,
+                 gdi_tuning *best, double *best_ms)
+{
+    if (!best) return fail(GDI_EINVAL, "NULL best");
+    if (!g) return fail(GDI_ESTATE, "NULL handle");
+    try {
+        if (use_cache) {
+            gdi_tuning t{};
+            double ms = 0;
+            if (tune_lookup(graph_key(g), &t, &ms)) {
+                g->tune = t;
+                g->have_tune = true;
+                *best = t;
+                if (best_ms) *best_ms = ms;
+                return GDI_OK;
+            }
+        }
+        return autotune_graph(g, s, seed, probe_sweeps, best, best_ms);
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_tune_cache_load(const char *path)
+{
+    if (!path) return fail(GDI_EINVAL, "NULL path");
+    try {
+        std::string text, err;
+        if (!gdi_tunecache::read_file(path, &text)) return fail(GDI_EINVAL, std::string("cannot read ") + path);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_env_read_locked();
+        if (gdi_tunecache::parse(text, &g_tune_table, &err)) return fail(GDI_EINVAL, std::string(path) + ": " + err);
+        return GDI_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_tune_cache_save(const char *path)
+{
+    if (!path) return fail(GDI_EINVAL, "NULL path");
+    try {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_env_read_locked();
+        if (!gdi_tunecache::write_file(path, gdi_tunecache::dump(g_tune_table)))
+            return fail(GDI_EINVAL, std::string("cannot write ") + path);
+        return GDI_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(GDI_ENOMEM, "out of host memory");
+    }
+}
+
+int gdi_tune_cache_clear(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_env_read = true;  // a cleared cache is not refilled from GDI_TUNE_CACHE
+    g_tune_table.clear();
+    return GDI_OK;
+}
+
+int gdi_tune_cache_size(void)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_env_read_locked();
+    return (int)std::min<size_t>(g_tune_table.size(), 0x7FFFFFFF);
 }
 
 int gdi_anneal_learned(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_mlp_weights *w,

@@ -76,6 +76,9 @@ struct GdiHaloArgs {
     uint64_t *group;           // 2 x 8 words (phase parity x group), GDI_HALO_GROUP_PAD apart
     int32_t lds_words;         // LDS words per workgroup: image (own and foreign words per class), the tail's gather and tail regions, the foreign-id lists
     int32_t thr_in_lds;        // 1: the current and next threshold rows are staged in LDS
+    // epochs of this launch start above epoch0: words left by earlier launches carry
+    // smaller ones, so the words need no clearing between launches
+    uint32_t epoch0;
     // Redundant tail: the last classes T0..C-1 hold at most one node per worker thread
     // in total; every workgroup runs them itself (identical results everywhere), so
     // they take no grid-wide barrier. Tail spins live in a tail region of LDS (ids
@@ -120,6 +123,11 @@ struct GdiBatchInstance {
     int32_t n, n_pad, C, lanes;
     uint32_t replica;
     uint32_t wide;             // 1: long rows for `lanes` (eight entries per lane and round)
+    // cluster: the instance runs on `members` workgroups, this entry is member `rank`;
+    // sync holds its epoch-tagged spin words (n_pad / 32 + 1) and two parities x 16 dM
+    // slots, zeroed before the launch (members == 1: no cluster, sync unused)
+    uint64_t *sync;
+    int32_t members, rank;
 };
 
 struct GdiBatchArgs {
@@ -133,7 +141,10 @@ struct GdiBatchArgs {
     uint32_t key0, key1;
     uint32_t snapshot;
     uint32_t rule;                 // acceptance rule, as in GdiSweepArgs
+    int64_t *error;                // set to 1 when a cluster's bounded wait expires
+    int64_t spin_limit;            // polls before such a wait gives up
 };
+#define GDI_BATCH_MAX_MEMBERS 16
 
 // Learned proposal: BF16 network parameters on the device (transposed weights).
 struct GdiMlpDev {
@@ -170,13 +181,16 @@ int gdi_async_capacity(int block, int *max_grid);
 int gdi_launch_sweep_async(const GdiSweepArgs &a, int grid, int block, void *stream);
 int gdi_launch_sweep_dense(const GdiSweepArgs &a, int block, int lanes, void *stream);
 int gdi_launch_sweep_wg(const GdiSweepArgs &a, int block, int lanes, int spins_in_lds, void *stream);
+int gdi_wgl_lds_bytes(int32_t n_pad, int32_t C, int32_t nnz);
+int gdi_launch_sweep_wgl(const GdiSweepArgs &a, const uint16_t *rp16, const uint16_t *ent16, int32_t nnz, int block,
+                         int lanes, void *stream);
 int gdi_launch_sweep_grid(const GdiSweepArgs &a, int grid, int block, int lanes, void *stream);
 int gdi_grid_capacity(int block, int lanes, int *max_grid);
 int gdi_launch_sweep_halo(const GdiHaloArgs &h, int grid, int block, void *stream);
 int gdi_halo_capacity(int block, int lds_bytes, int *max_grid);
 int gdi_wg_lds_bytes(int32_t n_pad, int32_t C, int spins_in_lds);
 int gdi_batch_lds_bytes(int32_t n_pad, int32_t C);
-int gdi_launch_sweep_batch(const GdiBatchArgs &ba, int grid, int block, int lds_bytes, void *stream);
+int gdi_launch_sweep_batch(const GdiBatchArgs &ba, int grid, int block, int lds_bytes, int cooperative, void *stream);
 int gdi_batch_occupancy(int block, int lds_bytes, int *per_cu);
 const char *gdi_hip_error_string(int code);
 

@@ -4,13 +4,17 @@
 // frozen for the next sweeps; masked sweeps then skip the nodes it flags, and a
 // full sweep runs every k sweeps. The network is 6 -> 64 -> 64 -> 1 with ReLU
 // hidden layers and a logistic output, BF16 weights and FP32 accumulation; both
-// dense layers run on MFMA (v_mfma_f32_16x16x16_bf16).
+// dense layers of the forward pass run on gfx950's v_mfma_f32_16x16x32_bf16.
 //
 // The layers are evaluated transposed, hidden x node: for a tile of 16 nodes,
-// layer 1 computes H1^T = W1^T X^T and layer 2 H2^T = W2^T H1^T. With the
-// 16x16x16 MFMA, lane l holds accumulator rows 4(l/16)..4(l/16)+3 of column
-// l%16, which is exactly the B-operand layout (k rows 4(l/16).., column l%16) of
-// the next product, so activations stay in registers between the layers.
+// layer 1 computes H1^T = W1^T X^T and layer 2 H2^T = W2^T H1^T. A 16x16 accumulator
+// leaves lane l with rows 4(l/16)..4(l/16)+3 of column l%16. The 16x16x32 product
+// pairs element j of lane group g = l/16 in A (row l%16) and in B (column l%16) for
+// the same reduction index, and the order of that index is free: so layer 2 takes,
+// for K rows 32q..32q+31, the eight values a lane already holds from the two layer-1
+// blocks 2q and 2q+1 (rows 32q + 4g + i and 32q + 16 + 4g + i) as its B operand, and
+// the matching weights as A. Activations stay in registers between the layers. The
+// backward pass keeps the 16x16x16 form, whose operand layout is the accumulator's.
 //
 // Training computes the mean logistic loss on a minibatch and its gradients
 // with the same MFMA layout (dH1 = W2 dPre2 directly in registers; the weight
@@ -28,9 +32,16 @@ namespace {
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
 __device__ __forceinline__ floatx4 mfma16(bf16x4 a, bf16x4 b, floatx4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ floatx4 mfma32(bf16x8 a, bf16x8 b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ void wave_lds_sync()
@@ -177,12 +188,24 @@ struct TileFwd {
 
 __device__ __forceinline__ void tile_forward(const MlpLds *m, bf16x4 xb, int g, int r, TileFwd &o)
 {
+    // layer 1 (K = 6 features, padded): lane group 0 carries features 0..7 of its node
+    // (xb holds features 4g..4g+3 for g < 2), the other groups zeros
+    bf16x8 x8;
+    {
+        const __bf16 z = (__bf16)0.0f;
+        const bf16x4 hi = __builtin_bit_cast(bf16x4, __shfl_down(__builtin_bit_cast(uint64_t, xb), 16, 64));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            x8[j] = g == 0 ? xb[j] : z;
+            x8[4 + j] = g == 0 ? hi[j] : z;
+        }
+    }
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-        bf16x4 a;
+        bf16x8 a;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) a[j] = m->w1t[(16 * mb + r) * 16 + 4 * g + j];
-        const floatx4 acc = mfma16(a, xb, floatx4{0.f, 0.f, 0.f, 0.f});
+        for (int j = 0; j < 8; ++j) a[j] = g == 0 ? m->w1t[(16 * mb + r) * 16 + j] : (__bf16)0.0f;
+        const floatx4 acc = mfma32(a, x8, floatx4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
         for (int i = 0; i < 4; ++i) o.h1[mb][i] = (__bf16)fmaxf(acc[i] + m->b1[16 * mb + 4 * g + i], 0.0f);
     }
@@ -191,11 +214,16 @@ __device__ __forceinline__ void tile_forward(const MlpLds *m, bf16x4 xb, int g, 
     for (int mo = 0; mo < 4; ++mo) {
         floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            bf16x4 a;
+        for (int q = 0; q < 2; ++q) {
+            bf16x8 a, b;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) a[j] = m->w2t[(16 * mo + r) * 64 + 16 * kb + 4 * g + j];
-            acc = mfma16(a, o.h1[kb], acc);
+            for (int j = 0; j < 4; ++j) {
+                a[j] = m->w2t[(16 * mo + r) * 64 + 32 * q + 4 * g + j];
+                a[4 + j] = m->w2t[(16 * mo + r) * 64 + 32 * q + 16 + 4 * g + j];
+                b[j] = o.h1[2 * q][j];
+                b[4 + j] = o.h1[2 * q + 1][j];
+            }
+            acc = mfma32(a, b, acc);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {

@@ -51,7 +51,9 @@ MIXED = [
 
 
 @pytest.mark.parametrize("tune", [None, dict(block=64, lanes_per_node=1, grid=3),
-                                  dict(block=256, lanes_per_node=8), dict(block=1024, lanes_per_node=64, grid=1000)])
+                                  dict(block=256, lanes_per_node=8), dict(block=1024, lanes_per_node=64, grid=1000),
+                                  dict(block=256, batch_members=-1), dict(block=256, batch_members=4, grid=24),
+                                  dict(block=512, batch_members=16, lanes_per_node=2)])
 @pytest.mark.parametrize("mode", [0, 1])
 def test_mixed_batch_matches_single_runs(gdi, oracle_lib, tune, mode):
     graphs = [f() for f in MIXED]

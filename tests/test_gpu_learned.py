@@ -4,6 +4,8 @@ forward pass and gradient, and training, against oracle/learned_ref.py.
 The network's expected values are its FP64 definition (BF16 storage points, exact
 arithmetic otherwise) with the error bounds of learned_ref.mlp_error_model; a skip
 decision is fixed wherever the FP64 logit lies outside its band around the threshold."""
+import time
+
 import numpy as np
 import pytest
 
@@ -301,11 +303,17 @@ def test_learned_rejects_bad_config(gdi):
 
 
 def test_trained_network_gain(gdi):
-    """What the trained network gains: trained on traces of two small RGGs, evaluated on a
-    larger one, over the whole schedule. Against the schedule without a proposal it skips
-    most node visits at the same cut (within a few percent); against the untrained
-    proposal that skips by age alone (a node that has not flipped for k sweeps), it keeps
-    the cut while that one loses a large part of it."""
+    """What the trained network gains, on a 60k-node RGG after training on traces of two
+    smaller RGGs (the plain annealer is the judge of cut quality):
+
+    * over the colder half of the schedule (the proposal from sweep S/2 on), the network
+      reaches the plain annealer's best balanced cut within 0.5 % and takes less wall time
+      per anneal than the plain annealer;
+    * over the whole schedule, the network keeps the cut (within 3 % of plain on average)
+      while the untrained proposal that skips by age alone (no flip for k sweeps) loses a
+      large part of it at a similar skip rate.
+    The age proposal over the colder half is reported beside the network (wall time and
+    best cut); the network is not asserted to beat it there."""
     import torch
 
     S, k = 1000, 8
@@ -322,22 +330,40 @@ def test_trained_network_gain(gdi):
     w, losses = gdi.mlp_train(dx.data_ptr(), dy.data_ptr(), off, gdi.mlp_init(1), epochs=3, batch=4096, lr=2e-3)
     ev = gs.rgg_graph(60_000, 8.0, 212)
     res = {}
+    runs = (("plain", {}, 6),
+            ("network_cold", dict(skip_mode=gdi.SKIP_MLP, weights=w, skip_threshold=0.9, learn_from=S // 2), 6),
+            ("age_cold", dict(skip_mode=gdi.SKIP_HEURISTIC, heuristic_k=k, learn_from=S // 2), 6),
+            ("network_all", dict(skip_mode=gdi.SKIP_MLP, weights=w, skip_threshold=0.97), 4),
+            ("age_all", dict(skip_mode=gdi.SKIP_HEURISTIC, heuristic_k=k), 4))
     with gdi.Annealer(ev) as a:
-        for name, kw in (("plain", {}), ("network", dict(skip_mode=gdi.SKIP_MLP, weights=w, skip_threshold=0.97)),
-                         ("age", dict(skip_mode=gdi.SKIP_HEURISTIC, heuristic_k=k))):
-            cuts, skips = [], []
-            for rep in range(4):
+        a.anneal_learned(T[:20], 5, k)  # warm-up: thresholds, launch choice
+        for name, kw, reps in runs:
+            cuts, skips, ms = [], [], []
+            for rep in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
                 r = a.anneal_learned(T, 5, k, replica=rep, **kw)
+                ms.append((time.perf_counter() - t0) * 1e3)
                 assert abs(r["M"]) <= 2
                 cuts.append(r["cut"])
                 rr = r["result"]
                 skips.append(rr["node_skips"] / (rr["node_skips"] + rr["node_visits"]))
-            res[name] = (float(np.mean(cuts)), float(np.mean(skips)))
-    print(f"losses {losses.tolist()}; mean cut / skipped fraction: {res}", flush=True)
-    plain, net, age = res["plain"][0], res["network"][0], res["age"][0]
-    assert res["network"][1] > 0.5 and res["age"][1] > 0.5
-    assert net <= 1.03 * plain
-    assert age >= 1.15 * plain
+            res[name] = dict(best=min(cuts), mean=float(np.mean(cuts)), skip=float(np.mean(skips)),
+                             ms=float(np.median(ms)))
+    print(f"losses {losses.tolist()}", flush=True)
+    for name, v in res.items():
+        print(f"{name}: best cut {v['best']}, mean cut {v['mean']:.1f}, skipped {v['skip']:.3f}, "
+              f"median {v['ms']:.1f} ms per anneal", flush=True)
+    plain, net, age = res["plain"], res["network_cold"], res["age_cold"]
+    # the colder half: the plain best within 0.5 %, in less wall time than plain
+    assert net["best"] <= 1.005 * plain["best"]
+    assert net["ms"] < plain["ms"] and net["skip"] > 0.3
+    # the whole schedule: the network keeps the cut, skipping by age alone loses it
+    assert res["network_all"]["skip"] > 0.5 and res["age_all"]["skip"] > 0.5
+    assert res["network_all"]["mean"] <= 1.03 * plain["mean"]
+    assert res["age_all"]["mean"] >= 1.15 * plain["mean"]
+    print(f"colder half: network {net['ms']:.1f} ms vs age {age['ms']:.1f} ms per anneal, best cuts "
+          f"{net['best']} vs {age['best']} (plain {plain['best']}, {plain['ms']:.1f} ms)", flush=True)
 
 
 def test_full_size_learned_schedules(gdi, L):

@@ -74,6 +74,7 @@ def test_small_graphs(gdi, oracle_lib, name, mode, scope):
     dict(scope=1, lanes_per_node=1, block=64),
     dict(scope=1, lanes_per_node=4, block=256),
     dict(scope=1, lanes_per_node=64, block=1024),
+    dict(scope=1, lanes_per_node=1, block=256, csr_lds=-1),
     dict(scope=2, grid=8, block=256),
     dict(scope=2, grid=64, block=512),
     dict(scope=2, grid=256, block=1024),
@@ -93,6 +94,60 @@ def test_launch_shape_invariance(gdi, oracle_lib, tune):
     T = gs.geometric_temps(3.0, 0.05, 30)
     ref, r, _ = run_both(gdi, oracle_lib, g, T, seed=5, tune=tune, label="shape")
     assert_same(ref, r)
+
+
+@pytest.mark.parametrize("tune", [
+    dict(scope=1, lanes_per_node=1, block=256, csr_lds=1),
+    dict(scope=1, lanes_per_node=2, block=512, csr_lds=1),
+    dict(scope=1, lanes_per_node=8, block=1024, csr_lds=1),
+    dict(scope=1, lanes_per_node=64, block=1024, csr_lds=1),
+])
+def test_lds_resident_launch_shapes(gdi, oracle_lib, tune):
+    """The LDS-resident workgroup sweep over lanes-per-node and block choices on a graph
+    that fits its 16-bit CSR (3001 nodes, ragged class tails)."""
+    g = gs.rgg_graph(3001, 10.0, 13, "pm1")
+    assert g.row_ptr[-1] <= 65535
+    T = gs.geometric_temps(3.0, 0.05, 30)
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, seed=5, tune=tune, label="lds-shape")
+    assert_same(ref, r)
+
+
+@pytest.mark.parametrize("name", ["er800", "torus100"])
+def test_small_configs_take_the_lds_resident_sweep(gdi, oracle_lib, name):
+    """er800 and torus100 (+-1 / unit weights, small) run with the whole graph in LDS by
+    default; the same schedule with the CSR in global memory gives the same result."""
+    g, T = gs.workload(name)
+    T = T[:300]
+    with gdi.Annealer(g) as a:
+        r_lds = a.anneal(T, 3, trace=True)
+        a.tune(csr_lds=-1)
+        r_glb = a.anneal(T, 3, trace=True)
+    print(f"{name}: LDS-resident {r_lds['result']['sweep_ms']:.2f} ms, global CSR {r_glb['result']['sweep_ms']:.2f} ms",
+          flush=True)
+    assert np.array_equal(r_lds["spins"], r_glb["spins"]) and r_lds["cut"] == r_glb["cut"]
+    assert np.array_equal(r_lds["trace_cut"], r_glb["trace_cut"])
+
+
+def test_lds_resident_sweep_rejects_what_does_not_fit(gdi):
+    """Weights other than +-1 keep the CSR in global memory; requiring LDS is an error."""
+    g = gs.er_graph(400, 0.05, 9, "unit")
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    up = g.col > rows
+    heavy = gs.from_edges(g.n, rows[up], g.col[up], np.full(int(up.sum()), 2))
+    with gdi.Annealer(heavy) as a:
+        a.tune(scope=1, csr_lds=1)
+        with pytest.raises(gdi.GdiError) as e:
+            a.anneal(np.ones(2), 1)
+        assert e.value.code == gdi.ERANGE
+    big = gs.rgg_graph(7777, 10.0, 12, "pm1")  # nnz beyond the 16-bit row pointers
+    assert big.row_ptr[-1] > 65535
+    with gdi.Annealer(big) as a:
+        a.tune(scope=1, csr_lds=1)
+        with pytest.raises(gdi.GdiError) as e:
+            a.anneal(np.ones(2), 1)
+        assert e.value.code == gdi.ERANGE
+        a.tune(scope=1, csr_lds=0)  # the automatic choice falls back to the global CSR
+        a.anneal(np.ones(2), 1)
 
 
 def test_er800_full_schedule(gdi, oracle_lib):
