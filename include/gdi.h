@@ -66,7 +66,11 @@ extern "C" {
 #define GDI_BAL_GATED 0u
 #define GDI_BAL_SNAPSHOT 1u
 
-/* Scope of the persistent sweep launch. */
+/* Scope of the persistent sweep launch. GDI_SCOPE_AUTO: one workgroup up to 6144
+ * padded nodes, else the grid sweep (GDI_SCOPE_GRID) on about one workgroup per 1,500
+ * nodes (at least 64 where that leaves 128 nodes each, at most one per CU); graphs the
+ * grid sweep cannot hold (|w| > 1023, too many spin words for LDS) run on one workgroup
+ * up to 65536 padded nodes, above that on GDI_SCOPE_GRID_FENCED. */
 #define GDI_SCOPE_AUTO 0u
 #define GDI_SCOPE_WORKGROUP 1u /* whole instance inside one workgroup */
 #define GDI_SCOPE_GRID 2u      /* instance spread over the whole device; spins exchanged through

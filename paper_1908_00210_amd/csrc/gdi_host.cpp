@@ -182,8 +182,30 @@ int lanes_for_degree(double avg_deg)
     return L;
 }
 
+// Lanes per node of the workgroup-scope phase loop (plain, batched and cluster
+// members): enough subgroups to take a class's nodes -- the average class, or a
+// member's share of it -- in one round where the block allows (a phase is a chain of
+// dependent loads, so nodes in flight matter more than lanes per row), and never more
+// lanes than the mean degree asks for. Measured on MI355X with 1024-thread blocks:
+// er2000 47.8 -> 25.2 us per sweep, torus100 28.1 -> 15.4, an 8000-node RGG 89 -> 44.
+int lanes_for_wg(const gdi_graph *g, uint32_t nth, int32_t members)
+{
+    const int Ld = lanes_for_degree(g->n ? (double)g->nnz / g->n : 0.0);
+    const double per_round = g->n ? (double)nth * (double)g->C * (double)members / (double)g->n : 64.0;
+    int Lc = 1;
+    while (Lc < 64 && 2.0 * Lc <= per_round) Lc *= 2;
+    return std::min(Ld, Lc);
+}
+
 const int64_t kSpinLimit = int64_t(1) << 22;
 const int32_t kWgMaxNodes = 65536;
+// Automatic scope: one workgroup up to this many padded nodes, the halo grid sweep
+// above (measured on MI355X, 300 sweeps: RGGs of mean degree 10 with 14-15 classes,
+// workgroup / best halo grid: 3000 nodes 30.7 / 35.1 us per sweep, 5000 33.7 / 37.4,
+// 8000 45.5 / 38.2, 12000 54.6 / 38.7, 20000 72.6 / 40.9). Graphs the halo sweep does
+// not take (weights beyond its packed range, LDS) stay on one workgroup up to
+// kWgMaxNodes padded nodes.
+const int32_t kWgAutoNodes = 6144;
 
 int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork, int32_t lead);
 
@@ -197,7 +219,7 @@ int pick_launch(gdi_graph *g, Choice *ch)
     ch->block = t.block ? t.block : 1024u;
     if (ch->block < 64 || ch->block > GDI_MAX_BLOCK || ch->block % 64 || ch->block < ch->lanes)
         return fail(GDI_EINVAL, "block must be a multiple of 64 in [64, 1024]");
-    ch->scope = t.scope ? t.scope : (g->n_pad <= kWgMaxNodes ? GDI_SCOPE_WORKGROUP : GDI_SCOPE_GRID);
+    ch->scope = t.scope ? t.scope : (g->n_pad <= kWgAutoNodes ? GDI_SCOPE_WORKGROUP : GDI_SCOPE_GRID);
     if (ch->scope < GDI_SCOPE_WORKGROUP || ch->scope > GDI_SCOPE_GRID_FENCED)
         return fail(GDI_EINVAL, "unknown scope");
     ch->grid = 1;
@@ -207,7 +229,10 @@ int pick_launch(gdi_graph *g, Choice *ch)
     HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
-    if (ch->scope == GDI_SCOPE_WORKGROUP) {
+    auto pick_wg = [&]() -> int {
+        ch->scope = GDI_SCOPE_WORKGROUP;
+        ch->grid = 1;
+        if (!t.lanes_per_node) ch->lanes = (uint32_t)lanes_for_wg(g, ch->block, 1);
         // beside the dynamic part: the kernel's own LDS words and two threshold rows
         const int fixed = 64 + 2 * GDI_WG_THR_MAX * 4;
         ch->spins_lds = gdi_wg_lds_bytes(g->n_pad, g->C, 1) + fixed <= lds_max;
@@ -220,14 +245,20 @@ int pick_launch(gdi_graph *g, Choice *ch)
                                     "(needs n_pad <= 32768, nnz <= 65535, weights +-1)");
         ch->csr_lds = wgl_fits && t.csr_lds >= 0;
         return GDI_OK;
-    }
+    };
+    if (ch->scope == GDI_SCOPE_WORKGROUP) return pick_wg();
     if (ch->scope == GDI_SCOPE_GRID) {
         // fence-free halo sweep: one node per thread, 1024-thread workgroups, grid a multiple of 8
         const uint32_t block = t.block ? t.block : 1024u;
-        // automatic grid: about 1,500 nodes per workgroup, at most one workgroup per CU
-        // (measured on 2e5 and 1e6-node RGGs: 128 and 256 workgroups are fastest)
+        // automatic grid: about 1,500 nodes per workgroup, at most one workgroup per CU,
+        // and at least 64 workgroups (fewer when that leaves under 128 nodes each)
+        // (measured on RGGs: 128 and 256 workgroups are fastest at 2e5 and 1e6 nodes,
+        // 64 from 1e4 to 6.4e4 nodes)
         const int64_t g_cap = (int64_t)std::min(cus, GDI_HALO_MAX_GRID) / 8 * 8;
-        uint32_t G = t.grid ? t.grid : (uint32_t)std::max<int64_t>(8, std::min<int64_t>(g_cap, g->n / 1536 / 8 * 8));
+        const int64_t g_small = std::min<int64_t>(64, g->n / 128 / 8 * 8);
+        uint32_t G = t.grid ? t.grid
+                            : (uint32_t)std::max<int64_t>(
+                                  8, std::min<int64_t>(g_cap, std::max<int64_t>(g_small, g->n / 1536 / 8 * 8)));
         if (block < 256) return fail(GDI_EINVAL, "the grid sweep needs at least 256 threads per workgroup");
         if (G < 8 || G % 8 || G > GDI_HALO_MAX_GRID)
             return fail(GDI_EINVAL, "the grid sweep needs a grid that is a multiple of 8 in [8, 512]");
@@ -260,7 +291,13 @@ int pick_launch(gdi_graph *g, Choice *ch)
             return fail(GDI_ERANGE, g->halo_lds_words == -3
                                         ? "the grid scope packs weights into 11 bits: |w| must be <= 1023"
                                         : "the spin words this graph needs per workgroup do not fit its LDS");
-        ch->scope = GDI_SCOPE_GRID_FENCED;  // automatic choice falls back
+        // the automatic choice falls back to one workgroup where the graph fits it, else
+        // to the fenced grid sweep
+        if (g->n_pad <= kWgMaxNodes) {
+            const int rc_wg = pick_wg();
+            if (rc_wg != GDI_ERANGE) return rc_wg;
+        }
+        ch->scope = GDI_SCOPE_GRID_FENCED;
     }
     int cap = 0;
     int e = gdi_grid_capacity((int)ch->block, (int)ch->lanes, &cap);
@@ -1099,7 +1136,7 @@ int run_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
     if (lds + 64 + 2 * GDI_WG_THR_MAX * 4 > lds_max) return fail(GDI_ERANGE, "an instance does not fit one workgroup's LDS");
-    const uint32_t block = tn.block ? tn.block : 256u;
+    const uint32_t block = tn.block ? tn.block : 512u;
     if (block < 64 || block > GDI_MAX_BLOCK || block % 64) return fail(GDI_EINVAL, "block must be a multiple of 64 in [64, 1024]");
     if (tn.lanes_per_node && (tn.lanes_per_node > 64 || (tn.lanes_per_node & (tn.lanes_per_node - 1))))
         return fail(GDI_EINVAL, "lanes_per_node must be a power of two in [1, 64]");
@@ -1215,8 +1252,7 @@ int run_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64
             b.n = g->n;
             b.n_pad = g->n_pad;
             b.C = g->C;
-            b.lanes = tn.lanes_per_node ? (int32_t)tn.lanes_per_node
-                                        : lanes_for_degree(g->n ? (double)g->nnz / g->n : 0.0);
+            b.lanes = tn.lanes_per_node ? (int32_t)tn.lanes_per_node : lanes_for_wg(g, block, mem[i]);
             b.replica = inst[i].replica;
             b.wide = g->n && (double)g->nnz / g->n >= 4.0 * b.lanes ? 1u : 0u;
             b.sync = mem[i] > 1 ? d_sync.p + sync_off[i] : nullptr;
@@ -1292,7 +1328,7 @@ int autotune_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, u
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "hipDeviceGetAttribute");
     probe = std::max<uint32_t>(1, std::min(probe, s->n_sweeps));
     gdi_tuning cur{};
-    cur.block = 256;
+    cur.block = 512;
     double cur_ms = 1e300;
     auto timed = [&](const gdi_tuning &t, double *ms) -> int {
         double a = 0, b = 0;

@@ -64,10 +64,11 @@ __device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t 
 // All sweeps of one instance inside one workgroup: phases are separated by
 // s_barrier, dM is summed in an LDS triple buffer (one barrier per phase).
 // sp points to the instance's spins (LDS, or global for large instances),
-// Psh to its per-class +1 counts in LDS, acc to three zeroed LDS words.
+// Psh to its per-class +1 counts in LDS, acc to three zeroed LDS words, thr_s to
+// 2 x GDI_WG_THR_MAX LDS words for the current and the next threshold row.
 template <int L, int U = 4>
-__device__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp, int32_t *Psh, int32_t *acc, int32_t &M,
-                              int64_t &dcut_total)
+__device__ __forceinline__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp, int32_t *Psh, int32_t *acc, uint32_t *thr_s,
+                              int32_t &M, int64_t &dcut_total)
 {
     const int tid = threadIdx.x;
     const int nth = blockDim.x;
@@ -76,7 +77,6 @@ __device__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp, int32_t *Psh, i
     uint32_t p = 0;
     // the current and the next threshold row in LDS when they fit (staged during the
     // last phase of each sweep, whose barrier publishes them)
-    __shared__ uint32_t thr_s[2 * GDI_WG_THR_MAX];
     const int32_t K1 = a.K + 1;
     const bool thr_lds = K1 <= GDI_WG_THR_MAX;
     if (thr_lds && a.t0 < a.S)
@@ -143,6 +143,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_wg(GdiSweepArgs a)
     if (!gate_open(a)) return;
     extern __shared__ int32_t dyn[];
     __shared__ int32_t acc[3];
+    __shared__ uint32_t thr_s[2 * GDI_WG_THR_MAX];
     int32_t *Psh = dyn;
     const int c_round = (a.C + 3) & ~3;
     int8_t *sp = SPIN_LDS ? reinterpret_cast<int8_t *>(dyn + c_round) : a.spin;
@@ -157,7 +158,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_wg(GdiSweepArgs a)
     __syncthreads();
 
     int64_t dcut_total = 0;
-    wg_run_sweeps<L>(a, sp, Psh, acc, M, dcut_total);
+    wg_run_sweeps<L>(a, sp, Psh, acc, thr_s, M, dcut_total);
 
     __syncthreads();
     if (SPIN_LDS)
@@ -442,9 +443,9 @@ __device__ __forceinline__ int32_t member_bound(int32_t size, int32_t r, int32_t
 }
 
 template <int L, int U = 4>
-__device__ void cluster_run_sweeps(const GdiSweepArgs &a, const GdiBatchInstance &in, int8_t *sp, int32_t *Psh,
-                                   int32_t *acc, int32_t *tot_sh, int32_t *flag, int32_t &M, int64_t &dcut_total,
-                                   int64_t limit)
+__device__ __forceinline__ void cluster_run_sweeps(const GdiSweepArgs &a, const GdiBatchInstance &in, int8_t *sp, int32_t *Psh,
+                                   int32_t *acc, uint32_t *thr_s, int32_t *tot_sh, int32_t *flag, int32_t &M,
+                                   int64_t &dcut_total, int64_t limit)
 {
     const int tid = threadIdx.x;
     const int nth = blockDim.x;
@@ -453,10 +454,15 @@ __device__ void cluster_run_sweeps(const GdiSweepArgs &a, const GdiBatchInstance
     uint64_t *words = in.sync;
     uint64_t *slots = in.sync + (in.n_pad / 32 + 1);
     const int32_t K1 = a.K + 1;
+    const bool thr_lds = K1 <= GDI_WG_THR_MAX;
+    if (thr_lds && a.t0 < a.S)
+        for (int i = tid; i < K1; i += nth) thr_s[(a.t0 & 1u) * GDI_WG_THR_MAX + i] = a.thr[(size_t)a.t0 * K1 + i];
+    __syncthreads();
     int64_t dcut = 0;
     uint32_t p = 0;
     for (uint32_t t = a.t0; t < a.S; ++t) {
         const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)K1;
+        const uint32_t *thr_l = thr_lds ? thr_s + (t & 1u) * GDI_WG_THR_MAX : nullptr;
         for (int32_t c = 0; c < a.C; ++c, ++p) {
             const int32_t beg = a.cbeg[c];
             const int32_t size = a.csz[c];
@@ -476,13 +482,17 @@ __device__ void cluster_run_sweeps(const GdiSweepArgs &a, const GdiBatchInstance
                     nr1 = a.rp[v + nsub + 1];
                 }
                 int32_t h, sigma;
-                const bool flip = node_decide<L, U>(a, sp, v, r0, r1, lane, t, pv, thr_row, nullptr, &h, &sigma);
+                const bool flip = node_decide<L, U>(a, sp, v, r0, r1, lane, t, pv, thr_row, thr_l, &h, &sigma);
                 if (flip && lane == 0) {
                     sp[v] = (int8_t)(-sigma);
                     dM -= 2 * sigma;
                     dcut += (int64_t)sigma * h;
                 }
             }
+            // the next sweep's threshold row, published by this phase's barriers
+            if (c + 1 == a.C && thr_lds && t + 1u < a.S)
+                for (int i = tid; i < K1; i += nth)
+                    thr_s[((t + 1u) & 1u) * GDI_WG_THR_MAX + i] = a.thr[(size_t)(t + 1u) * K1 + i];
             dM = wave_sum_i32(dM);
             if ((tid & 63) == 0 && dM != 0) atomicAdd(&acc[p % 3], dM);
             __syncthreads();
@@ -550,6 +560,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_batch(GdiBatchArgs ba)
 {
     extern __shared__ int32_t dyn[];
     __shared__ int32_t acc[3];
+    __shared__ uint32_t thr_s[2 * GDI_WG_THR_MAX];
     __shared__ int32_t next_idx;
     __shared__ int64_t red[2];
     __shared__ int32_t tot_sh, cflag;
@@ -624,13 +635,13 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_batch(GdiBatchArgs ba)
         int64_t dcut_total = 0;
         if (in.members > 1) {
             switch (in.lanes) {
-            case 1: cluster_run_sweeps<1>(a, in, sp, Psh, acc, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
-            case 2: cluster_run_sweeps<2>(a, in, sp, Psh, acc, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
-            case 4: cluster_run_sweeps<4>(a, in, sp, Psh, acc, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
-            case 8: cluster_run_sweeps<8>(a, in, sp, Psh, acc, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
-            case 16: cluster_run_sweeps<16>(a, in, sp, Psh, acc, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
-            case 32: cluster_run_sweeps<32>(a, in, sp, Psh, acc, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
-            default: cluster_run_sweeps<64>(a, in, sp, Psh, acc, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
+            case 1: cluster_run_sweeps<1>(a, in, sp, Psh, acc, thr_s, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
+            case 2: cluster_run_sweeps<2>(a, in, sp, Psh, acc, thr_s, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
+            case 4: cluster_run_sweeps<4>(a, in, sp, Psh, acc, thr_s, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
+            case 8: cluster_run_sweeps<8>(a, in, sp, Psh, acc, thr_s, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
+            case 16: cluster_run_sweeps<16>(a, in, sp, Psh, acc, thr_s, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
+            case 32: cluster_run_sweeps<32>(a, in, sp, Psh, acc, thr_s, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
+            default: cluster_run_sweeps<64>(a, in, sp, Psh, acc, thr_s, &tot_sh, &cflag, M, dcut_total, ba.spin_limit); break;
             }
             if (aborted(&cflag)) {
                 if (tid == 0) __hip_atomic_store(ba.error, (int64_t)1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -639,23 +650,23 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_batch(GdiBatchArgs ba)
             }
         } else if (in.wide) {
             switch (in.lanes) {
-            case 1: wg_run_sweeps<1, 8>(a, sp, Psh, acc, M, dcut_total); break;
-            case 2: wg_run_sweeps<2, 8>(a, sp, Psh, acc, M, dcut_total); break;
-            case 4: wg_run_sweeps<4, 8>(a, sp, Psh, acc, M, dcut_total); break;
-            case 8: wg_run_sweeps<8, 8>(a, sp, Psh, acc, M, dcut_total); break;
-            case 16: wg_run_sweeps<16, 8>(a, sp, Psh, acc, M, dcut_total); break;
-            case 32: wg_run_sweeps<32, 8>(a, sp, Psh, acc, M, dcut_total); break;
-            default: wg_run_sweeps<64, 8>(a, sp, Psh, acc, M, dcut_total); break;
+            case 1: wg_run_sweeps<1, 8>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            case 2: wg_run_sweeps<2, 8>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            case 4: wg_run_sweeps<4, 8>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            case 8: wg_run_sweeps<8, 8>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            case 16: wg_run_sweeps<16, 8>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            case 32: wg_run_sweeps<32, 8>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            default: wg_run_sweeps<64, 8>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
             }
         } else {
             switch (in.lanes) {
-            case 1: wg_run_sweeps<1>(a, sp, Psh, acc, M, dcut_total); break;
-            case 2: wg_run_sweeps<2>(a, sp, Psh, acc, M, dcut_total); break;
-            case 4: wg_run_sweeps<4>(a, sp, Psh, acc, M, dcut_total); break;
-            case 8: wg_run_sweeps<8>(a, sp, Psh, acc, M, dcut_total); break;
-            case 16: wg_run_sweeps<16>(a, sp, Psh, acc, M, dcut_total); break;
-            case 32: wg_run_sweeps<32>(a, sp, Psh, acc, M, dcut_total); break;
-            default: wg_run_sweeps<64>(a, sp, Psh, acc, M, dcut_total); break;
+            case 1: wg_run_sweeps<1>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            case 2: wg_run_sweeps<2>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            case 4: wg_run_sweeps<4>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            case 8: wg_run_sweeps<8>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            case 16: wg_run_sweeps<16>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            case 32: wg_run_sweeps<32>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
+            default: wg_run_sweeps<64>(a, sp, Psh, acc, thr_s, M, dcut_total); break;
             }
         }
         __syncthreads();

@@ -137,6 +137,43 @@ int relabel(const int32_t *rp, const int32_t *col, const int32_t *w, int32_t n, 
     return GDI_OK;
 }
 
+int pack_rows8(const Relabelled &g, PackedRows *out, std::string *err)
+{
+    const int32_t np = g.n_pad;
+    if (np >= 32767) {
+        if (err) *err = "packed rows need n_pad < 32767";
+        return -1;
+    }
+    for (const Edge &e : g.adj)
+        if (e.y != 1 && e.y != -1) {
+            if (err) *err = "packed rows need weights +-1";
+            return -1;
+        }
+    PackedRows r;
+    r.prow.assign((size_t)np + 1, 0);
+    uint64_t chunks = 0;
+    for (int32_t v = 0; v < np; ++v) {
+        r.prow[(size_t)v] = (uint32_t)chunks;
+        const int64_t len = (int64_t)g.rp[(size_t)v + 1] - g.rp[(size_t)v];
+        chunks += (uint64_t)((len + GDI_P8_ENTRIES - 1) / GDI_P8_ENTRIES);
+        if (chunks >= 0xFFFFFFFFull) {
+            if (err) *err = "packed rows: too many chunks";
+            return -1;
+        }
+    }
+    r.prow[(size_t)np] = (uint32_t)chunks;
+    r.pent.assign((size_t)std::max<uint64_t>(chunks, 1) * GDI_P8_ENTRIES, (uint16_t)np);
+    for (int32_t v = 0; v < np; ++v) {
+        size_t q = (size_t)r.prow[(size_t)v] * GDI_P8_ENTRIES;
+        for (int32_t k = g.rp[(size_t)v]; k < g.rp[(size_t)v + 1]; ++k, ++q) {
+            const Edge &e = g.adj[(size_t)k];
+            r.pent[q] = (uint16_t)((uint32_t)e.x | (e.y < 0 ? 0x8000u : 0u));
+        }
+    }
+    *out = std::move(r);
+    return 0;
+}
+
 int halo_layout(const Relabelled &g, int32_t C, int32_t G, int lds_budget, int32_t T0, int32_t lead, HaloLayout *out,
                 std::string *err)
 {

@@ -86,6 +86,21 @@ inline uint32_t pack_entry(int32_t lb, int32_t w)
     return ((uint32_t)(lb >> 5) << 16) | (((uint32_t)w & 0x7FFu) << 5) | ((uint32_t)lb & 31u);
 }
 
+// Packed rows of a graph whose weights are all +-1 and whose n_pad is below 32767: every
+// row is a whole number of 16-byte chunks of eight 16-bit entries, column | (weight < 0)
+// << 15, the last chunk filled with entries naming node n_pad (a spin slot that always
+// reads 0, so padding adds nothing to a local field). Row v occupies chunks
+// [prow[v], prow[v + 1]).
+#define GDI_P8_ENTRIES 8
+struct PackedRows {
+    std::vector<uint32_t> prow;   // n_pad + 1 chunk offsets
+    std::vector<uint16_t> pent;   // 8 x prow[n_pad] entries (at least one chunk)
+};
+
+// Returns 0, or -1 (not applicable: a weight other than +-1, n_pad >= 32767, or more
+// than 2^32 - 1 chunks) with a message in *err.
+int pack_rows8(const Relabelled &g, PackedRows *out, std::string *err);
+
 // The halo layout for G workgroups with the redundant tail from class T0 on.
 struct HaloLayout {
     int32_t status = 0;    // 0 = built; -2 = does not fit the LDS budget; -3 = a weight beyond GDI_HALO_WMAX

@@ -159,6 +159,35 @@ long check_layouts(const Csr &g, const char *name)
         }
     }
     long checked = 0;
+    // packed rows: built exactly for +-1 weights and n_pad < 32767; each row's chunks
+    // decode to its entries followed by padding that names node n_pad
+    {
+        bool pm1 = true;
+        for (const Edge &e : r.adj) pm1 = pm1 && (e.y == 1 || e.y == -1);
+        PackedRows pr;
+        const int rc = pack_rows8(r, &pr, &err);
+        CHECK((rc == 0) == (pm1 && r.n_pad < 32767), "%s: pack_rows8 applicability", name);
+        if (rc == 0) {
+            CHECK(pr.prow.size() == (size_t)r.n_pad + 1 && pr.prow[0] == 0, "%s: prow size", name);
+            CHECK(pr.pent.size() == (size_t)std::max<uint32_t>(pr.prow[(size_t)r.n_pad], 1) * GDI_P8_ENTRIES,
+                  "%s: pent size", name);
+            for (int32_t v = 0; v < r.n_pad; ++v) {
+                const int32_t r0 = r.rp[(size_t)v], deg = r.rp[(size_t)v + 1] - r0;
+                const uint32_t c0 = pr.prow[(size_t)v], c1 = pr.prow[(size_t)v + 1];
+                CHECK(c1 - c0 == (uint32_t)((deg + GDI_P8_ENTRIES - 1) / GDI_P8_ENTRIES), "%s: chunks of %d", name, v);
+                for (uint32_t q = 0; q < (c1 - c0) * GDI_P8_ENTRIES; ++q) {
+                    const uint16_t x = pr.pent[(size_t)c0 * GDI_P8_ENTRIES + q];
+                    if ((int32_t)q < deg) {
+                        const Edge &a = r.adj[(size_t)r0 + q];
+                        CHECK((x & 0x7FFF) == a.x && ((x >> 15) ? -1 : 1) == a.y, "%s: packed entry", name);
+                    } else {
+                        CHECK(x == (uint16_t)r.n_pad, "%s: padding entry", name);
+                    }
+                }
+                ++checked;
+            }
+        }
+    }
     const int budget = 160 * 1024 - 256;
     for (int32_t G : {8, 16, 64, 256}) {
         for (int32_t lead : {0, 8}) {

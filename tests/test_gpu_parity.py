@@ -114,14 +114,20 @@ def test_lds_resident_launch_shapes(gdi, oracle_lib, tune):
 
 @pytest.mark.parametrize("name", ["er800", "torus100"])
 def test_small_configs_take_the_lds_resident_sweep(gdi, oracle_lib, name):
-    """er800 and torus100 (+-1 / unit weights, small) run with the whole graph in LDS by
-    default; the same schedule with the CSR in global memory gives the same result."""
+    """On one workgroup, er800 and torus100 (+-1 / unit weights, small) run with the whole
+    graph in LDS; the same schedule with the CSR in global memory, and the automatic
+    choice (one workgroup for er800, the halo grid sweep for the 10,000-node torus), give
+    the same result."""
     g, T = gs.workload(name)
     T = T[:300]
     with gdi.Annealer(g) as a:
+        r_auto = a.anneal(T, 3, trace=True)
+        assert r_auto["result"]["scope"] == (gdi.SCOPE_WORKGROUP if g.n <= 6000 else gdi.SCOPE_GRID)
+        a.tune(scope=gdi.SCOPE_WORKGROUP)
         r_lds = a.anneal(T, 3, trace=True)
-        a.tune(csr_lds=-1)
+        a.tune(scope=gdi.SCOPE_WORKGROUP, csr_lds=-1)
         r_glb = a.anneal(T, 3, trace=True)
+    assert np.array_equal(r_auto["spins"], r_lds["spins"]) and r_auto["cut"] == r_lds["cut"]
     print(f"{name}: LDS-resident {r_lds['result']['sweep_ms']:.2f} ms, global CSR {r_glb['result']['sweep_ms']:.2f} ms",
           flush=True)
     assert np.array_equal(r_lds["spins"], r_glb["spins"]) and r_lds["cut"] == r_glb["cut"]
@@ -352,6 +358,22 @@ def test_asynchronous_sweep_against_the_oracle(gdi, oracle_lib, grid):
         with pytest.raises(gdi.GdiError) as e:
             a.anneal(T, 3, flags=gdi.FLAG_RACY, trace=True)
         assert e.value.code == gdi.EINVAL
+
+
+def test_large_weights_mid_size_fall_back_to_one_workgroup(gdi, oracle_lib):
+    """A 20,000-node graph would take the halo sweep, but its weights exceed the packed
+    range: the automatic choice runs it on one workgroup instead."""
+    g0 = gs.rgg_graph(20_000, 8.0, 23)
+    rows = np.repeat(np.arange(g0.n), np.diff(g0.row_ptr))
+    up = g0.col > rows
+    rng = np.random.default_rng(4)
+    w = rng.integers(-3000, 3001, int(up.sum()))
+    w[w == 0] = 1
+    g = gs.from_edges(g0.n, rows[up], g0.col[up], w)
+    T = gs.geometric_temps(4000.0, 50.0, 30)
+    ref, r, _ = run_both(gdi, oracle_lib, g, T, label="heavy-mid")
+    assert r["result"]["scope"] == gdi.SCOPE_WORKGROUP
+    assert_same(ref, r)
 
 
 def test_large_weights_take_the_fenced_grid_sweep(gdi, oracle_lib):
