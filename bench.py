@@ -50,6 +50,11 @@ def counter_bytes_per_sweep(path: str, workload: str):
     return None if w is None else float(w["hbm_bytes_per_sweep"])
 
 
+def progress(msg: str):
+    """One line per finished stage on stderr (stdout carries only the JSON result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes_per_sweep(n: int, nnz: int) -> int:
     """row_ptr (4(n+1)) + CSR column and weight (8 nnz) + spin read and write (2n)."""
     return 4 * (n + 1) + 8 * nnz + 2 * n
@@ -249,6 +254,7 @@ def forms_learned(gdi, gs, torch, seed, k_full=8, replicas=8):
     w, losses = gdi.mlp_train(dx.data_ptr(), dy.data_ptr(), off, gdi.mlp_init(seed), epochs=3, batch=4096, lr=2e-3,
                               seed=seed)
     t_train = time.perf_counter() - t0
+    progress(f"learned form: traces {t_collect:.1f} s, training {t_train:.1f} s")
     ybar = float(dy[:off].float().mean().item())
     out["training"] = {"graphs": [g.n for g in graphs], "rows": off, "frozen_fraction": ybar,
                        "collect_s": t_collect, "train_s": t_train, "epoch_loss": [float(x) for x in losses],
@@ -281,6 +287,7 @@ def forms_learned(gdi, gs, torch, seed, k_full=8, replicas=8):
                 rr = res["result"]
                 skip.append(rr.get("node_skips", 0) / max(1, rr.get("node_skips", 0) + rr.get("node_visits", 1)))
             runs[name] = (ms, Ms, cuts, skip)
+            progress(f"learned form: {name} x {replicas} replicas, {np.mean(ms):.1f} ms each")
     best_plain = best_state(runs["plain"][1], runs["plain"][2])
     target = best_plain * 1.005 if best_plain >= 0 else best_plain * 0.995
     for name, (ms, Ms, cuts, skip) in runs.items():
@@ -466,18 +473,26 @@ def main():
                    "tracked_cut": int(res.cut_weighted), "create_s": create_s},
     }
     ann.close()
+    progress(f"{args.workload}: {S} sweeps x {args.steps} steps timed, {line['ms_per_step']:.1f} ms per step")
     if not args.no_configs and args.workload == "rgg1m":
         line["layouts_rgg1m"] = layout_variants(gdi, g, temps, seed, torch)
+        progress("layout variants done")
     if not args.no_configs:
         line["configs"] = config_runs(gdi, gs, torch, seed, [w for w in ("er800", "torus100", "rgg8m")
                                                              if w != args.workload])
+        progress("configurations done")
     if not args.no_forms:
         line["forms"] = forms_batched(gdi, gs, torch, seed)
+        progress("batched form done")
         line["forms"]["learned_rgg200k"] = forms_learned(gdi, gs, torch, seed)
+        progress("learned form done")
         line["forms"]["gdi_vs_standard_torus"] = forms_standard(gdi, gs)
+        progress("standard solver done")
         line["forms"]["determinism_rgg1m"] = forms_racy(gdi, gs, seed)
+        progress("asynchronous form done")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, temps, seed, min(args.cpu_sweeps, S), min(args.cpu_sweeps_one, S))
+        progress("CPU baseline done")
     print(json.dumps(line), flush=True)
     # every handle is closed by now; leave no device work or library object to process exit
     import gc

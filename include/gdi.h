@@ -140,7 +140,8 @@ typedef struct {
     int32_t leaders;          /* GDI_SCOPE_GRID: > 0 = the 8 workgroups that collect the
                                  phase sums of their XCD (blocks 0..7) hold no nodes, so
                                  that no node work queues ahead of their polls; < 0 =
-                                 they hold nodes like every workgroup; 0 = automatic */
+                                 they hold nodes like every workgroup; 0 = automatic
+                                 (dedicated on grids of 64 or more workgroups) */
     int32_t general_weights;  /* GDI_SCOPE_GRID: > 0 = run the general-weight form of the
                                  sweep even when every weight is 1 (for measuring what the
                                  unit-weight form saves; same results); 0 = automatic */

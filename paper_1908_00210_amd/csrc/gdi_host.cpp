@@ -209,7 +209,9 @@ const int32_t kWgAutoNodes = 6144;
 
 int build_halo(gdi_graph *g, int32_t G, int lds_budget, int32_t nwork, int32_t lead);
 
-int pick_launch(gdi_graph *g, Choice *ch)
+// one_wg: the automatic scope takes one workgroup whenever the graph has at most
+// kWgMaxNodes padded nodes (the standard solver runs on one workgroup only)
+int pick_launch(gdi_graph *g, Choice *ch, bool one_wg)
 {
     const gdi_tuning t = g->have_tune ? g->tune : gdi_tuning{};
     const double avg = g->n ? (double)g->nnz / g->n : 0.0;
@@ -219,7 +221,8 @@ int pick_launch(gdi_graph *g, Choice *ch)
     ch->block = t.block ? t.block : 1024u;
     if (ch->block < 64 || ch->block > GDI_MAX_BLOCK || ch->block % 64 || ch->block < ch->lanes)
         return fail(GDI_EINVAL, "block must be a multiple of 64 in [64, 1024]");
-    ch->scope = t.scope ? t.scope : (g->n_pad <= kWgAutoNodes ? GDI_SCOPE_WORKGROUP : GDI_SCOPE_GRID);
+    ch->scope = t.scope ? t.scope
+                        : (g->n_pad <= (one_wg ? kWgMaxNodes : kWgAutoNodes) ? GDI_SCOPE_WORKGROUP : GDI_SCOPE_GRID);
     if (ch->scope < GDI_SCOPE_WORKGROUP || ch->scope > GDI_SCOPE_GRID_FENCED)
         return fail(GDI_EINVAL, "unknown scope");
     ch->grid = 1;
@@ -269,8 +272,10 @@ int pick_launch(gdi_graph *g, Choice *ch)
         // 256 workgroups; 5-9 % faster on a 2e5-node RGG at 128); tail_max < 0 turns it off
         const int32_t tail_auto = nwork;
         const int32_t tail_cap = t.tail_max < 0 ? 0 : (t.tail_max == 0 ? tail_auto : std::min(t.tail_max, nwork));
-        // dedicated group leaders: blocks 0..7 hold no nodes (automatic: never)
-        const int32_t lead = t.leaders > 0 ? 8 : 0;
+        // dedicated group leaders: blocks 0..7 hold no nodes (automatic: on grids of 64 or
+        // more workgroups; measured 105.9 -> 104.8 ms on the 1e6-node RGG at 256, and
+        // chosen by the autotuner on 1e4..6.4e4-node RGGs at 32 and 64)
+        const int32_t lead = t.leaders > 0 ? 8 : (t.leaders < 0 ? 0 : (G >= 64 ? 8 : 0));
         if (lead && G < 16) return fail(GDI_EINVAL, "dedicated leaders need a grid of at least 16 workgroups");
         int rc = build_halo(g, (int32_t)G, lds_max - 256, tail_cap, lead);
         if (rc) return rc;
@@ -595,7 +600,7 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
         return fail(GDI_ERANGE, "|B|*max_wdeg + 4|A|(n+1) must be < 2^31");
     const bool trace = s->trace_m || s->trace_cut;
 
-    if ((rc = pick_launch(g, &r.ch))) return rc;
+    if ((rc = pick_launch(g, &r.ch, (s->flags & GDI_FLAG_DENSE_BALANCE) != 0))) return rc;
     r.dense = (s->flags & GDI_FLAG_DENSE_BALANCE) != 0;
     r.racy = (s->flags & GDI_FLAG_RACY) != 0;
     if (r.dense) {
@@ -1079,8 +1084,9 @@ int autotune_graph(gdi_graph *g, const gdi_schedule *s, uint64_t seed, uint32_t 
         t.tail_max = -1;
         rc = consider(t);
         if (!rc && cur.grid >= 16) {
+            // the other leader arrangement than the automatic one for this grid
             t = cur;
-            t.leaders = 1;
+            t.leaders = cur.grid >= 64 ? -1 : 1;
             rc = consider(t);
         }
     }

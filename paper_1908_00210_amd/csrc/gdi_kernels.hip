@@ -60,6 +60,75 @@ __device__ __forceinline__ bool node_decide(const GdiSweepArgs &a, const int8_t 
     return decide_id(a, o, t, sigma, h, pv, thr_row, thr_l);
 }
 
+// A subgroup's first node of a phase, fetched ahead of the phase: its row bounds and
+// original id two phases before, the row's first GDI_AHEAD entries per lane one phase
+// before. CSR rows do not depend on spins, so these loads run under the earlier
+// phases' work and barriers, and the phase itself starts with LDS spin reads.
+#define GDI_AHEAD 4
+struct RowAhead {
+    int32_t v;              // new id, -1 when the subgroup has no node in the phase
+    int32_t r0, r1;
+    uint32_t o;             // original id
+    int2 e[GDI_AHEAD];      // entries r0 + lane + u * L (zero past the row)
+};
+
+// Bounds stage: node beg + j when j < hi.
+__device__ __forceinline__ void ahead_bounds(const GdiSweepArgs &a, int32_t beg, int32_t j, int32_t hi, RowAhead &r)
+{
+    r.v = j < hi ? beg + j : -1;
+    r.r0 = 0;
+    r.r1 = 0;
+    r.o = 0;
+    if (r.v >= 0) {
+        r.r0 = a.rp[r.v];
+        r.r1 = a.rp[r.v + 1];
+        r.o = (uint32_t)a.orig[r.v];
+    }
+}
+
+// Entries stage (after the bounds have arrived).
+template <int L>
+__device__ __forceinline__ void ahead_entries(const GdiSweepArgs &a, int lane, RowAhead &r)
+{
+#pragma unroll
+    for (int u = 0; u < GDI_AHEAD; ++u) {
+        const int32_t k = r.r0 + lane + u * L;
+        r.e[u] = k < r.r1 ? a.adj[k] : make_int2(0, 0);
+    }
+}
+
+// node_decide for a node fetched ahead: the first GDI_AHEAD entries per lane come from
+// registers, the rest of the row (if any) is read in rounds of U as usual.
+template <int L, int U = 4>
+__device__ __forceinline__ bool node_decide_ahead(const GdiSweepArgs &a, const int8_t *sp, const RowAhead &r, int lane,
+                                                  uint32_t t, const PhaseView &pv, const uint32_t *thr_row,
+                                                  const uint32_t *thr_l, int32_t *h_out, int32_t *sigma_out)
+{
+    int32_t h = 0;
+    {
+        int32_t sv[GDI_AHEAD];
+#pragma unroll
+        for (int u = 0; u < GDI_AHEAD; ++u) sv[u] = sp[r.e[u].x];
+#pragma unroll
+        for (int u = 0; u < GDI_AHEAD; ++u) h += r.e[u].y * sv[u];
+    }
+    for (int32_t k = r.r0 + lane + GDI_AHEAD * L; k < r.r1; k += U * L) {
+        int2 e[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) e[u] = k + u * L < r.r1 ? a.adj[k + u * L] : make_int2(0, 0);
+        int32_t sv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) sv[u] = sp[e[u].x];
+#pragma unroll
+        for (int u = 0; u < U; ++u) h += e[u].y * sv[u];
+    }
+    if (L > 1) h = group_sum<L>(h);
+    const int32_t sigma = sp[r.v];
+    *h_out = h;
+    *sigma_out = sigma;
+    return decide_id(a, r.o, t, sigma, h, pv, thr_row, thr_l);
+}
+
 // ------------------------------------------------------------------ workgroup scope
 // All sweeps of one instance inside one workgroup: phases are separated by
 // s_barrier, dM is summed in an LDS triple buffer (one barrier per phase).
@@ -82,6 +151,18 @@ __device__ __forceinline__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp,
     if (thr_lds && a.t0 < a.S)
         for (int i = tid; i < K1; i += nth) thr_s[(a.t0 & 1u) * GDI_WG_THR_MAX + i] = a.thr[(size_t)a.t0 * K1 + i];
     __syncthreads();
+    // the subgroup's first node of this phase (bounds and entries fetched) and of the
+    // next phase (bounds fetched); phases run (t, 0..C-1) for t = t0..S-1
+    RowAhead cur, b1;
+    cur.v = b1.v = -1;
+    cur.r0 = cur.r1 = b1.r0 = b1.r1 = 0;
+    cur.o = b1.o = 0;
+    if (a.t0 < a.S) {
+        ahead_bounds(a, a.cbeg[0], sub, a.csz[0], cur);
+        ahead_entries<L>(a, lane, cur);
+        const bool wrap = a.C == 1;
+        if (!wrap || a.t0 + 1u < a.S) ahead_bounds(a, a.cbeg[wrap ? 0 : 1], sub, a.csz[wrap ? 0 : 1], b1);
+    }
     for (uint32_t t = a.t0; t < a.S; ++t) {
         const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)K1;
         const uint32_t *thr_l = thr_lds ? thr_s + (t & 1u) * GDI_WG_THR_MAX : nullptr;
@@ -92,11 +173,21 @@ __device__ __forceinline__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp,
             int32_t dM = 0;
             // each subgroup loads the next node's row bounds while it works on this one
             int32_t nr0 = 0, nr1 = 0;
-            if (sub < size) {
-                nr0 = a.rp[beg + sub];
-                nr1 = a.rp[beg + sub + 1];
+            if (sub + nsub < size) {
+                nr0 = a.rp[beg + sub + nsub];
+                nr1 = a.rp[beg + sub + nsub + 1];
             }
-            for (int32_t j = sub; j < size; j += nsub) {
+            if (cur.v >= 0 && !(a.mask && ((a.mask[cur.v >> 5] >> (cur.v & 31)) & 1u))) {
+                int32_t h, sigma;
+                const bool flip = node_decide_ahead<L, U>(a, sp, cur, lane, t, pv, thr_row, thr_l, &h, &sigma);
+                if (flip && lane == 0) {
+                    sp[cur.v] = (int8_t)(-sigma);
+                    dM -= 2 * sigma;
+                    dcut += (int64_t)sigma * h;
+                    if (a.last_flip) a.last_flip[cur.v] = (int32_t)t;
+                }
+            }
+            for (int32_t j = sub + nsub; j < size; j += nsub) {
                 const int32_t v = beg + j;
                 const int32_t r0 = nr0, r1 = nr1;
                 if (j + nsub < size) {
@@ -116,6 +207,22 @@ __device__ __forceinline__ void wg_run_sweeps(const GdiSweepArgs &a, int8_t *sp,
             if (c + 1 == a.C && thr_lds && t + 1u < a.S)
                 for (int i = tid; i < K1; i += nth)
                     thr_s[((t + 1u) & 1u) * GDI_WG_THR_MAX + i] = a.thr[(size_t)(t + 1u) * K1 + i];
+            // after this phase's loads: the next phase's entries and the bounds of the phase
+            // after it (issued last, so that no wait of this phase's work covers them)
+            ahead_entries<L>(a, lane, b1);
+            cur = b1;
+            {
+                int32_t c2 = c + 2;
+                uint32_t t2 = t;
+                while (c2 >= a.C) {
+                    c2 -= a.C;
+                    ++t2;
+                }
+                b1.v = -1;
+                b1.r0 = b1.r1 = 0;
+                b1.o = 0;
+                if (t2 < a.S) ahead_bounds(a, a.cbeg[c2], sub, a.csz[c2], b1);
+            }
             dM = wave_sum_i32(dM);
             if ((tid & 63) == 0 && dM != 0) atomicAdd(&acc[p % 3], dM);
             __syncthreads();
@@ -460,6 +567,21 @@ __device__ __forceinline__ void cluster_run_sweeps(const GdiSweepArgs &a, const 
     __syncthreads();
     int64_t dcut = 0;
     uint32_t p = 0;
+    // this member's first node of a class for the subgroup, fetched ahead as in the
+    // workgroup loop
+    auto first_bounds = [&](int32_t cc, RowAhead &ra) {
+        const int32_t sz = a.csz[cc];
+        ahead_bounds(a, a.cbeg[cc], member_bound(sz, r, k) + sub, member_bound(sz, r + 1, k), ra);
+    };
+    RowAhead cur, b1;
+    cur.v = b1.v = -1;
+    cur.r0 = cur.r1 = b1.r0 = b1.r1 = 0;
+    cur.o = b1.o = 0;
+    if (a.t0 < a.S) {
+        first_bounds(0, cur);
+        ahead_entries<L>(a, lane, cur);
+        if (a.C > 1 || a.t0 + 1u < a.S) first_bounds(a.C > 1 ? 1 : 0, b1);
+    }
     for (uint32_t t = a.t0; t < a.S; ++t) {
         const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)K1;
         const uint32_t *thr_l = thr_lds ? thr_s + (t & 1u) * GDI_WG_THR_MAX : nullptr;
@@ -470,11 +592,20 @@ __device__ __forceinline__ void cluster_run_sweeps(const GdiSweepArgs &a, const 
             const PhaseView pv = make_view(M, Psh[c], size, a.C, a.n);
             int32_t dM = 0;
             int32_t nr0 = 0, nr1 = 0;
-            if (lo + sub < hi) {
-                nr0 = a.rp[beg + lo + sub];
-                nr1 = a.rp[beg + lo + sub + 1];
+            if (lo + sub + nsub < hi) {
+                nr0 = a.rp[beg + lo + sub + nsub];
+                nr1 = a.rp[beg + lo + sub + nsub + 1];
             }
-            for (int32_t j = lo + sub; j < hi; j += nsub) {
+            if (cur.v >= 0) {
+                int32_t h, sigma;
+                const bool flip = node_decide_ahead<L, U>(a, sp, cur, lane, t, pv, thr_row, thr_l, &h, &sigma);
+                if (flip && lane == 0) {
+                    sp[cur.v] = (int8_t)(-sigma);
+                    dM -= 2 * sigma;
+                    dcut += (int64_t)sigma * h;
+                }
+            }
+            for (int32_t j = lo + sub + nsub; j < hi; j += nsub) {
                 const int32_t v = beg + j;
                 const int32_t r0 = nr0, r1 = nr1;
                 if (j + nsub < hi) {
@@ -493,6 +624,22 @@ __device__ __forceinline__ void cluster_run_sweeps(const GdiSweepArgs &a, const 
             if (c + 1 == a.C && thr_lds && t + 1u < a.S)
                 for (int i = tid; i < K1; i += nth)
                     thr_s[((t + 1u) & 1u) * GDI_WG_THR_MAX + i] = a.thr[(size_t)(t + 1u) * K1 + i];
+            // the next phase's entries, the bounds of the phase after it (issued after this
+            // phase's loads; the exchange below hides them)
+            ahead_entries<L>(a, lane, b1);
+            cur = b1;
+            {
+                int32_t c2 = c + 2;
+                uint32_t t2 = t;
+                while (c2 >= a.C) {
+                    c2 -= a.C;
+                    ++t2;
+                }
+                b1.v = -1;
+                b1.r0 = b1.r1 = 0;
+                b1.o = 0;
+                if (t2 < a.S) first_bounds(c2, b1);
+            }
             dM = wave_sum_i32(dM);
             if ((tid & 63) == 0 && dM != 0) atomicAdd(&acc[p % 3], dM);
             __syncthreads();

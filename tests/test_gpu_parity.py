@@ -82,6 +82,9 @@ def test_small_graphs(gdi, oracle_lib, name, mode, scope):
     dict(scope=2, grid=256, tail_max=-1),
     dict(scope=2, grid=64, tail_max=100),
     dict(scope=2, grid=16, block=512, tail_max=300),
+    dict(scope=2, grid=16, leaders=1),
+    dict(scope=2, grid=64, leaders=-1),
+    dict(scope=2, grid=256, leaders=1, tail_max=-1),
     dict(scope=3, lanes_per_node=1, block=64, grid=1),
     dict(scope=3, lanes_per_node=2, block=128, grid=7),
     dict(scope=3, lanes_per_node=16, block=512, grid=64),
