@@ -315,6 +315,38 @@ __device__ __forceinline__ bool poll_phase_words(const GdiHaloArgs &h, const Gdi
     return true;
 }
 
+// Copies of up to three global ranges into LDS as one index space, PRO_INFLIGHT loads
+// per thread issued before any store, so the copies cost one memory round trip per
+// PRO_INFLIGHT x nth words rather than one per range.
+#define PRO_INFLIGHT 8
+struct LdsCopy {
+    uint32_t *dst;
+    const uint32_t *src;
+    int32_t n;
+};
+__device__ __forceinline__ void copy_ranges(const LdsCopy (&r)[3], int tid, int nth)
+{
+    const int32_t n01 = r[0].n + r[1].n, total = n01 + r[2].n;
+    for (int32_t base = 0; base < total; base += PRO_INFLIGHT * nth) {
+        uint32_t v[PRO_INFLIGHT];
+#pragma unroll
+        for (int u = 0; u < PRO_INFLIGHT; ++u) {
+            const int32_t i = base + u * nth + tid;
+            v[u] = 0u;
+            if (i < r[0].n) v[u] = r[0].src[i];
+            else if (i < n01) v[u] = r[1].src[i - r[0].n];
+            else if (i < total) v[u] = r[2].src[i - n01];
+        }
+#pragma unroll
+        for (int u = 0; u < PRO_INFLIGHT; ++u) {
+            const int32_t i = base + u * nth + tid;
+            if (i < r[0].n) r[0].dst[i] = v[u];
+            else if (i < n01) r[1].dst[i - r[0].n] = v[u];
+            else if (i < total) r[2].dst[i - n01] = v[u];
+        }
+    }
+}
+
 // Node of worker thread tid in the first pass of class s, or -1.
 __device__ __forceinline__ int32_t step_node(const GdiHaloArgs &h, const GdiHaloEntry *tab, int32_t s, int tid)
 {
@@ -385,21 +417,59 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     int32_t M = (int32_t)a.state[0];
     __syncthreads();
 
-    // prologue: the foreign-word ids, then every own, foreign and gather word and the tail
-    // region straight from the spin array, which no workgroup writes before its epilogue,
-    // so no workgroup waits for another here (words published during the launch carry
-    // epochs >= epoch0 + 2, words left by earlier launches smaller ones)
-    for (int32_t i = tid; i < h.flist_len; i += nth) bits[h.list_off + i] = (uint32_t)h.flist[(size_t)b * h.flist_len + i];
-    __syncthreads();
-    for (int32_t c = 0; c < T0; ++c) {
-        const GdiHaloEntry e = tab[c];
-        const int32_t w0 = e.node_lo >> 5, nown = e.node_hi > e.node_lo ? ((e.node_hi + 31) >> 5) - w0 : 0;
-        for (int32_t wd = tid; wd < nown; wd += nth) bits[e.own_off + wd] = pack_spins(a.spin, w0 + wd);
-        for (int32_t i = tid; i < e.for_len; i += nth)
-            bits[e.for_off + i] = pack_spins(a.spin, (int32_t)bits[e.list_off + i]);
+    // prologue: every own, foreign and gather word and the tail region straight from the
+    // spin array, which no workgroup writes before its epilogue, so no workgroup waits for
+    // another here (words published during the launch carry epochs >= epoch0 + 2, words
+    // left by earlier launches smaller ones). The own and foreign words of classes
+    // 0..T0-1 and the gather words form one index space (a word's id comes from the
+    // chunk bounds, the foreign list in global memory, or the gather list), with up to
+    // PRO_INFLIGHT words per thread in flight; the copies follow as one more space.
+    {
+        const int32_t *flist_b = h.flist + (size_t)b * h.flist_len;
+        int32_t n_cls = 0;
+        for (int32_t c = 0; c < T0; ++c) {
+            const GdiHaloEntry e = tab[c];
+            n_cls += (e.node_hi > e.node_lo ? ((e.node_hi + 31) >> 5) - (e.node_lo >> 5) : 0) + e.for_len;
+        }
+        const int32_t n_gat = has_tail ? h.gat_beg[T0] : 0, n_all = n_cls + n_gat;
+        for (int32_t base = 0; base < n_all; base += PRO_INFLIGHT * nth) {
+            int32_t wd[PRO_INFLIGHT], dst[PRO_INFLIGHT];
+#pragma unroll
+            for (int u = 0; u < PRO_INFLIGHT; ++u) {
+                int32_t i = base + u * nth + tid;
+                wd[u] = -1;
+                dst[u] = 0;
+                if (i < n_cls) {
+                    int32_t c = 0;
+                    for (;; ++c) {
+                        const GdiHaloEntry e = tab[c];
+                        const int32_t nown = e.node_hi > e.node_lo ? ((e.node_hi + 31) >> 5) - (e.node_lo >> 5) : 0;
+                        if (i < nown) {
+                            wd[u] = (e.node_lo >> 5) + i;
+                            dst[u] = e.own_off + i;
+                            break;
+                        }
+                        i -= nown;
+                        if (i < e.for_len) {
+                            wd[u] = flist_b[e.list_off - h.list_off + i];
+                            dst[u] = e.for_off + i;
+                            break;
+                        }
+                        i -= e.for_len;
+                    }
+                } else if (i < n_all) {
+                    wd[u] = h.gat_words[i - n_cls];
+                    dst[u] = h.gather_off + (i - n_cls);
+                }
+            }
+            uint32_t word[PRO_INFLIGHT];
+#pragma unroll
+            for (int u = 0; u < PRO_INFLIGHT; ++u) word[u] = wd[u] >= 0 ? pack_spins(a.spin, wd[u]) : 0u;
+#pragma unroll
+            for (int u = 0; u < PRO_INFLIGHT; ++u)
+                if (wd[u] >= 0) bits[dst[u]] = word[u];
+        }
     }
-    if (has_tail)
-        for (int32_t i = tid; i < h.gat_beg[T0]; i += nth) bits[h.gather_off + i] = pack_spins(a.spin, h.gat_words[i]);
     for (int32_t b0 = tail_base + wave * 64; b0 < a.n_pad; b0 += nwaves * 64) {
         const uint64_t m = __ballot(a.spin[b0 + lane] > 0);
         if (lane == 0) {
@@ -407,15 +477,19 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
             bits[h.tail_off + ((b0 - tail_base) >> 5) + 1] = (uint32_t)(m >> 32);
         }
     }
-    // the tail's CSR (row offsets, then entries as LDS bit index and weight) stays in LDS
+    // the foreign-word ids (polled from LDS in the sweep), the tail's CSR (row offsets,
+    // then entries as LDS bit index and weight) and this workgroup's overflow entries
     int32_t *trp = reinterpret_cast<int32_t *>(bits + h.trp_off);
     uint32_t *tent = bits + h.tent_off;
-    if (has_tail) {
-        for (int32_t i = tid; i <= h.tail_n; i += nth) trp[i] = h.tail_rp[i];
-        for (int32_t i = tid; i < h.tail_nnz; i += nth) tent[i] = h.tail_ent[i];
+    {
+        const LdsCopy r0[3] = {
+            {bits + h.list_off, reinterpret_cast<const uint32_t *>(h.flist + (size_t)b * h.flist_len), h.flist_len},
+            {bits + h.ovf_off, h.ovf + (size_t)b * h.ovf_len, h.ovf_len},
+            {reinterpret_cast<uint32_t *>(trp), reinterpret_cast<const uint32_t *>(h.tail_rp), has_tail ? h.tail_n + 1 : 0}};
+        copy_ranges(r0, tid, nth);
+        const LdsCopy r1[3] = {{tent, h.tail_ent, has_tail ? h.tail_nnz : 0}, {bits, nullptr, 0}, {bits, nullptr, 0}};
+        copy_ranges(r1, tid, nth);
     }
-    // overflow entries of this workgroup's long rows
-    for (int32_t i = tid; i < h.ovf_len; i += nth) bits[h.ovf_off + i] = h.ovf[(size_t)b * h.ovf_len + i];
     // pipeline fill: phase 0 entries, phase 1 rows
     NodePrefetch pf;
     RowAhead ra;
