@@ -154,6 +154,18 @@ __device__ __forceinline__ bool gate_open(const GdiSweepArgs &a)
     return (active <= a.active_max) == (a.gate_small != 0);
 }
 
+// First sweep of a launch that can start late: t0 with the gate open, else gate_t0.
+__device__ __forceinline__ uint32_t launch_begin(const GdiSweepArgs &a)
+{
+    return gate_open(a) ? a.t0 : a.gate_t0;
+}
+
+// Node v sits out sweep t (the proposal's mask, for sweeps before mask_end).
+__device__ __forceinline__ bool masked_out(const GdiSweepArgs &a, int32_t v, uint32_t t)
+{
+    return a.mask && t < a.mask_end && ((a.mask[v >> 5] >> (v & 31)) & 1u);
+}
+
 // ------------------------------------------------------------------ words shared between workgroups
 __device__ __forceinline__ uint64_t ld_agent(const uint64_t *p)
 {

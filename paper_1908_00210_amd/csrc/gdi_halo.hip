@@ -359,7 +359,9 @@ template <bool UNIT>
 __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
 {
     const GdiSweepArgs &a = h.base;
-    if (!gate_open(a)) return;
+    // sweeps t_begin..S-1 (t_begin is t0, or gate_t0 when the launch gate is closed)
+    const uint32_t t_begin = launch_begin(a);
+    if (t_begin >= a.S) return;
     extern __shared__ uint32_t lds[];
     uint32_t *bits = lds;                                                   // image, gather, tail, lists
     GdiHaloEntry *tab = reinterpret_cast<GdiHaloEntry *>(lds + h.lds_words); // C entries
@@ -405,8 +407,8 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
         Psh[i] = a.P[i];
         csz_sh[i] = a.csz[i];
     }
-    if (thr_lds && a.t0 < a.S)
-        for (int i = tid; i < K1; i += nth) thr_sh[(a.t0 & 1u) * K1 + i] = a.thr[(size_t)a.t0 * K1 + i];
+    if (thr_lds)
+        for (int i = tid; i < K1; i += nth) thr_sh[(t_begin & 1u) * K1 + i] = a.thr[(size_t)t_begin * K1 + i];
     if (tid == 0) {
         wg_acc = 0;
         total_sh = 0;
@@ -494,12 +496,12 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     NodePrefetch pf;
     RowAhead ra;
     {
-        const uint32_t t1 = T0 > 1 ? a.t0 : a.t0 + 1u;
+        const uint32_t t1 = T0 > 1 ? t_begin : t_begin + 1u;
         const int32_t s1 = T0 > 1 ? 1 : 0;
         const int32_t v0 = step_node(h, tab, 0, tid);
-        if (worker && a.t0 < a.S && v0 >= 0) {
+        if (worker && v0 >= 0) {
             load_row(a, v0, ra);
-            load_entries(h, ra, a.t0, pf);
+            load_entries(h, ra, t_begin, pf);
         }
         const int32_t v1 = step_node(h, tab, s1, tid);
         if (worker && t1 < a.S && v1 >= 0) load_row(a, v1, ra);
@@ -517,7 +519,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     // grid phase's dM travels
     uint32_t tx0 = 0, tx1 = 0;
     bool ttie = false;  // low bit of its word x2
-    for (uint32_t t = a.t0; t < a.S; ++t) {
+    for (uint32_t t = t_begin; t < a.S; ++t) {
         const uint32_t *thr_l = thr_sh + (t & 1u) * K1;
         const uint32_t *thr_g = a.thr + (size_t)t * K1;
         for (int32_t c = 0; c < T0; ++c, ++p) {
@@ -540,7 +542,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                     const bool active = v < e.node_hi;
                     bool flip = false;
                     int32_t sigma_l = 0;
-                    if (active && !(a.mask && ((a.mask[v >> 5] >> (v & 31)) & 1u))) {
+                    if (active && !masked_out(a, v, t)) {
                         NodePrefetch q;
                         if (base != e.node_lo) {
                             RowAhead rq;
@@ -595,7 +597,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                 const int32_t s2 = last_s1 ? 0 : s1 + 1;
                 // nodes the proposal skips need no entries
                 const int32_t v1 = step_node(h, tab, s1, tid);
-                const bool want1 = t1 < a.S && v1 >= 0 && !(a.mask && ((a.mask[v1 >> 5] >> (v1 & 31)) & 1u));
+                const bool want1 = t1 < a.S && v1 >= 0 && !masked_out(a, v1, t1);
                 if (t1 < a.S) {
                     if (c + 1 == T0 && thr_lds && t + 1u < a.S)
                         for (int i = tid; i < K1; i += nwork) thr_sh[((t + 1u) & 1u) * K1 + i] = a.thr[(size_t)(t + 1u) * K1 + i];
@@ -683,7 +685,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
             // Its CSR is in LDS, so no global load is in flight across these barriers.
             for (int32_t tc = T0; tc < a.C; ++tc, ++kk) {
                 int32_t dM = 0;
-                if (worker && my_tc == tc && !(a.mask && ((a.mask[my_tail >> 5] >> (my_tail & 31)) & 1u))) {
+                if (worker && my_tc == tc && !masked_out(a, my_tail, t)) {
                     const PhaseView pv = make_view(M, Psh[tc], csz_sh[tc], a.C, a.n);
                     const int32_t v = my_tail;
                     const int32_t hv = lds_field(bits, tent, trp[tid], trp[tid + 1]);

@@ -700,8 +700,11 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
 // skip) and last_flip are optional.
 // With gate set, the launch runs only if more than active_max nodes are active (the
 // active-set kernel takes the other case).
+// Sweeps t_from..t_to-1; the mask (if any) applies to sweeps before mask_end (0: all);
+// a closed gate skips the launch, or with gate_t0 > 0 (grid scope only) starts it at
+// sweep gate_t0.
 int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const uint32_t *mask, int32_t *last_flip,
-                 const uint64_t *gate = nullptr, int32_t active_max = 0)
+                 const uint64_t *gate = nullptr, int32_t active_max = 0, uint32_t mask_end = 0, uint32_t gate_t0 = 0)
 {
     hipStream_t st = g->stream;
     GdiSweepArgs a = r.a;
@@ -712,6 +715,12 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
     a.skip_count = reinterpret_cast<const unsigned long long *>(gate);
     a.active_max = active_max;
     a.gate_small = 0;
+    a.mask_end = mask_end ? mask_end : t_to;
+    a.gate_t0 = gate_t0 ? gate_t0 : t_to;
+    if ((mask_end && mask_end != t_to) || gate_t0) {
+        if (r.ch.scope != GDI_SCOPE_GRID || r.racy || r.dense)
+            return fail(GDI_EDEVICE, "internal: a partial mask or a late start needs the grid sweep");
+    }
     int rc = 0;
     if (r.racy) {
         // Alg. 3 in one persistent launch; the magnetisation stays the one its atomic
@@ -1503,12 +1512,21 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
     const uint32_t b0 = std::min(S, std::max(t_start, cfg->learn_from));
     if (cfg->mask_trace)
         std::memset(cfg->mask_trace, 0, (size_t)((S - b0 + k - 1) / k) * (size_t)g->n);
+    // On the grid sweep one launch runs a block's masked sweeps and the next block's full
+    // sweep (one cooperative launch per block instead of two): the mask stops applying at
+    // the block's end, and when the active-set kernel has run the masked sweeps the launch
+    // starts at the full sweep.
+    const bool merged = r.ch.scope == GDI_SCOPE_GRID;
     HIP_TRY(hipEventRecord(g->ev0, st), "hipEventRecord");
     if (b0 > t_start && (rc = launch_range(g, r, t_start, b0, nullptr, lf.p))) return rc;
+    if (merged && b0 < S && (rc = launch_range(g, r, b0, b0 + 1, nullptr, lf.p))) return rc;
     for (uint32_t b = b0; b < S; b += k) {
-        if ((rc = launch_range(g, r, b, b + 1, nullptr, lf.p))) return rc;
+        if (!merged && (rc = launch_range(g, r, b, b + 1, nullptr, lf.p))) return rc;
         if (b + 1 >= S) break;
         const uint32_t end = std::min<uint32_t>(b + k, S);
+        // the sweeps this block's launch on the grid sweep runs: the masked ones, then the
+        // next block's full sweep
+        const uint32_t t_next = merged ? std::min<uint32_t>(end + 1, S) : end;
         const uint32_t *mp = nullptr;
         if (cfg->skip_mode == GDI_SKIP_MLP) {
             e = gdi_launch_features(g->d_rp.p, g->d_adj.p, g->d_spin.p, lf.p, g->n_pad, g->d_state.p,
@@ -1542,9 +1560,13 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
             a.skip_count = reinterpret_cast<const unsigned long long *>(skipped.p + 1);
             a.active_max = amax;
             a.gate_small = 1;
+            a.mask_end = end;
+            a.gate_t0 = end;
             if ((e = gdi_launch_sweep_active(a, rec.p, st))) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
-            if ((rc = launch_range(g, r, b + 1, end, mp, lf.p, skipped.p + 1, amax))) return rc;
-        } else if ((rc = launch_range(g, r, b + 1, end, mp, lf.p))) {
+            if ((rc = launch_range(g, r, b + 1, t_next, mp, lf.p, skipped.p + 1, amax, merged ? end : 0,
+                                   merged ? end : 0)))
+                return rc;
+        } else if ((rc = launch_range(g, r, b + 1, t_next, mp, lf.p, nullptr, 0, merged && mp ? end : 0))) {
             return rc;
         }
     }

@@ -54,6 +54,11 @@ struct GdiSweepArgs {
     const unsigned long long *skip_count;
     int32_t active_max;
     int32_t gate_small;
+    // a launch whose gate is closed starts at sweep gate_t0 instead of t0 (gate_t0 >= S: it
+    // does nothing); the mask applies to sweeps t < mask_end only (the grid sweep uses both
+    // to run one block's masked sweeps and the next block's full sweep in one launch)
+    uint32_t gate_t0;
+    uint32_t mask_end;
 };
 
 // Record of one active node of a masked launch (k_sweep_active).
