@@ -104,6 +104,52 @@ def gpu_runs(ann, temps, seed, out_ptr, reps):
     return ms
 
 
+def cut_timing(ann, torch, d_spins, n: int, nnz: int, reps: int = 20) -> dict:
+    """gdi_cut from scratch on resident spins through the allocation-free entry point (the
+    spins gathered into the annealer's order, k_reduce, the final sum), called reps times
+    between two events on the handle's stream with no host synchronisation in between.
+    Algorithmic bytes per call: the gather's original ids, input and output spins
+    (4n + 2n), then row pointers 4(n+1), CSR entries 8 nnz and spins n (neighbour spins
+    are gathers from cache and not counted; the class padding is left out)."""
+    d_out = torch.zeros(3, dtype=torch.int64, device="cuda:0")
+    for _ in range(3):
+        ann.cut_dev_noalloc(d_spins, d_out.data_ptr())
+    s = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        ann.cut_dev_noalloc(d_spins, d_out.data_ptr())
+    e1.record(s)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    b = 6 * n + 4 * (n + 1) + 8 * nnz + n
+    return {"kernel": "k_reduce", "us_per_call": us, "bytes_per_call": b, "algorithmic_gbs": b / us / 1e3,
+            "frac": b / us / 1e3 / HBM_PEAK_GBS, "calls": reps}
+
+
+def form_paper_rule(gdi, g, seed, metropolis_ms: float) -> dict:
+    """The paper's acceptance rule (argmin, then a random flip with probability P_f(t);
+    P_f geometric 0.2 -> 0.001) on the headline graph, next to the Metropolis schedule's
+    kernel time: the rule changes the decision, not the sweep's cost."""
+    import numpy as np
+
+    import gdi_synth as gs
+
+    S = 2000
+    pf = gs.geometric_temps(0.2, 0.001, S)
+    with gdi.Annealer(g) as a:
+        a.anneal(pf[:10], seed, acceptance=gdi.ACCEPT_PAPER)
+        ms, cuts, Ms = [], [], []
+        for rep in range(2):
+            r = a.anneal(pf, seed + rep, acceptance=gdi.ACCEPT_PAPER)
+            ms.append(r["result"]["sweep_ms"])
+            cuts.append(int(r["cut"]))
+            Ms.append(int(r["M"]))
+    return {"sweeps": S, "p_f": [0.2, 0.001], "mean_kernel_ms": float(np.mean(ms)), "metropolis_kernel_ms": metropolis_ms,
+            "cuts": cuts, "M": Ms, "spin_updates_per_s": g.n * S / (float(np.mean(ms)) / 1e3)}
+
+
 def layout_variants(gdi, g, temps, seed, torch, reps=3):
     """The same 1M-node anneal with the unit-weight form switched off (the packed entries'
     11-bit weights summed as general weights) and with the uncompressed layout (int32
@@ -144,12 +190,15 @@ def config_runs(gdi, gs, torch, seed, names, reps=5):
             ms = float(np.median(gpu_runs(a, T, seed, d_out.data_ptr(), reps)))
             r = a.result()
             cw, ce, m = a.cut_dev(d_out.data_ptr())
+            cut_row = cut_timing(a, torch, d_out.data_ptr(), g.n, g.nnz) if g.n > 100_000 else None
         kern_s = ms / 1e3
         row = {"n": g.n, "nnz": g.nnz, "sweeps": int(T.size), "scope": int(r.scope), "grid": int(r.grid),
                "colours": int(r.n_colours), "kernel_ms": ms, "sweeps_per_s": T.size / kern_s,
                "spin_updates_per_s": g.n * T.size / kern_s,
                "algorithmic_gbs": algorithmic_bytes_per_sweep(g.n, g.nnz) * T.size / kern_s / 1e9,
                "M": int(m), "cut_weighted": int(cw), "cut_edges": int(ce)}
+        if cut_row is not None:
+            row["cut"] = cut_row
         cb = counter_bytes_per_sweep(os.path.join(ROOT, "profiles", "traffic.json"), name)
         if cb is not None and r.scope == gdi.SCOPE_GRID:
             row["hbm_gbs_counters"] = cb * T.size / kern_s / 1e9
@@ -422,6 +471,8 @@ def main():
     res = ann.result()
     cw, ce, m = ann.cut_dev(out.data_ptr())
     info = ann.info
+    # the from-scratch cut (gdi_cut) on the annealed spins, resident on the device
+    cut_row = cut_timing(ann, torch, out.data_ptr(), g.n, g.nnz)
 
     n, nnz = g.n, g.nnz
     updates = n * S
@@ -471,6 +522,7 @@ def main():
         },
         "result": {"M": int(m), "cut_weighted": int(cw), "cut_edges": int(ce),
                    "tracked_cut": int(res.cut_weighted), "create_s": create_s},
+        "cut": cut_row,
     }
     ann.close()
     progress(f"{args.workload}: {S} sweeps x {args.steps} steps timed, {line['ms_per_step']:.1f} ms per step")
@@ -490,6 +542,9 @@ def main():
         progress("standard solver done")
         line["forms"]["determinism_rgg1m"] = forms_racy(gdi, gs, seed)
         progress("asynchronous form done")
+        if args.workload == "rgg1m":
+            line["forms"]["paper_rule_rgg1m"] = form_paper_rule(gdi, g, seed, kern_s * 1e3)
+            progress("paper acceptance rule done")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(g, temps, seed, min(args.cpu_sweeps, S), min(args.cpu_sweeps_one, S))
         progress("CPU baseline done")

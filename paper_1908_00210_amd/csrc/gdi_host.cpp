@@ -641,7 +641,7 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_red.p), 4, st);
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_P.p), (g->C + 2) / 2, st);
     if (!rc && trace) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_trace.p), 2 * (int64_t)S, st);
-    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->d_cbeg.p, g->d_csz.p,
+    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p,
                                     g->C, g->d_red.p, g->d_P.p, st);
     // the sweep kernels read the initial M from state[0]
     if (!rc) {
@@ -738,7 +738,7 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
         if (!rc && sweeps > 0) rc = gdi_launch_sweep_async(a, grid, 1024, st);
         if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_red.p), 4, st);
         if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_P.p), (g->C + 2) / 2, st);
-        if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->d_cbeg.p, g->d_csz.p, g->C,
+        if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p, g->C,
                                         g->d_red.p, g->d_P.p, st);
         if (!rc) g->last.grid = (uint32_t)grid;
         if (!rc) g->last.block = 1024;
@@ -857,7 +857,7 @@ int cut_impl(gdi_graph *g, const int8_t *spins, bool dev, int64_t *cw, int64_t *
     rc = gdi_launch_gather_in(g->d_orig.p, src, g->n_pad, tmp.p, st);
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(red.p), 4, st);
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(P.p), (g->C + 2) / 2, st);
-    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, tmp.p, g->n_pad, g->d_cbeg.p, g->d_csz.p, g->C,
+    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, tmp.p, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p, g->C,
                                     red.p, P.p, st);
     if (rc) {
         tmp.release(); P.release(); red.release();
@@ -1864,7 +1864,7 @@ int gdi_cut_dev_noalloc(gdi_graph *g, const int8_t *d_spins, int64_t *d_out)
     int rc = gdi_launch_gather_in(g->d_orig.p, d_spins, g->n_pad, sp, st);
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(red), 4, st);
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(P), (g->C + 2) / 2, st);
-    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, sp, g->n_pad, g->d_cbeg.p, g->d_csz.p, g->C, red, P, st);
+    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, sp, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p, g->C, red, P, st);
     if (!rc) rc = gdi_launch_cut_finish(red, d_out, st);
     if (rc) return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
     return GDI_OK;

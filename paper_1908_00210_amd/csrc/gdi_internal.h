@@ -169,7 +169,7 @@ struct GdiMlpDev {
 // host-side launchers (gdi_kernels.hip)
 int gdi_launch_init_spins(const int32_t *orig, const int8_t *init_orig, int8_t *spin, int32_t n_pad,
                           uint32_t key0, uint32_t key1, uint32_t replica, void *stream);
-int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad,
+int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad, int64_t nnz,
                       const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P,
                       void *stream);
 int gdi_launch_fill_u64(uint64_t *p, int64_t count, void *stream);

@@ -1029,6 +1029,12 @@ __global__ void k_fill_u64(uint64_t *p, int64_t count)
 // counts. Grid-stride over 64-id chunks: a chunk (one wave) never straddles a class
 // because class starts are 64-aligned, so each wave adds its +1 count to one class
 // counter; the three sums are reduced per workgroup in LDS, one atomic each.
+// From-scratch M, doubled weighted cut, doubled crossing count and per-class +1
+// counts. L lanes share a row and read consecutive entries (U per lane in flight), and
+// a wave takes 64 / L consecutive rows, so a wave's entry loads cover one contiguous
+// stretch of the CSR; its rows lie in one 64-id chunk, hence in one class (classes
+// start at multiples of 64).
+template <int L, int U = 4>
 __global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad,
                                                 const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3,
                                                 int32_t *P)
@@ -1045,34 +1051,31 @@ __global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *a
         }
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int sub = lane / L, l = lane % L;
+    constexpr int RPW = 64 / L;  // rows per wave and round
     int64_t m = 0, cw = 0, ce = 0;
-    for (int32_t base = blockIdx.x * blockDim.x; base < n_pad; base += gridDim.x * blockDim.x) {
-        const int32_t v0 = base + (wave << 6);
-        const int32_t v = v0 + lane;
-        int32_t s = 0;
-        if (v < n_pad) {
-            s = spin[v];
-            m += s;
-            // eight entries per round, every load of a round issued before any is used;
-            // entries past the row are not loaded and count for nothing
-            const int32_t r0 = rp[v], r1 = rp[v + 1];
-            for (int32_t k = r0; k < r1; k += 8) {
-                int2 e[8];
+    const int32_t waves = (int32_t)(gridDim.x * (blockDim.x >> 6));
+    for (int32_t v0 = (int32_t)(blockIdx.x * (blockDim.x >> 6) + wave) * RPW; v0 < n_pad; v0 += waves * RPW) {
+        const int32_t v = v0 + sub;  // n_pad is a multiple of 64, so v < n_pad
+        const int32_t s = spin[v];
+        if (l == 0) m += s;
+        const int32_t r0 = rp[v], r1 = rp[v + 1];
+        for (int32_t k = r0 + l; k < r1; k += U * L) {
+            int2 e[U];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) e[u] = k + u < r1 ? adj[k + u] : make_int2(v, 0);
-                int8_t sj[8];
+            for (int u = 0; u < U; ++u) e[u] = k + u * L < r1 ? adj[k + u * L] : make_int2(v, 0);
+            int32_t sj[U];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) sj[u] = spin[e[u].x];
+            for (int u = 0; u < U; ++u) sj[u] = spin[e[u].x];
 #pragma unroll
-                for (int u = 0; u < 8; ++u)
-                    if (k + u < r1 && sj[u] != s) {
-                        cw += e[u].y;
-                        ce += 1;
-                    }
-            }
+            for (int u = 0; u < U; ++u)
+                if (k + u * L < r1 && sj[u] != s) {
+                    cw += e[u].y;
+                    ce += 1;
+                }
         }
-        const int32_t plus = __popcll(__ballot(s > 0));
-        if (lane == 0 && plus && v0 < n_pad) {
+        const int32_t plus = __popcll(__ballot(l == 0 && s > 0));
+        if (lane == 0 && plus) {
             int32_t lo = 0, hi = C - 1;  // class of the chunk: last c with cbeg[c] <= v0
             while (lo < hi) {
                 const int32_t mid = (lo + hi + 1) >> 1;
@@ -1325,13 +1328,25 @@ int gdi_launch_fill_u64(uint64_t *p, int64_t count, void *stream)
     return status(hipGetLastError());
 }
 
-int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad,
+int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad, int64_t nnz,
                       const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P,
                       void *stream)
 {
-    const unsigned grid = (unsigned)std::min<int64_t>(blocks_for(n_pad, 256), 2048);
-    hipLaunchKernelGGL(k_reduce, dim3(grid), dim3(256), 0, (hipStream_t)stream, rp, adj, spin, n_pad, cbeg, csz, C,
-                       out3, P);
+    // lanes per row: about half the mean degree (two entries per lane), 1..32
+    const double avg = n_pad ? (double)nnz / n_pad : 0.0;
+    int L = 1;
+    while (L < 32 && 2.0 * L < avg) L *= 2;
+    const int64_t rows_per_block = 4 * (64 / L);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_pad + rows_per_block - 1) / rows_per_block, 4096));
+    hipStream_t st = (hipStream_t)stream;
+    switch (L) {
+    case 1: hipLaunchKernelGGL(k_reduce<1>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
+    case 2: hipLaunchKernelGGL(k_reduce<2>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
+    case 4: hipLaunchKernelGGL(k_reduce<4>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
+    case 8: hipLaunchKernelGGL(k_reduce<8>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
+    case 16: hipLaunchKernelGGL(k_reduce<16>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
+    default: hipLaunchKernelGGL(k_reduce<32>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
+    }
     return status(hipGetLastError());
 }
 

@@ -493,3 +493,49 @@ def test_bad_schedule_is_rejected(gdi):
         assert e.value.code == gdi.ERANGE
         r = a.anneal(np.ones(3), 1)  # still usable
         assert r["spins"].shape == (g.n,)
+
+
+def _star_plus_matching(n, seed):
+    """One hub joined to every other node plus a random matching: one very long row,
+    many rows of length 1-2 (the cut kernel's lanes per row follow the mean degree)."""
+    rng = np.random.default_rng(seed)
+    hub_a = np.zeros(n - 1, dtype=np.int64)
+    hub_b = np.arange(1, n)
+    perm = rng.permutation(np.arange(1, n))
+    m_a, m_b = perm[0::2][: (n - 1) // 2], perm[1::2][: (n - 1) // 2]
+    a = np.concatenate([hub_a, m_a])
+    b = np.concatenate([hub_b, m_b])
+    w = rng.choice(np.array([-3, -1, 1, 2]), size=a.size)
+    return gs.from_edges(n, a, b, w)
+
+
+@pytest.mark.parametrize("kind", ["path", "star_matching", "rgg8", "er20", "er70"])
+def test_cut_from_scratch_over_row_widths(gdi, oracle_lib, kind):
+    """gdi_cut (k_reduce) against the oracle's count on graphs whose mean degree picks
+    1, 2, 4, 16 and 32 lanes per row, on random states; the allocation-free entry point
+    gives the same three values."""
+    torch = pytest.importorskip("torch")
+    n = 3000
+    if kind == "path":
+        a = np.arange(n - 1)
+        g = gs.from_edges(n, a, a + 1, np.where(a % 3 == 0, -2, 1))
+    elif kind == "star_matching":
+        g = _star_plus_matching(n, 5)
+    elif kind == "rgg8":
+        g = gs.rgg_graph(n, 8.0, 6, "pm1")
+    elif kind == "er20":
+        g = gs.er_graph(n, 20.0 / (n - 1), 7, "pm1")
+    else:
+        g = gs.er_graph(n, 70.0 / (n - 1), 8, "unit")
+    rng = np.random.default_rng(9)
+    print(f"[case] cut {kind} n={g.n} nnz={g.nnz}", flush=True)
+    with gdi.Annealer(g) as a:
+        for rep in range(3):
+            spins = np.where(rng.random(g.n) < (0.2 + 0.3 * rep), 1, -1).astype(np.int8)
+            ref = oracle_lib.cut(g, spins)
+            assert tuple(a.cut(spins)) == ref
+            d_sp = torch.from_numpy(spins).to("cuda:0")
+            d_out = torch.zeros(3, dtype=torch.int64, device="cuda:0")
+            a.cut_dev_noalloc(d_sp.data_ptr(), d_out.data_ptr())
+            torch.cuda.synchronize()
+            assert tuple(int(x) for x in d_out.cpu()) == ref
