@@ -240,9 +240,10 @@ int gdi_cut_dev(gdi_graph *g, const int8_t *d_spins, int64_t *cut_weighted, int6
  * value counts as -1); d_out: device, 3 int64 receiving the weighted cut, the
  * crossing-edge count and M. Stream-ordered on the handle's stream (gdi_set_stream);
  * returns after enqueueing and leaves a pending anneal's outcome untouched. Its scratch
- * (the relabelled spin copy and the reduction's accumulators) lives in one fixed 16 MiB
- * device array per GPU, held until the process ends: graphs with n + 64 * colours <=
- * 16,760,576 and at most 4094 colour classes; GDI_ERANGE otherwise. Every call on one
+ * (the relabelled spin copy, its bit-packed copy and the reduction's accumulators) lives
+ * in one fixed 16 MiB device array per GPU, held until the process ends: graphs with
+ * n + 64 * colours <= 14,897,664 and at most 4094 colour classes; GDI_ERANGE otherwise.
+ * Every call on one
  * GPU uses that GPU's array, so calls that overlap on one GPU (any handle, any stream)
  * race and must be serialised by the caller.
  */

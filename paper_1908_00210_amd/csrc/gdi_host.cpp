@@ -116,6 +116,7 @@ struct gdi_graph {
     DevBuf<uint16_t> d_rp16, d_ent16;
     DevBuf<int2> d_adj;
     DevBuf<int8_t> d_spin, d_io;
+    DevBuf<uint32_t> d_bits;          // bit-packed spins for the from-scratch cut's neighbour reads
     DevBuf<int64_t> d_state, d_red, d_trace;
     DevBuf<uint32_t> d_thr;
     DevBuf<uint64_t> d_bar;
@@ -140,7 +141,7 @@ struct gdi_graph {
     {
         d_rp.release(); d_orig.release(); d_cbeg.release(); d_csz.release(); d_P.release();
         d_rp16.release(); d_ent16.release();
-        d_adj.release(); d_spin.release(); d_io.release(); d_state.release(); d_red.release();
+        d_adj.release(); d_spin.release(); d_io.release(); d_state.release(); d_red.release(); d_bits.release();
         d_trace.release(); d_thr.release(); d_bar.release();
         d_adjL.release(); d_tail_v.release(); d_tail_beg.release(); d_gat_words.release(); d_gat_beg.release();
         d_tail_rp.release(); d_tail_ent.release(); d_ovf.release(); d_flist.release();
@@ -341,6 +342,7 @@ int upload(gdi_graph *g, const int32_t *rp, const int32_t *col, const int32_t *w
     HIP_TRY(g->d_csz.reserve((size_t)g->C), "hipMalloc classes");
     HIP_TRY(g->d_P.reserve((size_t)g->C + 2), "hipMalloc P");
     HIP_TRY(g->d_spin.reserve((size_t)g->n_pad), "hipMalloc spins");
+    HIP_TRY(g->d_bits.reserve((size_t)g->n_pad / 32 + 1), "hipMalloc spins");
     HIP_TRY(g->d_io.reserve((size_t)n), "hipMalloc io");
     HIP_TRY(g->d_state.reserve(8), "hipMalloc state");
     HIP_TRY(g->d_red.reserve(4), "hipMalloc state");
@@ -642,7 +644,7 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_P.p), (g->C + 2) / 2, st);
     if (!rc && trace) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_trace.p), 2 * (int64_t)S, st);
     if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p,
-                                    g->C, g->d_red.p, g->d_P.p, st);
+                                    g->C, g->d_red.p, g->d_P.p, g->d_bits.p, st);
     // the sweep kernels read the initial M from state[0]
     if (!rc) {
         hipError_t e = hipMemcpyAsync(g->d_state.p, g->d_red.p, 8, hipMemcpyDeviceToDevice, st);
@@ -739,7 +741,7 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
         if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_red.p), 4, st);
         if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_P.p), (g->C + 2) / 2, st);
         if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p, g->C,
-                                        g->d_red.p, g->d_P.p, st);
+                                        g->d_red.p, g->d_P.p, g->d_bits.p, st);
         if (!rc) g->last.grid = (uint32_t)grid;
         if (!rc) g->last.block = 1024;
     } else if (r.dense) {
@@ -858,7 +860,7 @@ int cut_impl(gdi_graph *g, const int8_t *spins, bool dev, int64_t *cw, int64_t *
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(red.p), 4, st);
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(P.p), (g->C + 2) / 2, st);
     if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, tmp.p, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p, g->C,
-                                    red.p, P.p, st);
+                                    red.p, P.p, g->d_bits.p, st);
     if (rc) {
         tmp.release(); P.release(); red.release();
         return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
@@ -1859,12 +1861,14 @@ int gdi_cut_dev_noalloc(gdi_graph *g, const int8_t *d_spins, int64_t *d_out)
     int64_t *red = static_cast<int64_t *>(base);
     int32_t *P = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(base) + 256);
     int8_t *sp = reinterpret_cast<int8_t *>(static_cast<unsigned char *>(base) + GDI_NOALLOC_SPIN_OFF);
+    uint32_t *bits = reinterpret_cast<uint32_t *>(static_cast<unsigned char *>(base) + GDI_NOALLOC_SPIN_OFF +
+                                                  (((size_t)g->n_pad + 255) & ~(size_t)255));
     hipStream_t st = g->stream;
     // the accumulators and counts keep the last call's values: cleared by fill kernels
     int rc = gdi_launch_gather_in(g->d_orig.p, d_spins, g->n_pad, sp, st);
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(red), 4, st);
     if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(P), (g->C + 2) / 2, st);
-    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, sp, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p, g->C, red, P, st);
+    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, sp, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p, g->C, red, P, bits, st);
     if (!rc) rc = gdi_launch_cut_finish(red, d_out, st);
     if (rc) return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
     return GDI_OK;

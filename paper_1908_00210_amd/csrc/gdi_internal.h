@@ -163,15 +163,19 @@ struct GdiMlpDev {
 #define GDI_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)  // 16 MiB per GPU
 #define GDI_NOALLOC_MAX_C 4094                         // colour classes
 #define GDI_NOALLOC_SPIN_OFF 16640                     // 256 + 4 (GDI_NOALLOC_MAX_C + 2), 256-aligned
-#define GDI_NOALLOC_MAX_NODES ((int64_t)GDI_NOALLOC_SCRATCH_BYTES - GDI_NOALLOC_SPIN_OFF)  // n_pad limit
+// then the relabelled spins (n_pad bytes, 256-aligned) and their bit-packed copy (n_pad / 8
+// bytes): n_pad + n_pad / 8 must fit in the 16,760,064 bytes after the accumulators and
+// the alignment padding
+#define GDI_NOALLOC_MAX_NODES ((int64_t)14897664)
 #define GDI_NOALLOC_MAX_DEVICES 64
 
 // host-side launchers (gdi_kernels.hip)
 int gdi_launch_init_spins(const int32_t *orig, const int8_t *init_orig, int8_t *spin, int32_t n_pad,
                           uint32_t key0, uint32_t key1, uint32_t replica, void *stream);
+// bits: n_pad / 32 words of scratch for the bit-packed spins the neighbour reads use
 int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad, int64_t nnz,
                       const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P,
-                      void *stream);
+                      uint32_t *bits, void *stream);
 int gdi_launch_fill_u64(uint64_t *p, int64_t count, void *stream);
 int gdi_launch_cut_finish(const int64_t *red, int64_t *out3, void *stream);
 int gdi_scratch_ptr(void **out);

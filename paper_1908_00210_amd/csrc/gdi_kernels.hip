@@ -1029,15 +1029,34 @@ __global__ void k_fill_u64(uint64_t *p, int64_t count)
 // counts. Grid-stride over 64-id chunks: a chunk (one wave) never straddles a class
 // because class starts are 64-aligned, so each wave adds its +1 count to one class
 // counter; the three sums are reduced per workgroup in LDS, one atomic each.
+// Bit-packed copy of the spins for the neighbour reads of k_reduce: bit i of word w is
+// set iff spin 32w + i is +1 (n_pad is a multiple of 64).
+__global__ void k_pack_spins(const int8_t *spin, int32_t words, uint32_t *bits)
+{
+    const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= words) return;
+    const uint4 *p = reinterpret_cast<const uint4 *>(spin + (size_t)w * 32);
+    const uint4 lo = p[0], hi = p[1];
+    const uint32_t x[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    uint32_t word = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) word |= (((int8_t)(x[i] >> (8 * j)) > 0) ? 1u : 0u) << (4 * i + j);
+    bits[w] = word;
+}
+
 // From-scratch M, doubled weighted cut, doubled crossing count and per-class +1
 // counts. L lanes share a row and read consecutive entries (U per lane in flight), and
 // a wave takes 64 / L consecutive rows, so a wave's entry loads cover one contiguous
 // stretch of the CSR; its rows lie in one 64-id chunk, hence in one class (classes
-// start at multiples of 64).
+// start at multiples of 64). A node's own spin comes from the int8 array; its
+// neighbours' from the bit-packed copy (an eighth of the cache lines for the random
+// reads, which dominate the kernel's memory traffic).
 template <int L, int U = 4>
-__global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad,
-                                                const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3,
-                                                int32_t *P)
+__global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin,
+                                                const uint32_t *bits, int32_t n_pad, const int32_t *cbeg,
+                                                const int32_t *csz, int32_t C, int64_t *out3, int32_t *P)
 {
     __shared__ int64_t red[3][4];
     // with few classes, class starts and this block's +1 counts live in LDS (one global
@@ -1064,12 +1083,13 @@ __global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *a
             int2 e[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) e[u] = k + u * L < r1 ? adj[k + u * L] : make_int2(v, 0);
-            int32_t sj[U];
+            uint32_t wj[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) sj[u] = spin[e[u].x];
+            for (int u = 0; u < U; ++u) wj[u] = bits[e[u].x >> 5];
+            // a real neighbour's spin is never 0, so it differs from s iff its bit does
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (k + u * L < r1 && sj[u] != s) {
+                if (k + u * L < r1 && (int32_t)((wj[u] >> (e[u].x & 31)) & 1u) != (s > 0 ? 1 : 0)) {
                     cw += e[u].y;
                     ce += 1;
                 }
@@ -1330,23 +1350,25 @@ int gdi_launch_fill_u64(uint64_t *p, int64_t count, void *stream)
 
 int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad, int64_t nnz,
                       const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P,
-                      void *stream)
+                      uint32_t *bits, void *stream)
 {
-    // lanes per row: about half the mean degree (two entries per lane), 1..32
+    const int32_t words = n_pad / 32;
+    if (words > 0)
+        hipLaunchKernelGGL(k_pack_spins, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, (hipStream_t)stream, spin,
+                           words, bits);
+    // lanes per row: rows in flight matter more than lanes per row (each row is a chain of
+    // row bound, entry and neighbour-spin loads); measured on MI355X over 1..32 lanes:
+    // 2 or 4 best on RGGs of mean degree 8 (1M and 8M nodes) and on an ER graph of mean
+    // degree 40, 16 and 32 up to 3.6x slower
     const double avg = n_pad ? (double)nnz / n_pad : 0.0;
-    int L = 1;
-    while (L < 32 && 2.0 * L < avg) L *= 2;
+    const int L = avg < 12.0 ? 2 : 4;
     const int64_t rows_per_block = 4 * (64 / L);
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_pad + rows_per_block - 1) / rows_per_block, 4096));
     hipStream_t st = (hipStream_t)stream;
-    switch (L) {
-    case 1: hipLaunchKernelGGL(k_reduce<1>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
-    case 2: hipLaunchKernelGGL(k_reduce<2>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
-    case 4: hipLaunchKernelGGL(k_reduce<4>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
-    case 8: hipLaunchKernelGGL(k_reduce<8>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
-    case 16: hipLaunchKernelGGL(k_reduce<16>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
-    default: hipLaunchKernelGGL(k_reduce<32>, dim3(grid), dim3(256), 0, st, rp, adj, spin, n_pad, cbeg, csz, C, out3, P); break;
-    }
+    if (L == 2)
+        hipLaunchKernelGGL(k_reduce<2>, dim3(grid), dim3(256), 0, st, rp, adj, spin, bits, n_pad, cbeg, csz, C, out3, P);
+    else
+        hipLaunchKernelGGL(k_reduce<4>, dim3(grid), dim3(256), 0, st, rp, adj, spin, bits, n_pad, cbeg, csz, C, out3, P);
     return status(hipGetLastError());
 }
 

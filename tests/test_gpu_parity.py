@@ -511,9 +511,10 @@ def _star_plus_matching(n, seed):
 
 @pytest.mark.parametrize("kind", ["path", "star_matching", "rgg8", "er20", "er70"])
 def test_cut_from_scratch_over_row_widths(gdi, oracle_lib, kind):
-    """gdi_cut (k_reduce) against the oracle's count on graphs whose mean degree picks
-    1, 2, 4, 16 and 32 lanes per row, on random states; the allocation-free entry point
-    gives the same three values."""
+    """gdi_cut (k_reduce) against the oracle's count on graphs from mean degree 2 (one
+    long row among short ones, a path) to 70, i.e. with 2 and 4 lanes per row and rows of
+    one to many rounds, on random states; the allocation-free entry point gives the same
+    three values."""
     torch = pytest.importorskip("torch")
     n = 3000
     if kind == "path":
