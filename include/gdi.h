@@ -309,11 +309,13 @@ int gdi_anneal_batch_dev(gdi_instance *inst, uint32_t n_inst, const gdi_schedule
                          const gdi_tuning *tune, double *kernel_ms);
 
 /*
- * gdi_autotune_batch -- time candidate launches (block size, workgroups per CU and
- * lanes per node relative to each graph's mean degree) on the first probe_sweeps
+ * gdi_autotune_batch -- time candidate launches (block size, lanes per node, workgroups
+ * per CU and cluster size, by coordinate descent) on the first probe_sweeps
  * sweeps of the schedule and return the fastest in best (and its time in best_ms).
  * The choice is cached per batch shape and used by gdi_anneal_batch with tune == NULL.
- * Results never depend on the choice. Outputs of inst are not written.
+ * Results never depend on the choice. Outputs of inst are not written. The search also
+ * covers the cluster size of the large instances (tuning.batch_members). Not in the
+ * paper: launch tuning of the batched form above.
  */
 int gdi_autotune_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *s, uint64_t seed,
                        uint32_t probe_sweeps, gdi_tuning *best, double *best_ms);
@@ -329,7 +331,8 @@ int gdi_autotune_batch(gdi_instance *inst, uint32_t n_inst, const gdi_schedule *
  * without timing. Results never depend on the choice. Runs anneals on the handle, so its
  * last result is overwritten. Errors: GDI_ESTATE (NULL handle), GDI_EINVAL (NULL best,
  * bad schedule), GDI_EDEVICE, GDI_ENOMEM, GDI_ETIMEOUT; on an error the handle's tuning
- * is left as it was.
+ * is left as it was. Not in the paper: launch tuning of the sweep that gdi_anneal runs
+ * (Alg. 3 with colour phases, Sec. V).
  */
 int gdi_autotune(gdi_graph *g, const gdi_schedule *s, uint64_t seed, uint32_t probe_sweeps, int use_cache,
                  gdi_tuning *best, double *best_ms);
@@ -350,6 +353,7 @@ int gdi_autotune(gdi_graph *g, const gdi_schedule *s, uint64_t seed, uint32_t pr
  *   rename); GDI_EINVAL (NULL path, cannot write).
  * gdi_tune_cache_clear -- empty the in-memory cache (the file is not touched).
  * gdi_tune_cache_size -- number of entries in the in-memory cache.
+ * Not in the paper (bookkeeping of the launch tuners above).
  */
 int gdi_tune_cache_load(const char *path);
 int gdi_tune_cache_save(const char *path);

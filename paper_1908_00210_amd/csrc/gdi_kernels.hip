@@ -1362,8 +1362,13 @@ int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, in
     // degree 40, 16 and 32 up to 3.6x slower
     const double avg = n_pad ? (double)nnz / n_pad : 0.0;
     const int L = avg < 12.0 ? 2 : 4;
+    // workgroups: one per 4096 padded nodes, between 1024 and 4096, never more than the
+    // rows need; every workgroup ends with a few atomic adds to the same words, so more
+    // workgroups contend (measured on 1M- and 8M-node RGGs: 1024 and 2048 best, 16384 up
+    // to 2.3x slower)
     const int64_t rows_per_block = 4 * (64 / L);
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_pad + rows_per_block - 1) / rows_per_block, 4096));
+    const int64_t want = std::min<int64_t>(4096, std::max<int64_t>(1024, (int64_t)n_pad / 4096));
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_pad + rows_per_block - 1) / rows_per_block, want));
     hipStream_t st = (hipStream_t)stream;
     if (L == 2)
         hipLaunchKernelGGL(k_reduce<2>, dim3(grid), dim3(256), 0, st, rp, adj, spin, bits, n_pad, cbeg, csz, C, out3, P);
