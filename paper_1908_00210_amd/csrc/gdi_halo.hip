@@ -537,6 +537,10 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                 const PhaseView pv = make_view(M, Psh[c], csz_sh[c], a.C, a.n);
                 // wave-uniform trip count so that ballots see whole waves of 64 nodes;
                 // the first pass uses the prefetched rows, later passes load their own
+                // row bounds of this thread's node in the next pass, loaded at the end of
+                // each pass (classes larger than the worker count take several passes)
+                RowAhead rn;
+                rn.r0 = rn.r1 = rn.id = 0;
                 for (int32_t base = e.node_lo; base < e.node_hi; base += nwork) {
                     const int32_t v = base + tid;
                     const bool active = v < e.node_hi;
@@ -545,9 +549,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                     if (active && !masked_out(a, v, t)) {
                         NodePrefetch q;
                         if (base != e.node_lo) {
-                            RowAhead rq;
-                            load_row(a, v, rq);
-                            load_entries(h, rq, t, q);
+                            load_entries(h, rn, t, q);
                         } else {
                             q = pf;
                         }
@@ -578,6 +580,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
                             st_agent(h.words + wd + 1, ((uint64_t)epoch << 32) | lw[1]);
                         }
                     }
+                    if (base + nwork < e.node_hi) load_row(a, min(v + nwork, e.node_hi - 1), rn);
                 }
                 if (lane == 0 && dM != 0) atomicAdd(&wg_acc, dM);
             }
