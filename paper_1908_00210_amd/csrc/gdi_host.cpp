@@ -1478,13 +1478,13 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
     const uint32_t S = s->n_sweeps, t_start = s->start_sweep, k = cfg->k_full;
     DevBuf<int32_t> lf;
     DevBuf<uint32_t> mask;
-    DevBuf<uint64_t> X, skipped;
+    DevBuf<uint64_t> skipped;
     DevBuf<GdiActiveRec> rec;
     MlpDevice net;
     struct Rel {
-        DevBuf<int32_t> &a; DevBuf<uint32_t> &b; DevBuf<uint64_t> &c, &d; DevBuf<GdiActiveRec> &e;
-        ~Rel() { a.release(); b.release(); c.release(); d.release(); e.release(); }
-    } rel{lf, mask, X, skipped, rec};
+        DevBuf<int32_t> &a; DevBuf<uint32_t> &b; DevBuf<uint64_t> &d; DevBuf<GdiActiveRec> &e;
+        ~Rel() { a.release(); b.release(); d.release(); e.release(); }
+    } rel{lf, mask, skipped, rec};
     // masked sweeps with few active nodes: one workgroup over the active set, if every
     // spin fits its LDS as a bit
     int dev = 0, lds_max = 0;
@@ -1505,8 +1505,6 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
     if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
     float thr_logit = 0.0f;
     if (cfg->skip_mode == GDI_SKIP_MLP) {
-        HIP_TRY(X.reserve((size_t)g->n_pad * 2), "hipMalloc features");
-        if ((e = gdi_launch_fill_u64(X.p, (int64_t)g->n_pad * 2, st))) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
         if ((rc = upload_mlp(w, net, st))) return rc;
         thr_logit = std::log(cfg->skip_threshold / (1.0f - cfg->skip_threshold));
     }
@@ -1530,17 +1528,19 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
         // next block's full sweep
         const uint32_t t_next = merged ? std::min<uint32_t>(end + 1, S) : end;
         const uint32_t *mp = nullptr;
-        if (cfg->skip_mode == GDI_SKIP_MLP) {
-            e = gdi_launch_features(g->d_rp.p, g->d_adj.p, g->d_spin.p, lf.p, g->n_pad, g->d_state.p,
-                                    (float)s->temps[b], (int32_t)b, s->A, s->B, g->d_orig.p, X.p, -1, 0, st);
-            if (!e) e = gdi_launch_mlp_infer(X.p, g->n_pad, net.packed.p, thr_logit, mask.p, nullptr, st);
+        if (cfg->skip_mode != GDI_SKIP_NONE) {
             mp = mask.p;
-        } else if (cfg->skip_mode == GDI_SKIP_HEURISTIC) {
-            e = gdi_launch_mask_heuristic(lf.p, g->n_pad, (int32_t)b, (int32_t)cfg->heuristic_k, mask.p, st);
-            mp = mask.p;
+            e = gdi_launch_fill_u64(skipped.p + 1, 1, st);
         }
-        if (!e && mp) e = gdi_launch_fill_u64(skipped.p + 1, 1, st);
-        if (!e && mp) e = gdi_launch_mask_finish(mask.p, g->d_orig.p, g->n_pad, skipped.p, end - b - 1, skipped.p + 1, st);
+        if (!e && cfg->skip_mode == GDI_SKIP_MLP) {
+            // features, network and mask (with its counts) in one kernel
+            e = gdi_launch_mlp_mask(g->d_rp.p, g->d_adj.p, g->d_spin.p, lf.p, g->n_pad, g->d_state.p,
+                                    (float)s->temps[b], (int32_t)b, s->A, s->B, g->d_orig.p, net.packed.p, thr_logit,
+                                    mask.p, skipped.p, end - b - 1, skipped.p + 1, st);
+        } else if (!e && cfg->skip_mode == GDI_SKIP_HEURISTIC) {
+            e = gdi_launch_mask_heuristic(lf.p, g->n_pad, (int32_t)b, (int32_t)cfg->heuristic_k, mask.p, st);
+            if (!e) e = gdi_launch_mask_finish(mask.p, g->d_orig.p, g->n_pad, skipped.p, end - b - 1, skipped.p + 1, st);
+        }
         if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
         if (cfg->mask_trace) {
             const size_t words = (size_t)g->n_pad / 32;

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 
 #include "gdi_internal.h"
 
@@ -56,6 +57,20 @@ __device__ __forceinline__ void wave_lds_sync()
 //   f3 = clamp(B s h / T, -16, 16) / 4 (local field in units of T, positive = stable),
 //   f4 = min(|4A(1 - s M)| / T, 64) / 16 (balance cost of a flip in units of T),
 //   f5 = min(t - last_flip, 255) / 64 (sweeps since the last flip).
+// The six features of one node from its row sums (FP32; the callers round them to BF16).
+__device__ __forceinline__ void node_features(int32_t deg, int32_t wabs, int32_t other, int32_t h, int32_t s,
+                                              int32_t M, float T, int32_t t, int32_t A, int32_t B, int32_t lf,
+                                              float f[6])
+{
+    f[0] = deg / 16.0f;
+    f[1] = wabs / 16.0f;
+    f[2] = deg ? (float)other / (float)deg : 0.0f;
+    f[3] = fminf(fmaxf((float)(B * s * h) / T, -16.0f), 16.0f) / 4.0f;
+    const int32_t bal = 4 * A * (1 - s * M);
+    f[4] = fminf(fabsf((float)bal) / T, 64.0f) / 16.0f;
+    f[5] = (float)min(t - lf, 255) / 64.0f;
+}
+
 __global__ void k_features(const int32_t *rp, const int2 *adj, const int8_t *spin, const int32_t *last_flip,
                            int32_t n_pad, const int64_t *state, float T, int32_t t, int32_t A, int32_t B,
                            const int32_t *orig, __bf16 *X, int32_t x_stride_rows, int64_t x_base)
@@ -87,13 +102,7 @@ __global__ void k_features(const int32_t *rp, const int2 *adj, const int8_t *spi
             }
     }
     float f[8];
-    f[0] = deg / 16.0f;
-    f[1] = wabs / 16.0f;
-    f[2] = deg ? (float)other / (float)deg : 0.0f;
-    f[3] = fminf(fmaxf((float)(B * s * h) / T, -16.0f), 16.0f) / 4.0f;
-    const int32_t bal = 4 * A * (1 - s * M);
-    f[4] = fminf(fabsf((float)bal) / T, 64.0f) / 16.0f;
-    f[5] = (float)min(t - last_flip[v], 255) / 64.0f;
+    node_features(deg, wabs, other, h, s, M, T, t, A, B, last_flip[v], f);
     f[6] = 0.0f;
     f[7] = 0.0f;
     // x_stride_rows < 0: row = new id (inference); otherwise row = x_base + original id (dataset)
@@ -158,22 +167,45 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t value)
 }
 
 // ------------------------------------------------------------------ MLP parameters
-struct MlpLds {
-    __bf16 w1t[64 * 16];
-    __bf16 w2t[64 * 64];
-    float b1[64], b2[64], w3[64], b3;
+// LDS copy of the parameters. The weight rows are padded (W1 rows to 24 values, W2 rows
+// to 72) so that the 16 rows a lane group reads at once fall into distinct LDS banks;
+// unpadded 128-byte W2 rows put all of them into one bank.
+constexpr int kW1S = 24, kW2S = 72;
+struct __align__(16) MlpLds {
+    __bf16 w1t[64 * kW1S];
+    __bf16 w2t[64 * kW2S];
+    float b1[64], b2[64], w3[64], b3, pad[3];
 };
+static_assert(sizeof(GdiMlpDev) == 11024, "device parameter layout");
+static_assert(offsetof(MlpLds, b1) == 64 * (kW1S + kW2S) * 2, "LDS parameter layout");
 
+// Copies the parameters in 16-byte pieces: 128 of W1 (two per row), 512 of W2 (eight per
+// row), 49 of the biases and output weights, which follow in the same order in both
+// layouts. A thread issues all of its loads before its stores; workgroups of 256 threads.
 __device__ void load_params(const GdiMlpDev *p, MlpLds *m)
 {
-    for (int i = threadIdx.x; i < 64 * 16; i += blockDim.x) m->w1t[i] = p->w1t[i];
-    for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) m->w2t[i] = p->w2t[i];
-    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
-        m->b1[i] = p->b1[i];
-        m->b2[i] = p->b2[i];
-        m->w3[i] = p->w3[i];
+    constexpr int kPieces = 128 + 512 + 49, kMaxPer = 3;
+    const uint4 *src = reinterpret_cast<const uint4 *>(p);
+    char *dst = reinterpret_cast<char *>(m);
+    uint4 val[kMaxPer];
+    int off[kMaxPer];
+#pragma unroll
+    for (int j = 0; j < kMaxPer; ++j) {
+        const int c = threadIdx.x + j * 256;
+        off[j] = -1;
+        if (c < kPieces && threadIdx.x < 256) {
+            val[j] = src[c];
+            if (c < 128)
+                off[j] = (c >> 1) * kW1S * 2 + (c & 1) * 16;
+            else if (c < 640)
+                off[j] = (int)offsetof(MlpLds, w2t) + ((c - 128) >> 3) * kW2S * 2 + ((c - 128) & 7) * 16;
+            else
+                off[j] = (int)offsetof(MlpLds, b1) + (c - 640) * 16;
+        }
     }
-    if (threadIdx.x == 0) m->b3 = p->b3;
+#pragma unroll
+    for (int j = 0; j < kMaxPer; ++j)
+        if (off[j] >= 0) *reinterpret_cast<uint4 *>(dst + off[j]) = val[j];
     __syncthreads();
 }
 
@@ -202,9 +234,9 @@ __device__ __forceinline__ void tile_forward(const MlpLds *m, bf16x4 xb, int g, 
     }
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
-        bf16x8 a;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) a[j] = g == 0 ? m->w1t[(16 * mb + r) * 16 + j] : (__bf16)0.0f;
+        // one 16-byte read of row 16 mb + r (rows are 48 bytes apart), zero for g > 0
+        bf16x8 a = *reinterpret_cast<const bf16x8 *>(&m->w1t[(16 * mb + r) * kW1S]);
+        if (g != 0) a = bf16x8{};
         const floatx4 acc = mfma32(a, x8, floatx4{0.f, 0.f, 0.f, 0.f});
 #pragma unroll
         for (int i = 0; i < 4; ++i) o.h1[mb][i] = (__bf16)fmaxf(acc[i] + m->b1[16 * mb + 4 * g + i], 0.0f);
@@ -215,11 +247,15 @@ __device__ __forceinline__ void tile_forward(const MlpLds *m, bf16x4 xb, int g, 
         floatx4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
+            // two 8-byte reads (row offsets are multiples of four values)
+            const __bf16 *row = &m->w2t[(16 * mo + r) * kW2S + 32 * q + 4 * g];
+            const bf16x4 alo = *reinterpret_cast<const bf16x4 *>(row);
+            const bf16x4 ahi = *reinterpret_cast<const bf16x4 *>(row + 16);
             bf16x8 a, b;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                a[j] = m->w2t[(16 * mo + r) * 64 + 32 * q + 4 * g + j];
-                a[4 + j] = m->w2t[(16 * mo + r) * 64 + 32 * q + 16 + 4 * g + j];
+                a[j] = alo[j];
+                a[4 + j] = ahi[j];
                 b[j] = o.h1[2 * q][j];
                 b[4 + j] = o.h1[2 * q + 1][j];
             }
@@ -271,6 +307,132 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const __bf16 *X, int32_t coun
             bits |= (uint32_t)(b & 0xFFFFu) << (16 * half);
         }
         if (lane == 0 && mask) mask[w] = bits;
+    }
+}
+
+// Per-node values a row scan starts from: original id, spin, row bounds, last flip.
+struct NodeHead {
+    int32_t o, s, r0, r1, lf;
+};
+
+__device__ __forceinline__ NodeHead load_head(const int32_t *rp, const int8_t *spin, const int32_t *last_flip,
+                                              const int32_t *orig, int32_t n_pad, int32_t v)
+{
+    NodeHead x{-1, 0, 0, 0, 0};
+    if (v < n_pad) {
+        x.o = orig[v];
+        x.s = spin[v];
+        x.r0 = rp[v];
+        x.r1 = rp[v + 1];
+        x.lf = last_flip[v];
+    }
+    return x;
+}
+
+// The proposal's mask for one block in one pass (what k_features, k_mlp_infer and
+// k_mask_finish compute in turn, without the feature rows in memory). A wave takes a
+// mask word, two 16-node tiles: the four lanes of a node (r, r + 16, r + 32, r + 48)
+// split both tiles' row scans, which run in one loop so that their loads overlap, and
+// then hold the node's features for the tile's network. The next word's row bounds are
+// loaded before the network runs. The mask bit is set for real ids whose logit exceeds
+// thr_logit; the skipped nodes are counted into block_skips and, times weight, into
+// skipped, one pair of atomics per workgroup.
+__global__ void __launch_bounds__(256) k_mlp_mask(const int32_t *rp, const int2 *adj, const int8_t *spin,
+                                                   const int32_t *last_flip, int32_t n_pad, const int64_t *state,
+                                                   float T, int32_t t, int32_t A, int32_t B, const int32_t *orig,
+                                                   const GdiMlpDev *p, float thr_logit, uint32_t *mask,
+                                                   unsigned long long *skipped, uint32_t weight,
+                                                   unsigned long long *block_skips)
+{
+    __shared__ MlpLds m;
+    __shared__ unsigned long long cnt_s[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int64_t words = ((int64_t)n_pad + 31) / 32;
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    int64_t w = (int64_t)blockIdx.x * 4 + wave;
+    NodeHead hd[2];
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf)
+        hd[hf] = load_head(rp, spin, last_flip, orig, n_pad, (int32_t)(w * 32 + 16 * hf + r));
+    load_params(p, &m);
+    const int32_t M = (int32_t)state[0];
+    unsigned long long cnt = 0;
+    for (; w < words; w += stride) {
+        // this lane's entries g, g + 4, ... of both rows, four per row and round (a row of
+        // up to 16 entries in one round), every load of a round issued before any is used
+        int32_t wabs[2] = {0, 0}, other[2] = {0, 0}, h[2] = {0, 0};
+        const int32_t deg0 = hd[0].r1 - hd[0].r0, deg1 = hd[1].r1 - hd[1].r0;
+        const int32_t dmax = max(deg0, deg1);
+        for (int32_t j = g; j < dmax; j += 16) {
+            int2 e[2][4];
+            int32_t sj[2][4];
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    e[hf][u] = j + 4 * u < hd[hf].r1 - hd[hf].r0 ? adj[hd[hf].r0 + j + 4 * u] : make_int2(0, 0);
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sj[hf][u] = spin[e[hf][u].x];
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (j + 4 * u < hd[hf].r1 - hd[hf].r0) {
+                        wabs[hf] += e[hf][u].y < 0 ? -e[hf][u].y : e[hf][u].y;
+                        other[hf] += sj[hf][u] != hd[hf].s;
+                        h[hf] += e[hf][u].y * sj[hf][u];
+                    }
+        }
+        bf16x4 xb[2];
+        bool real[2];
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+#pragma unroll
+            for (int off = 16; off < 64; off <<= 1) {
+                wabs[hf] += __shfl_xor(wabs[hf], off, 64);
+                other[hf] += __shfl_xor(other[hf], off, 64);
+                h[hf] += __shfl_xor(h[hf], off, 64);
+            }
+            float f[6];
+            node_features(hd[hf].r1 - hd[hf].r0, wabs[hf], other[hf], h[hf], hd[hf].s, M, T, t, A, B, hd[hf].lf, f);
+            real[hf] = hd[hf].o >= 0;
+            // B operand of layer 1: features 4g .. 4g + 3 (zero past feature 5 and for padding)
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int fi = 4 * g + jj;
+                xb[hf][jj] = (real[hf] && fi < 6) ? (__bf16)(fi < 4 ? f[fi & 3] : f[4 + (fi & 1)]) : (__bf16)0.0f;
+            }
+        }
+        const int64_t wn = w + stride;
+        if (wn < words) {
+#pragma unroll
+            for (int hf = 0; hf < 2; ++hf)
+                hd[hf] = load_head(rp, spin, last_flip, orig, n_pad, (int32_t)(wn * 32 + 16 * hf + r));
+        }
+        uint32_t bits = 0;
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+            TileFwd tf;
+            tile_forward(&m, xb[hf], g, r, tf);
+            const uint64_t b = __ballot(g == 0 && real[hf] && tf.z > thr_logit);
+            bits |= (uint32_t)(b & 0xFFFFu) << (16 * hf);
+        }
+        if (lane == 0) {
+            mask[w] = bits;
+            cnt += (unsigned long long)__popc(bits);
+        }
+    }
+    if (lane == 0) cnt_s[wave] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long c = cnt_s[0] + cnt_s[1] + cnt_s[2] + cnt_s[3];
+        if (c) {
+            atomicAdd(skipped, c * weight);
+            atomicAdd(block_skips, c);
+        }
     }
 }
 
@@ -360,7 +522,7 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const __bf16 *X, const uint8_t
             for (int mo = 0; mo < 4; ++mo) {
                 bf16x4 a;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) a[j] = m.w2t[(16 * mo + 4 * g + j) * 64 + 16 * kb + r];
+                for (int j = 0; j < 4; ++j) a[j] = m.w2t[(16 * mo + 4 * g + j) * kW2S + 16 * kb + r];
                 acc = mfma16(a, dp2b[mo], acc);
             }
 #pragma unroll
@@ -521,6 +683,29 @@ int gdi_launch_mlp_infer(const void *X, int32_t count, const GdiMlpDev *p, float
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((words + 3) / 4, 4096));
     hipLaunchKernelGGL(k_mlp_infer, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const __bf16 *)X, count, p,
                        thr_logit, mask, logits);
+    return (int)hipGetLastError();
+}
+
+int gdi_launch_mlp_mask(const int32_t *rp, const int2 *adj, const int8_t *spin, const int32_t *last_flip,
+                        int32_t n_pad, const int64_t *state, float T, int32_t t, int32_t A, int32_t B,
+                        const int32_t *orig, const GdiMlpDev *p, float thr_logit, uint32_t *mask, uint64_t *skipped,
+                        uint32_t weight, uint64_t *block_skips, void *stream)
+{
+    const int64_t words = ((int64_t)n_pad + 31) / 32;
+    // no more workgroups than fit on the device at once: the parameters are copied to LDS
+    // once per workgroup, and a wave takes further words in turn
+    static const int64_t resident = [] {
+        int dev = 0, cus = 0, per_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mlp_mask, 256, 0) != hipSuccess)
+            return (int64_t)1024;
+        return (int64_t)std::max(1, cus) * std::max(1, per_cu);
+    }();
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((words + 3) / 4, resident));
+    hipLaunchKernelGGL(k_mlp_mask, dim3(grid), dim3(256), 0, (hipStream_t)stream, rp, adj, spin, last_flip, n_pad,
+                       state, T, t, A, B, orig, p, thr_logit, mask, (unsigned long long *)skipped, weight,
+                       (unsigned long long *)block_skips);
     return (int)hipGetLastError();
 }
 
