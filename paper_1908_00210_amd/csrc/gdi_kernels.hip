@@ -394,12 +394,42 @@ __device__ __forceinline__ int32_t class_of(const int32_t *cbeg, int32_t C, int3
 }
 
 // ------------------------------------------------------------------ active-set sweeps
+// Bit i set iff byte i of q (sixteen int8 spins, +1 or -1) is positive: per 32-bit part,
+// the bytes' inverted sign bits gathered into a nibble by one multiply (the partial
+// products of the four bits meet in the top byte without carries).
+__device__ __forceinline__ uint32_t plus_bits16(uint4 q)
+{
+    const uint32_t x[4] = {q.x, q.y, q.z, q.w};
+    uint32_t r = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t y = (~x[i] >> 7) & 0x01010101u;
+        r |= ((y * 0x01020408u) >> 24) << (4 * i);
+    }
+    return r;
+}
+
+// Active ids of the 64-id chunk ch (first id v0) of a class ending at cend: real ids
+// whose mask bit is clear.
+__device__ __forceinline__ uint64_t active_chunk(const GdiSweepArgs &a, int32_t ch, int32_t v0, int32_t cend)
+{
+    const int32_t nv = min(64, max(0, cend - v0));
+    const uint64_t valid = nv == 64 ? ~0ull : ((1ull << nv) - 1ull);
+    const uint64_t m = a.mask ? reinterpret_cast<const uint64_t *>(a.mask)[ch] : 0ull;
+    return valid & ~m;
+}
+
 // Masked sweeps of the learned proposal in one workgroup when few nodes are active:
 // every spin of the graph is one bit in LDS (so neighbour reads never leave the CU),
 // the active nodes (mask bit clear, real ids) are compacted at the start into
 // records {new id, row, original id} in class order, and a class with no active node
 // takes no phase at all -- nothing in it can change, so M and the class counts stay.
 // The decisions are those of the full-graph kernels with the mask applied.
+// Set-up in two passes over the graph: the spins become bits with 16-byte loads (32 ids
+// per word, four words per thread in flight), and the compaction gives each thread a run
+// of consecutive 64-id chunks (records in id order, which is class order), counts its
+// active ids, takes its first record's position from one workgroup scan and writes its
+// records; class starts are multiples of 64, so a chunk lies in one class.
 __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_active(GdiSweepArgs a, GdiActiveRec *rec)
 {
     if (!gate_open(a)) return;
@@ -408,66 +438,85 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_active(GdiSweepArgs a, 
     uint32_t *bits = lds;                                           // n_pad spin bits (1 = +1)
     int32_t *abeg = reinterpret_cast<int32_t *>(lds + nw);          // C + 1 record offsets
     int32_t *Psh = abeg + a.C + 1;                                  // C counts of +1
+    int32_t *cb_s = Psh + a.C;                                      // C class starts, then n_pad
+    int32_t *cs_s = cb_s + a.C + 1;                                 // C class sizes
     __shared__ int32_t acc[3];
     __shared__ int32_t wtot[GDI_MAX_BLOCK / 64];
-    __shared__ int32_t base_sh;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int lane = tid & 63, wave = tid >> 6, nwaves = nth >> 6;
 
-    // spins -> bits, 64 ids per wave step (n_pad is a multiple of 64)
-    for (int32_t b0 = wave * 64; b0 < a.n_pad; b0 += nwaves * 64) {
-        const uint64_t b = __ballot(a.spin[b0 + lane] > 0);
-        if (lane == 0) {
-            bits[b0 >> 5] = (uint32_t)b;
-            bits[(b0 >> 5) + 1] = (uint32_t)(b >> 32);
+    // spins -> bits (n_pad is a multiple of 64; the spin array is 16-byte aligned)
+    const uint4 *sp4 = reinterpret_cast<const uint4 *>(a.spin);
+    for (int32_t w0 = tid; w0 < nw; w0 += 4 * nth) {
+        uint4 q[4][2] = {};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t wd = w0 + u * nth;
+            if (wd < nw) {
+                q[u][0] = sp4[2 * wd];
+                q[u][1] = sp4[2 * wd + 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t wd = w0 + u * nth;
+            if (wd < nw) bits[wd] = plus_bits16(q[u][0]) | (plus_bits16(q[u][1]) << 16);
         }
     }
-    for (int i = tid; i < a.C; i += nth) Psh[i] = a.P[i];
+    for (int i = tid; i < a.C; i += nth) {
+        Psh[i] = a.P[i];
+        cb_s[i] = a.cbeg[i];
+        cs_s[i] = a.csz[i];
+    }
+    if (tid == 0) cb_s[a.C] = a.n_pad;
     if (tid < 3) acc[tid] = 0;
-    if (tid == 0) base_sh = 0;
     int32_t M = (int32_t)a.state[0];
     __syncthreads();
 
-    // compaction: one 64-id chunk per thread per round; chunks never straddle classes
+    // compaction: thread tid takes the chunks [ch0, ch1)
     const int32_t nch = a.n_pad >> 6;
-    for (int32_t r0 = 0; r0 < nch; r0 += nth) {
-        const int32_t ch = r0 + tid;
-        uint64_t act = 0;
-        int32_t c = -1;
-        if (ch < nch) {
-            const int32_t v0 = ch << 6;
-            c = class_of(a.cbeg, a.C, v0);
-            const int32_t nv = min(64, max(0, a.cbeg[c] + a.csz[c] - v0));
-            const uint64_t valid = nv == 64 ? ~0ull : ((1ull << nv) - 1ull);
-            const uint64_t m = a.mask ? ((uint64_t)a.mask[2 * ch] | ((uint64_t)a.mask[2 * ch + 1] << 32)) : 0ull;
-            act = valid & ~m;
-            if (v0 != a.cbeg[c]) c = -1;  // c >= 0 only on the first chunk of a class
+    const int32_t per = (nch + nth - 1) / nth;
+    const int32_t ch0 = min(nch, tid * per), ch1 = min(nch, ch0 + per);
+    int32_t c0 = 0;  // class of chunk ch0: the last c with cb_s[c] <= its first id
+    {
+        int32_t lo = 0, hi = a.C - 1;
+        const int32_t v0 = ch0 << 6;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (cb_s[mid] <= v0) lo = mid; else hi = mid - 1;
         }
-        const int32_t cnt = __popcll(act);
-        int32_t incl = cnt;
+        c0 = lo;
+    }
+    int32_t cnt = 0;
+    for (int32_t ch = ch0, c = c0; ch < ch1; ++ch) {
+        const int32_t v0 = ch << 6;
+        while (cb_s[c + 1] <= v0) ++c;  // cb_s[C] = n_pad ends it
+        cnt += __popcll(active_chunk(a, ch, v0, cb_s[c] + cs_s[c]));
+    }
+    int32_t incl = cnt;
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int32_t y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
-        }
-        if (lane == 63) wtot[wave] = incl;
-        __syncthreads();
-        int32_t before = 0, round_total = 0;
-        for (int w = 0; w < nwaves; ++w) {
-            before += w < wave ? wtot[w] : 0;
-            round_total += wtot[w];
-        }
-        int32_t pos = base_sh + before + incl - cnt;
-        if (c >= 0) abeg[c] = pos;
-        for (uint64_t x = act; x; x &= x - 1) {
-            const int32_t v = (ch << 6) + __ffsll((unsigned long long)x) - 1;
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    int32_t before = 0, total = 0;
+    for (int w = 0; w < nwaves; ++w) {
+        before += w < wave ? wtot[w] : 0;
+        total += wtot[w];
+    }
+    int32_t pos = before + incl - cnt;
+    for (int32_t ch = ch0, c = c0; ch < ch1; ++ch) {
+        const int32_t v0 = ch << 6;
+        while (cb_s[c + 1] <= v0) ++c;
+        if (v0 == cb_s[c]) abeg[c] = pos;
+        for (uint64_t x = active_chunk(a, ch, v0, cb_s[c] + cs_s[c]); x; x &= x - 1) {
+            const int32_t v = v0 + __ffsll((unsigned long long)x) - 1;
             rec[pos++] = GdiActiveRec{v, a.rp[v], a.rp[v + 1], a.orig[v]};
         }
-        __syncthreads();
-        if (tid == 0) base_sh += round_total;
-        __syncthreads();
     }
-    if (tid == 0) abeg[a.C] = base_sh;
+    if (tid == 0) abeg[a.C] = total;
     __syncthreads();
 
     int64_t dcut = 0;
@@ -1499,12 +1548,14 @@ int gdi_launch_sweep_wgl(const GdiSweepArgs &a, const uint16_t *rp16, const uint
 
 int gdi_active_lds_bytes(int32_t n_pad, int32_t C)
 {
-    return (n_pad / 32) * 4 + (2 * C + 1) * 4;
+    return (n_pad / 32) * 4 + (4 * C + 2) * 4;
 }
 
 int gdi_launch_sweep_active(const GdiSweepArgs &a, GdiActiveRec *rec, void *stream)
 {
     const void *f = (const void *)k_sweep_active;
+    if ((a.n_pad & 63) || (reinterpret_cast<uintptr_t>(a.spin) & 15) || (reinterpret_cast<uintptr_t>(a.mask) & 7))
+        return (int)hipErrorInvalidValue;
     const int lds = gdi_active_lds_bytes(a.n_pad, a.C);
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return status(e);
