@@ -1477,14 +1477,15 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
     hipStream_t st = g->stream;
     const uint32_t S = s->n_sweeps, t_start = s->start_sweep, k = cfg->k_full;
     DevBuf<int32_t> lf;
-    DevBuf<uint32_t> mask;
+    DevBuf<uint32_t> mask, part;
     DevBuf<uint64_t> skipped;
     DevBuf<GdiActiveRec> rec;
     MlpDevice net;
     struct Rel {
-        DevBuf<int32_t> &a; DevBuf<uint32_t> &b; DevBuf<uint64_t> &d; DevBuf<GdiActiveRec> &e;
-        ~Rel() { a.release(); b.release(); d.release(); e.release(); }
-    } rel{lf, mask, skipped, rec};
+        DevBuf<int32_t> &a; DevBuf<uint32_t> &b, &c; DevBuf<uint64_t> &d; DevBuf<GdiActiveRec> &e;
+        ~Rel() { a.release(); b.release(); c.release(); d.release(); e.release(); }
+    } rel{lf, mask, part, skipped, rec};
+    const int32_t kParts = 4096;  // workgroup counts of the network's mask kernel
     // masked sweeps with few active nodes: one workgroup over the active set, if every
     // spin fits its LDS as a bit
     int dev = 0, lds_max = 0;
@@ -1505,6 +1506,7 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
     if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
     float thr_logit = 0.0f;
     if (cfg->skip_mode == GDI_SKIP_MLP) {
+        HIP_TRY(part.reserve((size_t)kParts), "hipMalloc learned");
         if ((rc = upload_mlp(w, net, st))) return rc;
         thr_logit = std::log(cfg->skip_threshold / (1.0f - cfg->skip_threshold));
     }
@@ -1527,18 +1529,15 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
         // the sweeps this block's launch on the grid sweep runs: the masked ones, then the
         // next block's full sweep
         const uint32_t t_next = merged ? std::min<uint32_t>(end + 1, S) : end;
-        const uint32_t *mp = nullptr;
-        if (cfg->skip_mode != GDI_SKIP_NONE) {
-            mp = mask.p;
-            e = gdi_launch_fill_u64(skipped.p + 1, 1, st);
-        }
-        if (!e && cfg->skip_mode == GDI_SKIP_MLP) {
-            // features, network and mask (with its counts) in one kernel
+        const uint32_t *mp = cfg->skip_mode != GDI_SKIP_NONE ? mask.p : nullptr;
+        if (cfg->skip_mode == GDI_SKIP_MLP) {
+            // features, network and mask in one kernel, then the block's counts
             e = gdi_launch_mlp_mask(g->d_rp.p, g->d_adj.p, g->d_spin.p, lf.p, g->n_pad, g->d_state.p,
                                     (float)s->temps[b], (int32_t)b, s->A, s->B, g->d_orig.p, net.packed.p, thr_logit,
-                                    mask.p, skipped.p, end - b - 1, skipped.p + 1, st);
-        } else if (!e && cfg->skip_mode == GDI_SKIP_HEURISTIC) {
-            e = gdi_launch_mask_heuristic(lf.p, g->n_pad, (int32_t)b, (int32_t)cfg->heuristic_k, mask.p, st);
+                                    mask.p, part.p, kParts, skipped.p, end - b - 1, skipped.p + 1, st);
+        } else if (cfg->skip_mode == GDI_SKIP_HEURISTIC) {
+            e = gdi_launch_fill_u64(skipped.p + 1, 1, st);
+            if (!e) e = gdi_launch_mask_heuristic(lf.p, g->n_pad, (int32_t)b, (int32_t)cfg->heuristic_k, mask.p, st);
             if (!e) e = gdi_launch_mask_finish(mask.p, g->d_orig.p, g->n_pad, skipped.p, end - b - 1, skipped.p + 1, st);
         }
         if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));

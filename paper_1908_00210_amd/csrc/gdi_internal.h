@@ -214,11 +214,13 @@ int gdi_launch_mask_heuristic(const int32_t *last_flip, int32_t n_pad, int32_t t
 int gdi_launch_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad, uint64_t *skipped, uint32_t weight,
                            uint64_t *block_skips, void *stream);
 int gdi_launch_fill_i32(int32_t *p, int64_t n, int32_t value, void *stream);
-// Features, network and mask of one proposal block in one launch (k_mlp_mask).
+// Features, network and mask of one proposal block (k_mlp_mask), then its count of skipped
+// nodes into *block_skips (set) and, times weight, into *skipped (added) (k_sum_counts);
+// part: scratch of part_cap >= 1 workgroup counts.
 int gdi_launch_mlp_mask(const int32_t *rp, const int2 *adj, const int8_t *spin, const int32_t *last_flip,
                         int32_t n_pad, const int64_t *state, float T, int32_t t, int32_t A, int32_t B,
-                        const int32_t *orig, const GdiMlpDev *p, float thr_logit, uint32_t *mask, uint64_t *skipped,
-                        uint32_t weight, uint64_t *block_skips, void *stream);
+                        const int32_t *orig, const GdiMlpDev *p, float thr_logit, uint32_t *mask, uint32_t *part,
+                        int32_t part_cap, uint64_t *skipped, uint32_t weight, uint64_t *block_skips, void *stream);
 int gdi_launch_mlp_infer(const void *X, int32_t count, const GdiMlpDev *p, float thr_logit, uint32_t *mask,
                          float *logits, void *stream);
 int gdi_launch_mlp_grad(const void *X, const uint8_t *Y, const int32_t *idx, int32_t count, const GdiMlpDev *p,

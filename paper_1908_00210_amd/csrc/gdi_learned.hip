@@ -181,31 +181,26 @@ static_assert(offsetof(MlpLds, b1) == 64 * (kW1S + kW2S) * 2, "LDS parameter lay
 
 // Copies the parameters in 16-byte pieces: 128 of W1 (two per row), 512 of W2 (eight per
 // row), 49 of the biases and output weights, which follow in the same order in both
-// layouts. A thread issues all of its loads before its stores; workgroups of 256 threads.
+// layouts. Workgroups of 256 threads: thread i copies pieces i, i + 256 and i + 512
+// (if below 689), all three loads issued before the stores.
+__device__ __forceinline__ int param_piece_offset(int c)
+{
+    if (c < 128) return (c >> 1) * kW1S * 2 + (c & 1) * 16;
+    if (c < 640) return (int)offsetof(MlpLds, w2t) + ((c - 128) >> 3) * kW2S * 2 + ((c - 128) & 7) * 16;
+    return (int)offsetof(MlpLds, b1) + (c - 640) * 16;
+}
+
 __device__ void load_params(const GdiMlpDev *p, MlpLds *m)
 {
-    constexpr int kPieces = 128 + 512 + 49, kMaxPer = 3;
+    constexpr int kPieces = 128 + 512 + 49;
     const uint4 *src = reinterpret_cast<const uint4 *>(p);
     char *dst = reinterpret_cast<char *>(m);
-    uint4 val[kMaxPer];
-    int off[kMaxPer];
-#pragma unroll
-    for (int j = 0; j < kMaxPer; ++j) {
-        const int c = threadIdx.x + j * 256;
-        off[j] = -1;
-        if (c < kPieces && threadIdx.x < 256) {
-            val[j] = src[c];
-            if (c < 128)
-                off[j] = (c >> 1) * kW1S * 2 + (c & 1) * 16;
-            else if (c < 640)
-                off[j] = (int)offsetof(MlpLds, w2t) + ((c - 128) >> 3) * kW2S * 2 + ((c - 128) & 7) * 16;
-            else
-                off[j] = (int)offsetof(MlpLds, b1) + (c - 640) * 16;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kMaxPer; ++j)
-        if (off[j] >= 0) *reinterpret_cast<uint4 *>(dst + off[j]) = val[j];
+    const int c0 = threadIdx.x, c1 = c0 + 256, c2 = c0 + 512;
+    const uint4 v0 = src[c0], v1 = src[c1];
+    const uint4 v2 = c2 < kPieces ? src[c2] : uint4{0u, 0u, 0u, 0u};
+    *reinterpret_cast<uint4 *>(dst + param_piece_offset(c0)) = v0;
+    *reinterpret_cast<uint4 *>(dst + param_piece_offset(c1)) = v1;
+    if (c2 < kPieces) *reinterpret_cast<uint4 *>(dst + param_piece_offset(c2)) = v2;
     __syncthreads();
 }
 
@@ -305,6 +300,7 @@ __global__ void __launch_bounds__(256) k_mlp_infer(const __bf16 *X, int32_t coun
             if (g == 0 && node < count && logits) logits[node] = f.z;
             const uint64_t b = __ballot(frozen);
             bits |= (uint32_t)(b & 0xFFFFu) << (16 * half);
+            __builtin_amdgcn_sched_barrier(0);  // one tile at a time (register use)
         }
         if (lane == 0 && mask) mask[w] = bits;
     }
@@ -335,17 +331,16 @@ __device__ __forceinline__ NodeHead load_head(const int32_t *rp, const int8_t *s
 // split both tiles' row scans, which run in one loop so that their loads overlap, and
 // then hold the node's features for the tile's network. The next word's row bounds are
 // loaded before the network runs. The mask bit is set for real ids whose logit exceeds
-// thr_logit; the skipped nodes are counted into block_skips and, times weight, into
-// skipped, one pair of atomics per workgroup.
+// thr_logit; each workgroup stores its count of skipped nodes in part[blockIdx.x]
+// (k_sum_counts adds them up: atomics on one shared counter from every workgroup cost
+// about as much as the rest of the kernel).
 __global__ void __launch_bounds__(256) k_mlp_mask(const int32_t *rp, const int2 *adj, const int8_t *spin,
                                                    const int32_t *last_flip, int32_t n_pad, const int64_t *state,
                                                    float T, int32_t t, int32_t A, int32_t B, const int32_t *orig,
-                                                   const GdiMlpDev *p, float thr_logit, uint32_t *mask,
-                                                   unsigned long long *skipped, uint32_t weight,
-                                                   unsigned long long *block_skips)
+                                                   const GdiMlpDev *p, float thr_logit, uint32_t *mask, uint32_t *part)
 {
     __shared__ MlpLds m;
-    __shared__ unsigned long long cnt_s[4];
+    __shared__ uint32_t cnt_s[4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
     const int64_t words = ((int64_t)n_pad + 31) / 32;
@@ -357,7 +352,7 @@ __global__ void __launch_bounds__(256) k_mlp_mask(const int32_t *rp, const int2 
         hd[hf] = load_head(rp, spin, last_flip, orig, n_pad, (int32_t)(w * 32 + 16 * hf + r));
     load_params(p, &m);
     const int32_t M = (int32_t)state[0];
-    unsigned long long cnt = 0;
+    uint32_t cnt = 0;
     for (; w < words; w += stride) {
         // this lane's entries g, g + 4, ... of both rows, four per row and round (a row of
         // up to 16 entries in one round), every load of a round issued before any is used
@@ -399,11 +394,12 @@ __global__ void __launch_bounds__(256) k_mlp_mask(const int32_t *rp, const int2 
             float f[6];
             node_features(hd[hf].r1 - hd[hf].r0, wabs[hf], other[hf], h[hf], hd[hf].s, M, T, t, A, B, hd[hf].lf, f);
             real[hf] = hd[hf].o >= 0;
-            // B operand of layer 1: features 4g .. 4g + 3 (zero past feature 5 and for padding)
+            // B operand of layer 1: features 4g .. 4g + 3 (zero past feature 5 and for padding);
+            // constant indices into f, so that it stays in registers
 #pragma unroll
             for (int jj = 0; jj < 4; ++jj) {
-                const int fi = 4 * g + jj;
-                xb[hf][jj] = (real[hf] && fi < 6) ? (__bf16)(fi < 4 ? f[fi & 3] : f[4 + (fi & 1)]) : (__bf16)0.0f;
+                const float fv = g == 0 ? f[jj] : (jj < 2 ? f[4 + (jj & 1)] : 0.0f);
+                xb[hf][jj] = (real[hf] && g < 2) ? (__bf16)fv : (__bf16)0.0f;
             }
         }
         const int64_t wn = w + stride;
@@ -419,20 +415,36 @@ __global__ void __launch_bounds__(256) k_mlp_mask(const int32_t *rp, const int2 
             tile_forward(&m, xb[hf], g, r, tf);
             const uint64_t b = __ballot(g == 0 && real[hf] && tf.z > thr_logit);
             bits |= (uint32_t)(b & 0xFFFFu) << (16 * hf);
+            // one tile at a time: interleaving the two tiles' products would double the
+            // live registers and halve the waves per SIMD
+            __builtin_amdgcn_sched_barrier(0);
         }
         if (lane == 0) {
             mask[w] = bits;
-            cnt += (unsigned long long)__popc(bits);
+            cnt += (uint32_t)__popc(bits);
         }
     }
     if (lane == 0) cnt_s[wave] = cnt;
     __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = cnt_s[0] + cnt_s[1] + cnt_s[2] + cnt_s[3];
+}
+
+// One workgroup of 256: the skipped nodes of a block (sum of the nparts workgroup counts,
+// below 2^31) go to block_skips, and times weight are added to skipped.
+__global__ void __launch_bounds__(256) k_sum_counts(const uint32_t *part, int32_t nparts, uint32_t weight,
+                                                     unsigned long long *skipped, unsigned long long *block_skips)
+{
+    __shared__ uint32_t ws[4];
+    uint32_t c = 0;
+    for (int i = threadIdx.x; i < nparts; i += 256) c += part[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned long long c = cnt_s[0] + cnt_s[1] + cnt_s[2] + cnt_s[3];
-        if (c) {
-            atomicAdd(skipped, c * weight);
-            atomicAdd(block_skips, c);
-        }
+        const unsigned long long tot = (unsigned long long)ws[0] + ws[1] + ws[2] + ws[3];
+        *skipped += tot * weight;
+        *block_skips = tot;
     }
 }
 
@@ -688,9 +700,10 @@ int gdi_launch_mlp_infer(const void *X, int32_t count, const GdiMlpDev *p, float
 
 int gdi_launch_mlp_mask(const int32_t *rp, const int2 *adj, const int8_t *spin, const int32_t *last_flip,
                         int32_t n_pad, const int64_t *state, float T, int32_t t, int32_t A, int32_t B,
-                        const int32_t *orig, const GdiMlpDev *p, float thr_logit, uint32_t *mask, uint64_t *skipped,
-                        uint32_t weight, uint64_t *block_skips, void *stream)
+                        const int32_t *orig, const GdiMlpDev *p, float thr_logit, uint32_t *mask, uint32_t *part,
+                        int32_t part_cap, uint64_t *skipped, uint32_t weight, uint64_t *block_skips, void *stream)
 {
+    if (part_cap < 1) return (int)hipErrorInvalidValue;
     const int64_t words = ((int64_t)n_pad + 31) / 32;
     // no more workgroups than fit on the device at once: the parameters are copied to LDS
     // once per workgroup, and a wave takes further words in turn
@@ -702,10 +715,14 @@ int gdi_launch_mlp_mask(const int32_t *rp, const int2 *adj, const int8_t *spin, 
             return (int64_t)1024;
         return (int64_t)std::max(1, cus) * std::max(1, per_cu);
     }();
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((words + 3) / 4, resident));
+    const unsigned grid =
+        (unsigned)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>((words + 3) / 4, resident), part_cap));
     hipLaunchKernelGGL(k_mlp_mask, dim3(grid), dim3(256), 0, (hipStream_t)stream, rp, adj, spin, last_flip, n_pad,
-                       state, T, t, A, B, orig, p, thr_logit, mask, (unsigned long long *)skipped, weight,
-                       (unsigned long long *)block_skips);
+                       state, T, t, A, B, orig, p, thr_logit, mask, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(256), 0, (hipStream_t)stream, part, (int32_t)grid, weight,
+                       (unsigned long long *)skipped, (unsigned long long *)block_skips);
     return (int)hipGetLastError();
 }
 
