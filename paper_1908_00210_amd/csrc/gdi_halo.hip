@@ -373,6 +373,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
     __shared__ int32_t abort_sh;
     __shared__ int32_t tacc[3];
     __shared__ uint32_t wdone;  // worker waves whose polls are done (running count)
+    __shared__ int64_t dcut_sh;  // the workgroup's cut change, summed at the end
 
     const int tid = threadIdx.x, nth = blockDim.x;
     const int wave = tid >> 6, lane = tid & 63, nwaves = nth >> 6;
@@ -415,7 +416,10 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
         abort_sh = 0;
     }
     if (tid < 3) tacc[tid] = 0;
-    if (tid == 0) wdone = 0;
+    if (tid == 0) {
+        wdone = 0;
+        dcut_sh = 0;
+    }
     int32_t M = (int32_t)a.state[0];
     __syncthreads();
 
@@ -742,8 +746,11 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_halo(GdiHaloArgs h)
         for (int i = tid; i < a.C; i += nth) a.P[i] = Psh[i];
         if (tid == 0) a.state[0] = M;
     }
+    // one global atomic per workgroup: the device serialises atomics on one word
     const int64_t w = wave_sum_i64(dcut_total);
-    if (lane == 0 && w != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)w);
+    if (lane == 0 && w != 0) atomicAdd((unsigned long long *)&dcut_sh, (unsigned long long)w);
+    __syncthreads();
+    if (tid == 0 && dcut_sh != 0) atomicAdd((unsigned long long *)&a.state[1], (unsigned long long)dcut_sh);
 }
 
 inline int status(hipError_t e) { return (int)e; }

@@ -1103,11 +1103,11 @@ __global__ void k_pack_spins(const int8_t *spin, int32_t words, uint32_t *bits)
 // neighbours' from the bit-packed copy (an eighth of the cache lines for the random
 // reads, which dominate the kernel's memory traffic).
 template <int L, int U = 4>
-__global__ void __launch_bounds__(256) k_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin,
+__global__ void __launch_bounds__(1024) k_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin,
                                                 const uint32_t *bits, int32_t n_pad, const int32_t *cbeg,
                                                 const int32_t *csz, int32_t C, int64_t *out3, int32_t *P)
 {
-    __shared__ int64_t red[3][4];
+    __shared__ int64_t red[3][16];
     // with few classes, class starts and this block's +1 counts live in LDS (one global
     // atomic per class and block instead of one per 64-id chunk)
     __shared__ int32_t cb_sh[256], pc_sh[256];
@@ -1411,18 +1411,20 @@ int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, in
     // degree 40, 16 and 32 up to 3.6x slower
     const double avg = n_pad ? (double)nnz / n_pad : 0.0;
     const int L = avg < 12.0 ? 2 : 4;
-    // workgroups: one per 4096 padded nodes, between 1024 and 4096, never more than the
-    // rows need; every workgroup ends with a few atomic adds to the same words, so more
-    // workgroups contend (measured on 1M- and 8M-node RGGs: 1024 and 2048 best, 16384 up
-    // to 2.3x slower)
-    const int64_t rows_per_block = 4 * (64 / L);
-    const int64_t want = std::min<int64_t>(4096, std::max<int64_t>(1024, (int64_t)n_pad / 4096));
+    // workgroups of 1024: one per 2048 padded nodes, between 256 and 1024, never more than
+    // the rows need; every workgroup ends with a few atomic adds to the same words, which
+    // the device serialises, so fewer and larger workgroups win (measured on MI355X, whole
+    // cut call: 1M-node RGG 49.9 us with 1024 workgroups of 256 threads, 42.8 us with 256
+    // of 1024, 39.6 us with 512 of 1024; 200k-node RGG 28.5, 19.2 and 20.1 us; 200k-node
+    // ER graph of mean degree 40 48.7, 42.3 and 46.5 us)
+    const int64_t rows_per_block = 16 * (64 / L);
+    const int64_t want = std::min<int64_t>(1024, std::max<int64_t>(256, (int64_t)n_pad / 2048));
     const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n_pad + rows_per_block - 1) / rows_per_block, want));
     hipStream_t st = (hipStream_t)stream;
     if (L == 2)
-        hipLaunchKernelGGL(k_reduce<2>, dim3(grid), dim3(256), 0, st, rp, adj, spin, bits, n_pad, cbeg, csz, C, out3, P);
+        hipLaunchKernelGGL(k_reduce<2>, dim3(grid), dim3(1024), 0, st, rp, adj, spin, bits, n_pad, cbeg, csz, C, out3, P);
     else
-        hipLaunchKernelGGL(k_reduce<4>, dim3(grid), dim3(256), 0, st, rp, adj, spin, bits, n_pad, cbeg, csz, C, out3, P);
+        hipLaunchKernelGGL(k_reduce<4>, dim3(grid), dim3(1024), 0, st, rp, adj, spin, bits, n_pad, cbeg, csz, C, out3, P);
     return status(hipGetLastError());
 }
 

@@ -137,10 +137,13 @@ __global__ void k_mask_heuristic(const int32_t *last_flip, int32_t n_pad, int32_
 }
 
 // Clears the bits of padding ids, counts the skipped nodes of this block into
-// block_skips and the skipped node visits (bits x weight) into skipped.
-__global__ void k_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad, unsigned long long *skipped,
-                              uint32_t weight, unsigned long long *block_skips)
+// block_skips and the skipped node visits (bits x weight) into skipped (workgroups of
+// 256, one pair of atomics each).
+__global__ void __launch_bounds__(256) k_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad,
+                                                      unsigned long long *skipped, uint32_t weight,
+                                                      unsigned long long *block_skips)
 {
+    __shared__ unsigned long long ws[4];
     const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t bits = 0;
     if (w * 32 < n_pad) {
@@ -154,9 +157,14 @@ __global__ void k_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad
     unsigned long long c = (unsigned long long)__popc(bits);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if ((threadIdx.x & 63) == 0 && c) {
-        atomicAdd(skipped, c * weight);
-        atomicAdd(block_skips, c);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long tot = ws[0] + ws[1] + ws[2] + ws[3];
+        if (tot) {
+            atomicAdd(skipped, tot * weight);
+            atomicAdd(block_skips, tot);
+        }
     }
 }
 
