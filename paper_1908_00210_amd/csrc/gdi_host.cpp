@@ -1635,15 +1635,17 @@ int train_impl(const void *d_x, const uint8_t *d_y, uint64_t n, gdi_mlp_weights 
     if (!d_x || !d_y || !w || !cfg || n == 0) return fail(GDI_EINVAL, "bad argument");
     if (cfg->batch < 16 || n > (uint64_t)INT32_MAX) return fail(GDI_EINVAL, "batch must be >= 16, n < 2^31");
     MlpDevice net;
-    DevBuf<float> grad, mo, ve, loss;
+    DevBuf<float> grad, mo, ve, loss, part;
     DevBuf<int32_t> perm;
     struct Rel {
-        DevBuf<float> &a, &b, &c, &d; DevBuf<int32_t> &e;
-        ~Rel() { a.release(); b.release(); c.release(); d.release(); e.release(); }
-    } rel{grad, mo, ve, loss, perm};
+        DevBuf<float> &a, &b, &c, &d, &f; DevBuf<int32_t> &e;
+        ~Rel() { a.release(); b.release(); c.release(); d.release(); f.release(); e.release(); }
+    } rel{grad, mo, ve, loss, part, perm};
     int rc = upload_mlp(w, net, st);
     if (rc) return rc;
     HIP_TRY(grad.reserve(GDI_MLP_PARAMS + 1), "hipMalloc training");
+    HIP_TRY(part.reserve((size_t)gdi_mlp_grad_part_floats((int32_t)std::min<uint64_t>(cfg->batch, n))),
+            "hipMalloc training");
     HIP_TRY(mo.reserve(GDI_MLP_PARAMS + 1), "hipMalloc training");
     HIP_TRY(ve.reserve(GDI_MLP_PARAMS + 1), "hipMalloc training");
     HIP_TRY(loss.reserve(2), "hipMalloc training");
@@ -1661,8 +1663,9 @@ int train_impl(const void *d_x, const uint8_t *d_y, uint64_t n, gdi_mlp_weights 
         for (uint64_t off = 0; off < n; off += cfg->batch) {
             const int32_t cnt = (int32_t)std::min<uint64_t>(cfg->batch, n - off);
             ++step;
-            HIP_TRY(hipMemsetAsync(grad.p, 0, (GDI_MLP_PARAMS + 1) * 4, st), "zero gradient");
-            int e = gdi_launch_mlp_grad(d_x, d_y, perm.p + off, cnt, net.packed.p, 1.0f / (float)cnt, grad.p, loss.p, st);
+            // the gradient is written whole, the loss added
+            int e = gdi_launch_mlp_grad(d_x, d_y, perm.p + off, cnt, net.packed.p, 1.0f / (float)cnt, part.p, grad.p,
+                                        loss.p, st);
             const float bc1 = 1.0f - std::pow(cfg->beta1, (float)step), bc2 = 1.0f - std::pow(cfg->beta2, (float)step);
             if (!e) e = gdi_launch_adam(net.master.p, grad.p, mo.p, ve.p, GDI_MLP_PARAMS, cfg->lr, cfg->beta1, cfg->beta2,
                                         cfg->eps, bc1, bc2, st);
@@ -2037,19 +2040,24 @@ int gdi_mlp_gradient(const gdi_mlp_weights *w, const void *d_x, const uint8_t *d
 {
     if (!w || !d_x || !d_y || !grad || n == 0) return fail(GDI_EINVAL, "bad argument");
     hipStream_t st = (hipStream_t)hip_stream;
+    if (n > (uint32_t)INT32_MAX) return fail(GDI_EINVAL, "n must be < 2^31");
     MlpDevice net;
-    DevBuf<float> gbuf;
+    DevBuf<float> gbuf, part;
+    struct Rel {
+        DevBuf<float> &a, &b;
+        ~Rel() { a.release(); b.release(); }
+    } rel{gbuf, part};
     int rc = upload_mlp(w, net, st);
     if (rc) return rc;
     HIP_TRY(gbuf.reserve(GDI_MLP_PARAMS + 2), "hipMalloc gradient");
+    HIP_TRY(part.reserve((size_t)gdi_mlp_grad_part_floats((int32_t)n)), "hipMalloc gradient");
     HIP_TRY(hipMemsetAsync(gbuf.p, 0, (GDI_MLP_PARAMS + 2) * 4, st), "zero gradient");
-    int e = gdi_launch_mlp_grad(d_x, d_y, nullptr, (int32_t)n, net.packed.p, 1.0f / (float)n, gbuf.p,
+    int e = gdi_launch_mlp_grad(d_x, d_y, nullptr, (int32_t)n, net.packed.p, 1.0f / (float)n, part.p, gbuf.p,
                                 gbuf.p + GDI_MLP_PARAMS + 1, st);
-    if (e) { gbuf.release(); return fail(GDI_EDEVICE, gdi_hip_error_string(e)); }
+    if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
     std::vector<float> h(GDI_MLP_PARAMS + 2);
     hipError_t he = hipMemcpyAsync(h.data(), gbuf.p, h.size() * 4, hipMemcpyDeviceToHost, st);
     if (he == hipSuccess) he = hipStreamSynchronize(st);
-    gbuf.release();
     if (he != hipSuccess) return hip_fail(he, "network gradient");
     std::memcpy(grad, h.data(), sizeof(gdi_mlp_weights));
     if (loss) *loss = h[GDI_MLP_PARAMS + 1] / (float)n;

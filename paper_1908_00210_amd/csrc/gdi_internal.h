@@ -223,8 +223,12 @@ int gdi_launch_mlp_mask(const int32_t *rp, const int2 *adj, const int8_t *spin, 
                         int32_t part_cap, uint64_t *skipped, uint32_t weight, uint64_t *block_skips, void *stream);
 int gdi_launch_mlp_infer(const void *X, int32_t count, const GdiMlpDev *p, float thr_logit, uint32_t *mask,
                          float *logits, void *stream);
+// Loss and gradient of a minibatch of count rows: per-wave partial sums in part (at least
+// gdi_mlp_grad_part_floats(count) floats), then grad (written, GDI_MLP_PARAMS floats) and
+// *loss (the summed loss added, if loss is not NULL), the same bits on every run.
+int gdi_mlp_grad_part_floats(int32_t count);
 int gdi_launch_mlp_grad(const void *X, const uint8_t *Y, const int32_t *idx, int32_t count, const GdiMlpDev *p,
-                        float inv_batch, float *grad, float *loss, void *stream);
+                        float inv_batch, float *part, float *grad, float *loss, void *stream);
 int gdi_launch_adam(float *w, const float *g, float *m, float *v, int32_t P, float lr, float b1, float b2, float eps,
                     float bc1, float bc2, void *stream);
 int gdi_launch_mlp_pack(const float *w, GdiMlpDev *p, void *stream);

@@ -459,7 +459,11 @@ __global__ void __launch_bounds__(256) k_sum_counts(const uint32_t *part, int32_
 // ------------------------------------------------------------------ gradients
 // Mean logistic loss over the minibatch rows idx[0..count) and its gradient with
 // respect to the packed FP32 parameters (layout of gdi_mlp_weights: w1[64][6], b1,
-// w2[64][64], b2, w3, b3), accumulated with atomics into grad (zeroed by the caller).
+// w2[64][64], b2, w3, b3). Every wave writes its own sums over its tiles, all
+// GDI_MLP_PARAMS of them and its loss sum after them, to row blockIdx.x * 4 + wave of
+// part (rows of kGradStride floats); k_grad_sum adds the rows up in row order. No
+// atomics: the gradient is the same bits on every run (a float atomic sum is not), and
+// a quarter of a million atomic adds on 4673 words cost more than the products.
 struct WaveTiles {
     __bf16 dp2[64 * 16];  // dPre2^T [o][node]
     __bf16 h1[64 * 16];   // H1^T [k][node]
@@ -475,9 +479,11 @@ __device__ __forceinline__ bf16x4 lds4(const __bf16 *base)
     return v;
 }
 
+constexpr int kGradStride = (GDI_MLP_PARAMS + 1 + 3) & ~3;
+constexpr int64_t kGradBlocks = 128;  // at most 512 partial rows (9.6 MB)
+
 __global__ void __launch_bounds__(256) k_mlp_grad(const __bf16 *X, const uint8_t *Y, const int32_t *idx,
-                                                   int32_t count, const GdiMlpDev *p, float inv_batch,
-                                                   float *grad, float *loss)
+                                                   int32_t count, const GdiMlpDev *p, float inv_batch, float *part)
 {
     __shared__ MlpLds m;
     __shared__ WaveTiles tiles[4];
@@ -573,24 +579,20 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const __bf16 *X, const uint8_t
         wave_lds_sync();
     }
     // flush: D layout row = 16a + 4g + i, column = 16b + r
-    float *gw1 = grad, *gb1p = grad + 64 * 6, *gw2 = gb1p + 64, *gb2p = gw2 + 64 * 64, *gw3p = gb2p + 64,
+    float *row = part + (size_t)(blockIdx.x * 4 + wave) * kGradStride;
+    float *gw1 = row, *gb1p = row + 64 * 6, *gw2 = gb1p + 64, *gb2p = gw2 + 64 * 64, *gw3p = gb2p + 64,
           *gb3p = gw3p + 64;
 #pragma unroll
     for (int mo = 0; mo < 4; ++mo)
 #pragma unroll
         for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float v = acc_w2[mo][kb][i];
-                if (v != 0.0f) atomicAdd(&gw2[(16 * mo + 4 * g + i) * 64 + 16 * kb + r], v);
-            }
+            for (int i = 0; i < 4; ++i) gw2[(16 * mo + 4 * g + i) * 64 + 16 * kb + r] = acc_w2[mo][kb][i];
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float v = acc_w1[kb][i];
-            if (r < 6 && v != 0.0f) atomicAdd(&gw1[(16 * kb + 4 * g + i) * 6 + r], v);
-        }
+        for (int i = 0; i < 4; ++i)
+            if (r < 6) gw1[(16 * kb + 4 * g + i) * 6 + r] = acc_w1[kb][i];
     // per-hidden-unit sums over nodes: reduce the 16 node lanes of each row group
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -605,9 +607,9 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const __bf16 *X, const uint8_t
             }
             if (r == 0) {
                 const int hrow = 16 * a + 4 * g + i;
-                if (v1 != 0.0f) atomicAdd(&gb1p[hrow], v1);
-                if (v2 != 0.0f) atomicAdd(&gb2p[hrow], v2);
-                if (v3 != 0.0f) atomicAdd(&gw3p[hrow], v3);
+                gb1p[hrow] = v1;
+                gb2p[hrow] = v2;
+                gw3p[hrow] = v3;
             }
         }
 #pragma unroll
@@ -616,8 +618,31 @@ __global__ void __launch_bounds__(256) k_mlp_grad(const __bf16 *X, const uint8_t
         lsum += __shfl_xor(lsum, off, 64);
     }
     if (lane == 0) {
-        if (gb3 != 0.0f) atomicAdd(gb3p, gb3);
-        if (loss) atomicAdd(loss, lsum);
+        gb3p[0] = gb3;
+        row[GDI_MLP_PARAMS] = lsum;
+    }
+}
+
+// grad[i] = sum over the rows of part[row][i] for i < GDI_MLP_PARAMS; the rows' loss
+// sums are added to *loss. Workgroups of 1024: 64 columns, 16 slices of rows (slice s
+// sums rows s, s + 16, ... in order), then the 16 slice sums in order: a fixed order,
+// with 16 loads in flight per column.
+__global__ void __launch_bounds__(1024) k_grad_sum(const float *part, int32_t rows, float *grad, float *loss)
+{
+    __shared__ float red[16][64];
+    const int pi = threadIdx.x & 63, sl = threadIdx.x >> 6;
+    const int32_t i = blockIdx.x * 64 + pi;
+    float acc = 0.0f;
+    if (i <= GDI_MLP_PARAMS)
+        for (int32_t w = sl; w < rows; w += 16) acc += part[(size_t)w * kGradStride + i];
+    red[sl][pi] = acc;
+    __syncthreads();
+    if (sl == 0 && i <= GDI_MLP_PARAMS) {
+        float t = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t += red[k][pi];
+        if (i < GDI_MLP_PARAMS) grad[i] = t;
+        else if (loss) *loss += t;
     }
 }
 
@@ -734,13 +759,25 @@ int gdi_launch_mlp_mask(const int32_t *rp, const int2 *adj, const int8_t *spin, 
     return (int)hipGetLastError();
 }
 
-int gdi_launch_mlp_grad(const void *X, const uint8_t *Y, const int32_t *idx, int32_t count, const GdiMlpDev *p,
-                        float inv_batch, float *grad, float *loss, void *stream)
+int gdi_mlp_grad_part_floats(int32_t count)
 {
     const int64_t tiles = ((int64_t)count + 15) / 16;
-    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, 1024));
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, kGradBlocks));
+    return (int)(grid * 4 * kGradStride);
+}
+
+int gdi_launch_mlp_grad(const void *X, const uint8_t *Y, const int32_t *idx, int32_t count, const GdiMlpDev *p,
+                        float inv_batch, float *part, float *grad, float *loss, void *stream)
+{
+    if (count < 1) return (int)hipErrorInvalidValue;
+    const int64_t tiles = ((int64_t)count + 15) / 16;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((tiles + 3) / 4, kGradBlocks));
     hipLaunchKernelGGL(k_mlp_grad, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const __bf16 *)X, Y, idx, count,
-                       p, inv_batch, grad, loss);
+                       p, inv_batch, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(k_grad_sum, dim3((GDI_MLP_PARAMS + 1 + 63) / 64), dim3(1024), 0, (hipStream_t)stream, part,
+                       (int32_t)(grid * 4), grad, loss);
     return (int)hipGetLastError();
 }
 

@@ -250,6 +250,9 @@ def test_mlp_gradient_matches_reference(gdi, L):
     dx = torch.from_numpy(X).to(torch.bfloat16).cuda()
     dy = torch.from_numpy(y).cuda()
     grad, loss = gdi.mlp_gradient(w, dx.data_ptr(), dy.data_ptr(), n)
+    # partial sums per wave added in a fixed order: the same bits on a second call
+    grad2, loss2 = gdi.mlp_gradient(w, dx.data_ptr(), dy.data_ptr(), n)
+    assert np.array_equal(np.asarray(grad), np.asarray(grad2)) and loss == loss2
     m = L.mlp_error_model(w, X, y)
     assert abs(loss - m["loss"]) <= m["loss_bound"]
     err = np.abs(np.asarray(grad, np.float64) - m["grad"])
@@ -285,6 +288,9 @@ def test_training_reduces_loss(gdi, L):
     X = dx.view(-1, 8)[:rows].float().cpu().numpy()
     loss_ref, _ = L.mlp_loss_grad(w.astype(np.float64), X[:, :6], dy[:rows].cpu().numpy(), round_points=True)
     assert loss_ref < 0.8 * const_loss
+    # training is reproducible: the same weights and losses, bit for bit, on a second run
+    w2, losses2 = gdi.mlp_train(dx.data_ptr(), dy.data_ptr(), rows, w0, epochs=4, batch=1024, lr=2e-3, seed=3)
+    assert np.array_equal(w, w2) and np.array_equal(losses, losses2)
 
 
 def test_learned_rejects_bad_config(gdi):
