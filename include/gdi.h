@@ -445,7 +445,10 @@ int gdi_mlp_init(gdi_mlp_weights *w, uint64_t seed);
  * gdi_mlp_train -- minimise the mean logistic loss on (d_x, d_y) (device rows as
  * written by gdi_collect_traces) with the library's forward / backward / Adam
  * kernels; w holds the initial weights and receives the trained ones;
- * epoch_loss (host, epochs entries) may be NULL. Runs on hip_stream.
+ * epoch_loss (host, epochs entries) may be NULL. Runs on hip_stream. The gradient
+ * sums run in a fixed order (no floating-point atomics), so equal inputs give the
+ * same weights and losses bit for bit on every run. Device scratch of about
+ * 73 KB per 64 minibatch rows (at most 9.6 MB) is allocated for the call.
  */
 int gdi_mlp_train(const void *d_x, const uint8_t *d_y, uint64_t n, gdi_mlp_weights *w, const gdi_train_cfg *cfg,
                   float *epoch_loss, void *hip_stream);
@@ -453,7 +456,8 @@ int gdi_mlp_train(const void *d_x, const uint8_t *d_y, uint64_t n, gdi_mlp_weigh
 /* gdi_mlp_forward -- logits of n device rows into d_logits (device); for checking the kernels. */
 int gdi_mlp_forward(const gdi_mlp_weights *w, const void *d_x, uint32_t n, float *d_logits, void *hip_stream);
 
-/* gdi_mlp_gradient -- mean logistic loss of n device rows and its gradient (host outputs). */
+/* gdi_mlp_gradient -- mean logistic loss of n device rows (n < 2^31) and its gradient
+ * (host outputs); the same bits on every call (sums in a fixed order). */
 int gdi_mlp_gradient(const gdi_mlp_weights *w, const void *d_x, const uint8_t *d_y, uint32_t n,
                      gdi_mlp_weights *grad, float *loss, void *hip_stream);
 
