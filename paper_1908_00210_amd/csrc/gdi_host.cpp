@@ -640,8 +640,6 @@ int prepare_run(gdi_graph *g, const gdi_schedule *s, uint64_t seed, bool dev_out
             return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
     }
     rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_state.p), 8, st);
-    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_red.p), 4, st);
-    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_P.p), (g->C + 2) / 2, st);
     if (!rc && trace) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_trace.p), 2 * (int64_t)S, st);
     if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p,
                                     g->C, g->d_red.p, g->d_P.p, g->d_bits.p, st);
@@ -738,8 +736,6 @@ int launch_range(gdi_graph *g, RunCtx &r, uint32_t t_from, uint32_t t_to, const 
         a.bar_glob = g->d_bar.p + sweeps * GDI_BAR_GROUPS * GDI_BAR_PAD;
         if (!rc) rc = gdi_launch_fill_u64(g->d_bar.p, (int64_t)(sweeps * (GDI_BAR_GROUPS + 1) * GDI_BAR_PAD), st);
         if (!rc && sweeps > 0) rc = gdi_launch_sweep_async(a, grid, 1024, st);
-        if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_red.p), 4, st);
-        if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(g->d_P.p), (g->C + 2) / 2, st);
         if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, g->d_spin.p, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p, g->C,
                                         g->d_red.p, g->d_P.p, g->d_bits.p, st);
         if (!rc) g->last.grid = (uint32_t)grid;
@@ -856,11 +852,12 @@ int cut_impl(gdi_graph *g, const int8_t *spins, bool dev, int64_t *cw, int64_t *
     HIP_TRY(P.reserve((size_t)g->C + 2), "hipMalloc");
     DevBuf<int64_t> red;
     HIP_TRY(red.reserve(4), "hipMalloc");
+    // the spins gathered into the annealer's order (one thread per id: a gather per
+    // thread keeps the most loads in flight), then reduced
     rc = gdi_launch_gather_in(g->d_orig.p, src, g->n_pad, tmp.p, st);
-    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(red.p), 4, st);
-    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(P.p), (g->C + 2) / 2, st);
-    if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, tmp.p, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p, g->C,
-                                    red.p, P.p, g->d_bits.p, st);
+    if (!rc)
+        rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, tmp.p, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p, g->C, red.p,
+                               P.p, g->d_bits.p, st);
     if (rc) {
         tmp.release(); P.release(); red.release();
         return fail(GDI_EDEVICE, gdi_hip_error_string(rc));
@@ -1866,10 +1863,9 @@ int gdi_cut_dev_noalloc(gdi_graph *g, const int8_t *d_spins, int64_t *d_out)
     uint32_t *bits = reinterpret_cast<uint32_t *>(static_cast<unsigned char *>(base) + GDI_NOALLOC_SPIN_OFF +
                                                   (((size_t)g->n_pad + 255) & ~(size_t)255));
     hipStream_t st = g->stream;
-    // the accumulators and counts keep the last call's values: cleared by fill kernels
+    // the accumulators and counts keep the last call's values: the reduction's first
+    // kernel clears them (a kernel, not a memset)
     int rc = gdi_launch_gather_in(g->d_orig.p, d_spins, g->n_pad, sp, st);
-    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(red), 4, st);
-    if (!rc) rc = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(P), (g->C + 2) / 2, st);
     if (!rc) rc = gdi_launch_reduce(g->d_rp.p, g->d_adj.p, sp, g->n_pad, g->nnz, g->d_cbeg.p, g->d_csz.p, g->C, red, P, bits, st);
     if (!rc) rc = gdi_launch_cut_finish(red, d_out, st);
     if (rc) return fail(GDI_EDEVICE, gdi_hip_error_string(rc));

@@ -172,7 +172,10 @@ struct GdiMlpDev {
 // host-side launchers (gdi_kernels.hip)
 int gdi_launch_init_spins(const int32_t *orig, const int8_t *init_orig, int8_t *spin, int32_t n_pad,
                           uint32_t key0, uint32_t key1, uint32_t replica, void *stream);
-// bits: n_pad / 32 words of scratch for the bit-packed spins the neighbour reads use
+// From-scratch M, doubled cut, doubled crossing count into out3[0..2] and the per-class +1
+// counts into P; out3[0..3] and P[0 .. 2 ((C + 2) / 2)) are cleared first (no fills
+// needed). bits: n_pad / 32 words of scratch for the bit-packed spins the neighbour reads
+// use; spin 16-byte aligned.
 int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, int32_t n_pad, int64_t nnz,
                       const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P,
                       uint32_t *bits, void *stream);

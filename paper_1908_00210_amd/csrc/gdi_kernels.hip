@@ -1079,10 +1079,15 @@ __global__ void k_fill_u64(uint64_t *p, int64_t count)
 // because class starts are 64-aligned, so each wave adds its +1 count to one class
 // counter; the three sums are reduced per workgroup in LDS, one atomic each.
 // Bit-packed copy of the spins for the neighbour reads of k_reduce: bit i of word w is
-// set iff spin 32w + i is +1 (n_pad is a multiple of 64).
-__global__ void k_pack_spins(const int8_t *spin, int32_t words, uint32_t *bits)
+// set iff spin 32w + i is +1 (n_pad is a multiple of 64). The first threads also clear
+// k_reduce's accumulators (zero64 64-bit words of z64, zero32 32-bit words of z32), so
+// that no separate fill launches precede it.
+__global__ void k_pack_spins(const int8_t *spin, int32_t words, uint32_t *bits, int64_t *z64, int32_t zero64,
+                             int32_t *z32, int32_t zero32)
 {
     const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < zero64) z64[w] = 0;
+    if (w < zero32) z32[w] = 0;
     if (w >= words) return;
     const uint4 *p = reinterpret_cast<const uint4 *>(spin + (size_t)w * 32);
     const uint4 lo = p[0], hi = p[1];
@@ -1401,10 +1406,13 @@ int gdi_launch_reduce(const int32_t *rp, const int2 *adj, const int8_t *spin, in
                       const int32_t *cbeg, const int32_t *csz, int32_t C, int64_t *out3, int32_t *P,
                       uint32_t *bits, void *stream)
 {
+    if ((n_pad & 63) || (reinterpret_cast<uintptr_t>(spin) & 15)) return (int)hipErrorInvalidValue;
     const int32_t words = n_pad / 32;
-    if (words > 0)
-        hipLaunchKernelGGL(k_pack_spins, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, (hipStream_t)stream, spin,
-                           words, bits);
+    // the accumulators: out3[0..3] and P[0 .. 2 ((C + 2) / 2)), cleared by the first threads
+    const int32_t zero32 = 2 * ((C + 2) / 2);
+    const int32_t threads = std::max(std::max(words, zero32), 4);
+    hipLaunchKernelGGL(k_pack_spins, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, (hipStream_t)stream, spin,
+                       words, bits, out3, 4, P, zero32);
     // lanes per row: rows in flight matter more than lanes per row (each row is a chain of
     // row bound, entry and neighbour-spin loads); measured on MI355X over 1..32 lanes:
     // 2 or 4 best on RGGs of mean degree 8 (1M and 8M nodes) and on an ER graph of mean
