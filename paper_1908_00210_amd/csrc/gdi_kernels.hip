@@ -429,8 +429,11 @@ __device__ __forceinline__ uint64_t active_chunk(const GdiSweepArgs &a, int32_t 
 // per word, four words per thread in flight), and the compaction gives each thread a run
 // of consecutive 64-id chunks (records in id order, which is class order), counts its
 // active ids, takes its first record's position from one workgroup scan and writes its
-// records; class starts are multiples of 64, so a chunk lies in one class.
-__global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_active(GdiSweepArgs a, GdiActiveRec *rec)
+// records; class starts are multiples of 64, so a chunk lies in one class. When thr_bytes
+// (at LDS byte offset thr_off) hold the launch's threshold rows, they are copied there
+// and every decision reads its threshold from LDS.
+__global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_active(GdiSweepArgs a, GdiActiveRec *rec, int32_t thr_off,
+                                                                int32_t thr_bytes)
 {
     if (!gate_open(a)) return;
     extern __shared__ uint32_t lds[];
@@ -469,6 +472,13 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_active(GdiSweepArgs a, 
         cs_s[i] = a.csz[i];
     }
     if (tid == 0) cb_s[a.C] = a.n_pad;
+    // the threshold rows of sweeps t0 .. S - 1
+    const int32_t K1 = a.K + 1;
+    const int64_t thr_n = a.S > a.t0 ? (int64_t)(a.S - a.t0) * K1 : 0;
+    const bool thr_staged = thr_n * 4 <= (int64_t)thr_bytes;
+    uint32_t *thr_s = reinterpret_cast<uint32_t *>(reinterpret_cast<unsigned char *>(lds) + thr_off);
+    if (thr_staged)
+        for (int64_t i = tid; i < thr_n; i += nth) thr_s[i] = a.thr[(size_t)a.t0 * K1 + i];
     if (tid < 3) acc[tid] = 0;
     int32_t M = (int32_t)a.state[0];
     __syncthreads();
@@ -523,10 +533,11 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_active(GdiSweepArgs a, 
     uint32_t p = 0;
     for (uint32_t t = a.t0; t < a.S; ++t) {
         const uint32_t *thr_row = a.thr + (size_t)t * (uint32_t)(a.K + 1);
+        const uint32_t *thr_l = thr_staged ? thr_s + (size_t)(t - a.t0) * K1 : nullptr;
         for (int32_t c = 0; c < a.C; ++c) {
             const int32_t jb = abeg[c], je = abeg[c + 1];
             if (jb == je) continue;
-            const PhaseView pv = make_view(M, Psh[c], a.csz[c], a.C, a.n);
+            const PhaseView pv = make_view(M, Psh[c], cs_s[c], a.C, a.n);
             int32_t dM = 0;
             // each thread loads its next record while it works on this one, and a row's
             // entries eight at a time, all loads of a round issued before any is used
@@ -546,7 +557,7 @@ __global__ void __launch_bounds__(GDI_MAX_BLOCK) k_sweep_active(GdiSweepArgs a, 
                         if (k0 + u < r.r1) h += ((bits[e[u].x >> 5] >> (e[u].x & 31)) & 1u) ? e[u].y : -e[u].y;
                 }
                 const int32_t sigma = ((bits[r.v >> 5] >> (r.v & 31)) & 1u) ? 1 : -1;
-                if (decide_id(a, (uint32_t)r.orig, t, sigma, h, pv, thr_row)) {
+                if (decide_id(a, (uint32_t)r.orig, t, sigma, h, pv, thr_row, thr_l)) {
                     // members of a class are never neighbours: other readers of this word
                     // only look at bits that do not change in this phase
                     atomicXor(&bits[r.v >> 5], 1u << (r.v & 31));
@@ -1566,11 +1577,20 @@ int gdi_launch_sweep_active(const GdiSweepArgs &a, GdiActiveRec *rec, void *stre
     const void *f = (const void *)k_sweep_active;
     if ((a.n_pad & 63) || (reinterpret_cast<uintptr_t>(a.spin) & 15) || (reinterpret_cast<uintptr_t>(a.mask) & 7))
         return (int)hipErrorInvalidValue;
-    const int lds = gdi_active_lds_bytes(a.n_pad, a.C);
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    // the bits and counts, then the launch's threshold rows if they fit beside them
+    int dev = 0, lds_max = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return status(e);
+    const int base = gdi_active_lds_bytes(a.n_pad, a.C);
+    int32_t thr_off = (base + 15) & ~15;
+    const int64_t want = a.S > a.t0 ? (int64_t)(a.S - a.t0) * (a.K + 1) * 4 : 0;
+    int32_t thr_bytes = (int64_t)thr_off + want + 512 <= (int64_t)lds_max ? (int32_t)want : 0;
+    const int lds = thr_bytes > 0 ? thr_off + thr_bytes : base;
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
     if (e != hipSuccess) return status(e);
     GdiSweepArgs copy = a;
-    void *args[] = {&copy, &rec};
+    void *args[] = {&copy, &rec, &thr_off, &thr_bytes};
     e = hipLaunchKernel(f, dim3(1), dim3(GDI_MAX_BLOCK), args, (size_t)lds, (hipStream_t)stream);
     return status(e);
 }
