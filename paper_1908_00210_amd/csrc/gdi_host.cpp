@@ -1482,7 +1482,7 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
         DevBuf<int32_t> &a; DevBuf<uint32_t> &b, &c; DevBuf<uint64_t> &d; DevBuf<GdiActiveRec> &e;
         ~Rel() { a.release(); b.release(); c.release(); d.release(); e.release(); }
     } rel{lf, mask, part, skipped, rec};
-    const int32_t kParts = 4096;  // workgroup counts of the network's mask kernel
+    const int32_t kParts = 4096;  // workgroup counts of the proposal's mask kernel
     // masked sweeps with few active nodes: one workgroup over the active set, if every
     // spin fits its LDS as a bit
     int dev = 0, lds_max = 0;
@@ -1502,8 +1502,8 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
     if (!e) e = gdi_launch_fill_u64(reinterpret_cast<uint64_t *>(mask.p), (int64_t)g->n_pad / 64, st);
     if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
     float thr_logit = 0.0f;
+    if (cfg->skip_mode != GDI_SKIP_NONE) HIP_TRY(part.reserve((size_t)kParts), "hipMalloc learned");
     if (cfg->skip_mode == GDI_SKIP_MLP) {
-        HIP_TRY(part.reserve((size_t)kParts), "hipMalloc learned");
         if ((rc = upload_mlp(w, net, st))) return rc;
         thr_logit = std::log(cfg->skip_threshold / (1.0f - cfg->skip_threshold));
     }
@@ -1533,9 +1533,8 @@ int learned_impl(gdi_graph *g, const gdi_schedule *s, uint64_t seed, const gdi_m
                                     (float)s->temps[b], (int32_t)b, s->A, s->B, g->d_orig.p, net.packed.p, thr_logit,
                                     mask.p, part.p, kParts, skipped.p, end - b - 1, skipped.p + 1, st);
         } else if (cfg->skip_mode == GDI_SKIP_HEURISTIC) {
-            e = gdi_launch_fill_u64(skipped.p + 1, 1, st);
-            if (!e) e = gdi_launch_mask_heuristic(lf.p, g->n_pad, (int32_t)b, (int32_t)cfg->heuristic_k, mask.p, st);
-            if (!e) e = gdi_launch_mask_finish(mask.p, g->d_orig.p, g->n_pad, skipped.p, end - b - 1, skipped.p + 1, st);
+            e = gdi_launch_mask_age(lf.p, g->d_orig.p, g->n_pad, (int32_t)b, (int32_t)cfg->heuristic_k, mask.p, part.p,
+                                    kParts, skipped.p, end - b - 1, skipped.p + 1, st);
         }
         if (e) return fail(GDI_EDEVICE, gdi_hip_error_string(e));
         if (cfg->mask_trace) {

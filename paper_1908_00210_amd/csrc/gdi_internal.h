@@ -212,10 +212,12 @@ int gdi_launch_features(const int32_t *rp, const int2 *adj, const int8_t *spin, 
                         const int32_t *orig, void *X, int32_t dataset_rows, int64_t x_base, void *stream);
 int gdi_launch_labels(const int32_t *last_flip, const int32_t *orig, int32_t n_pad, int32_t t_cut, uint8_t *y,
                       int64_t y_base, void *stream);
-int gdi_launch_mask_heuristic(const int32_t *last_flip, int32_t n_pad, int32_t t, int32_t k, uint32_t *mask,
-                              void *stream);
-int gdi_launch_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad, uint64_t *skipped, uint32_t weight,
-                           uint64_t *block_skips, void *stream);
+// Age proposal of one block (k_mask_age: real ids unflipped for >= k sweeps), then its
+// count of skipped nodes into *block_skips (set) and, times weight, into *skipped (added)
+// (k_sum_counts); part: scratch of part_cap >= 1 workgroup counts.
+int gdi_launch_mask_age(const int32_t *last_flip, const int32_t *orig, int32_t n_pad, int32_t t, int32_t k,
+                        uint32_t *mask, uint32_t *part, int32_t part_cap, uint64_t *skipped, uint32_t weight,
+                        uint64_t *block_skips, void *stream);
 int gdi_launch_fill_i32(int32_t *p, int64_t n, int32_t value, void *stream);
 // Features, network and mask of one proposal block (k_mlp_mask), then its count of skipped
 // nodes into *block_skips (set) and, times weight, into *skipped (added) (k_sum_counts);

@@ -123,49 +123,36 @@ __global__ void k_labels(const int32_t *last_flip, const int32_t *orig, int32_t 
     y[y_base + o] = last_flip[v] <= t_cut ? 1 : 0;
 }
 
-// Heuristic proposal: skip nodes that have not flipped for at least k sweeps.
-__global__ void k_mask_heuristic(const int32_t *last_flip, int32_t n_pad, int32_t t, int32_t k, uint32_t *mask)
+// Age proposal: skip the real ids that have not flipped for at least k sweeps. A thread
+// takes a mask word (32 ids: their last flips and original ids as 16-byte loads), in
+// turn over the grid; each workgroup stores its count of skipped nodes in
+// part[blockIdx.x] for k_sum_counts (workgroups of 256; n_pad a multiple of 32).
+__global__ void __launch_bounds__(256) k_mask_age(const int32_t *last_flip, const int32_t *orig, int32_t n_pad,
+                                                   int32_t t, int32_t k, uint32_t *mask, uint32_t *part)
 {
-    const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w * 32 >= n_pad) return;
-    uint32_t bits = 0;
-    for (int i = 0; i < 32; ++i) {
-        const int32_t v = w * 32 + i;
-        if (v < n_pad && t - last_flip[v] >= k) bits |= 1u << i;
-    }
-    mask[w] = bits;
-}
-
-// Clears the bits of padding ids, counts the skipped nodes of this block into
-// block_skips and the skipped node visits (bits x weight) into skipped (workgroups of
-// 256, one pair of atomics each).
-__global__ void __launch_bounds__(256) k_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad,
-                                                      unsigned long long *skipped, uint32_t weight,
-                                                      unsigned long long *block_skips)
-{
-    __shared__ unsigned long long ws[4];
-    const int32_t w = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t bits = 0;
-    if (w * 32 < n_pad) {
-        bits = mask[w];
-        for (int i = 0; i < 32; ++i) {
-            const int32_t v = w * 32 + i;
-            if (v >= n_pad || orig[v] < 0) bits &= ~(1u << i);
+    __shared__ uint32_t ws[4];
+    const int32_t words = n_pad >> 5;
+    uint32_t cnt = 0;
+    for (int32_t w = blockIdx.x * blockDim.x + threadIdx.x; w < words; w += gridDim.x * blockDim.x) {
+        const int4 *lf4 = reinterpret_cast<const int4 *>(last_flip + (size_t)w * 32);
+        const int4 *or4 = reinterpret_cast<const int4 *>(orig + (size_t)w * 32);
+        uint32_t bits = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int4 l = lf4[q], o = or4[q];
+            const int32_t lv[4] = {l.x, l.y, l.z, l.w}, ov[4] = {o.x, o.y, o.z, o.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (ov[j] >= 0 && t - lv[j] >= k) bits |= 1u << (4 * q + j);
         }
         mask[w] = bits;
+        cnt += (uint32_t)__popc(bits);
     }
-    unsigned long long c = (unsigned long long)__popc(bits);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+    for (int off = 32; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = cnt;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned long long tot = ws[0] + ws[1] + ws[2] + ws[3];
-        if (tot) {
-            atomicAdd(skipped, tot * weight);
-            atomicAdd(block_skips, tot);
-        }
-    }
+    if (threadIdx.x == 0) part[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t value)
@@ -698,19 +685,21 @@ int gdi_launch_labels(const int32_t *last_flip, const int32_t *orig, int32_t n_p
     return (int)hipGetLastError();
 }
 
-int gdi_launch_mask_heuristic(const int32_t *last_flip, int32_t n_pad, int32_t t, int32_t k, uint32_t *mask,
-                              void *stream)
+int gdi_launch_mask_age(const int32_t *last_flip, const int32_t *orig, int32_t n_pad, int32_t t, int32_t k,
+                        uint32_t *mask, uint32_t *part, int32_t part_cap, uint64_t *skipped, uint32_t weight,
+                        uint64_t *block_skips, void *stream)
 {
-    hipLaunchKernelGGL(k_mask_heuristic, dim3(nblk((n_pad + 31) / 32, 256)), dim3(256), 0, (hipStream_t)stream,
-                       last_flip, n_pad, t, k, mask);
-    return (int)hipGetLastError();
-}
-
-int gdi_launch_mask_finish(uint32_t *mask, const int32_t *orig, int32_t n_pad, uint64_t *skipped, uint32_t weight,
-                           uint64_t *block_skips, void *stream)
-{
-    hipLaunchKernelGGL(k_mask_finish, dim3(nblk((n_pad + 31) / 32, 256)), dim3(256), 0, (hipStream_t)stream, mask, orig,
-                       n_pad, (unsigned long long *)skipped, weight, (unsigned long long *)block_skips);
+    if (part_cap < 1 || (n_pad & 31) || (reinterpret_cast<uintptr_t>(last_flip) & 15) ||
+        (reinterpret_cast<uintptr_t>(orig) & 15))
+        return (int)hipErrorInvalidValue;
+    const int64_t words = n_pad / 32;
+    const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((words + 255) / 256, part_cap));
+    hipLaunchKernelGGL(k_mask_age, dim3(grid), dim3(256), 0, (hipStream_t)stream, last_flip, orig, n_pad, t, k, mask,
+                       part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL(k_sum_counts, dim3(1), dim3(256), 0, (hipStream_t)stream, part, (int32_t)grid, weight,
+                       (unsigned long long *)skipped, (unsigned long long *)block_skips);
     return (int)hipGetLastError();
 }
 
